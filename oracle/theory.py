@@ -1,0 +1,97 @@
+"""Closed forms from the paper used as pins and as step-size rules.
+
+Oracle module (test infrastructure only).
+"""
+import numpy as np
+
+
+def theta_gaussian(m, d):
+    """Inverse moments of C_S for a Gaussian embedding (Section 2, from Gupta's lemma):
+    theta_1 = m / (m - d - 1),  theta_2 = m^2 (m - 1) / ((m - d)(m - d - 1)(m - d - 3)),  m >= d + 4."""
+    if m < d + 4:
+        raise ValueError("needs m >= d + 4")
+    t1 = m / (m - d - 1)
+    t2 = m * m * (m - 1) / ((m - d) * (m - d - 1) * (m - d - 3))
+    return t1, t2
+
+
+def theta_haar(n, d, m):
+    """Finite-sample approximations for a Haar embedding with orthonormal rows (Section 2); the same
+    trace formulas hold asymptotically for the SRHT:
+    theta_1 ~ (n - d)/(m - d),  theta_2 ~ (n - d)(d^2 + m n - 2 d m)/(m - d)^3."""
+    t1 = (n - d) / (m - d)
+    t2 = (n - d) * (d * d + m * n - 2 * d * m) / (m - d) ** 3
+    return t1, t2
+
+
+def srht_thetas_scaled(N, d, m):
+    """theta's of the SRHT as scaled here (S = m^{-1/2} R H E, so S S^T = (N/m) I): the Haar values
+    for an m x N embedding with orthonormal rows, times (m/N) and (m/N)^2."""
+    t1, t2 = theta_haar(N, d, m)
+    c = m / N
+    return c * t1, c * c * t2
+
+
+def optimal_step(t1, t2):
+    """mu = theta_1 / theta_2, the minimiser of the refreshed-IHS expected error (Theorem 4.1)."""
+    return t1 / t2
+
+
+def refreshed_ihs_expected(t1, t2, mu, T):
+    """E delta_t / E delta_0 = prod_j (1 - 2 mu theta_1 + mu^2 theta_2) for constant mu (Theorem 4.1)."""
+    c = 1.0 - 2.0 * mu * t1 + mu * mu * t2
+    return c ** np.arange(T + 1)
+
+
+def polyak_expected(t1, t2, mu, beta, T):
+    """E delta_t / E delta_0 for refreshed Polyak-IHS with x_{-1} = x_0, from the linear recursion of
+    the second moments in the proof of Theorem 4.3: with
+        a_t = E delta_{t+1},  b_t = -(beta/2) E<Delta_t, Delta_{t+1}>,  c_t = beta^2 E delta_t,
+        eta = (1+beta)^2 - 2 mu theta_1 (1+beta) + mu^2 theta_2,  gamma = 1 + beta - mu theta_1,
+    X_{t+1} = [[eta, 2 gamma, 1], [-beta gamma, -beta, 0], [beta^2, 0, 0]] X_t.
+    The first step is a plain IHS step, so a_0 = (1 - 2 mu theta_1 + mu^2 theta_2) delta_0,
+    b_0 = -beta (1 - mu theta_1) delta_0 and E delta_{t+1} = a_t."""
+    eta = (1 + beta) ** 2 - 2 * mu * t1 * (1 + beta) + mu * mu * t2
+    gamma = 1 + beta - mu * t1
+    M = np.array([[eta, 2 * gamma, 1.0], [-beta * gamma, -beta, 0.0], [beta * beta, 0.0, 0.0]])
+    X = np.array([1 - 2 * mu * t1 + mu * mu * t2, -beta * (1 - mu * t1), beta * beta])
+    out = [1.0]
+    for _ in range(T):
+        out.append(X[0])
+        X = M @ X
+    return np.array(out)
+
+
+def c_s(U, S):
+    """C_S = U^T S^T S U for orthonormal U (n x d) and an explicit S (m x n) (Section 1.3)."""
+    SU = S @ U
+    return SU.T @ SU
+
+
+def fixed_ihs_exact(C, Delta0, mu, T):
+    """Per-instance IHS error with a fixed sketch (proof of Theorem 3.3):
+    delta_t = 1/2 sum_i (1 - mu/lambda_i)^{2t} (v_i^T Delta_0)^2, (lambda_i, v_i) eigenpairs of C_S."""
+    lam, V = np.linalg.eigh(C)
+    xi2 = (V.T @ Delta0) ** 2
+    return np.array([0.5 * np.sum((1 - mu / lam) ** (2 * t) * xi2) for t in range(T + 1)])
+
+
+def pcg_optimal_error(C, Delta0, t):
+    """Theorem 3.1: the smallest delta_t reachable after t steps by any method of the class with the
+    fixed sketch, 1/2 min over polynomials Q of degree <= t with Q(0) = 1 of
+    sum_i Q(1/lambda_i)^2 xi_i^2, xi_i = <v_i, Delta_0>.  PCG attains it."""
+    lam, V = np.linalg.eigh(C)
+    xi = V.T @ Delta0
+    if t == 0:
+        return 0.5 * float(xi @ xi)
+    Vand = np.stack([(1.0 / lam) ** k for k in range(1, t + 1)], axis=1)
+    c, *_ = np.linalg.lstsq(xi[:, None] * Vand, -xi, rcond=None)
+    res = xi + (xi[:, None] * Vand) @ c
+    return 0.5 * float(res @ res)
+
+
+def pcg_bound(C, T):
+    """delta_t / delta_0 <= 4 ((sqrt(l1) - sqrt(ld)) / (sqrt(l1) + sqrt(ld)))^{2t} (Section 3.1)."""
+    lam = np.linalg.eigvalsh(C)
+    q = (np.sqrt(lam[-1]) - np.sqrt(lam[0])) / (np.sqrt(lam[-1]) + np.sqrt(lam[0]))
+    return 4.0 * q ** (2 * np.arange(T + 1))

@@ -1,0 +1,83 @@
+"""Pins of the oracle's explicit sketches: the Hadamard matrix against its definition and scipy's
+Sylvester construction, H H = N I, the no-subsampling case S^T S = I, column norms of the SJLT, the
+scatter against the dense matrix, and the inverse moments of Gaussian embeddings (Section 2)."""
+import numpy as np
+import scipy.linalg
+
+from oracle import draws, sketch, theory
+
+
+def test_fwht_matches_scipy_hadamard_and_hh():
+    rng = np.random.default_rng(0)
+    for N in (1, 2, 8, 64, 1024):
+        X = rng.standard_normal((N, 3))
+        H = scipy.linalg.hadamard(N)
+        assert np.allclose(sketch.fwht_rows(X), H @ X, atol=1e-11)
+        assert np.array_equal(H @ H, N * np.eye(N))
+        k, j = np.meshgrid(np.arange(N), np.arange(N), indexing="ij")
+        assert np.array_equal(sketch.hadamard_entry(k, j), H)
+
+
+def test_srht_full_sample_is_orthogonal():
+    # m = N: R is the identity, S = N^{-1/2} H E and S^T S = I (so H_S = H)
+    for n in (32, 29):
+        S = sketch.srht_matrix(n, draws.padded_length(n), seed=4)
+        assert np.allclose(S.T @ S, np.eye(S.shape[1]), atol=1e-12)
+
+
+def test_srht_sketch_equals_dense_and_rowwise():
+    rng = np.random.default_rng(1)
+    for n in (256, 200):
+        A = rng.standard_normal((n, 5))
+        SA = sketch.srht_sketch(A, 24, seed=9, t=2)
+        N = draws.padded_length(n)
+        Ap = np.zeros((N, 5))
+        Ap[:n] = A
+        assert np.allclose(SA, sketch.srht_matrix(n, 24, 9, 2) @ Ap, atol=1e-12)
+        pick = sketch.srht_sketch_rows(A, 24, 9, 2, [0, 7, 23], cols=[1, 4])
+        assert np.allclose(pick, SA[[0, 7, 23]][:, [1, 4]], atol=1e-12)
+
+
+def test_sjlt_columns_unit_norm_and_scatter():
+    n, m, s = 500, 32, 3
+    S = sketch.sjlt_matrix(n, m, s, seed=5)
+    assert np.allclose((S * S).sum(axis=0), 1.0, atol=1e-15)
+    assert np.all((S != 0).sum(axis=0) == s)
+    A = np.random.default_rng(2).standard_normal((n, 4))
+    assert np.allclose(sketch.sjlt_sketch(A, m, s, 5), S @ A, atol=1e-12)
+
+
+def test_embeddings_isotropic_in_expectation():
+    # E[S^T S] = I for all three scalings
+    n, m, T = 16, 8, 3000
+    acc = {k: np.zeros((n, n)) for k in ("srht", "sjlt", "gaussian")}
+    for seed in range(T):
+        for k in acc:
+            if k == "srht":
+                S = sketch.srht_matrix(n, m, seed)
+            elif k == "sjlt":
+                S = sketch.sjlt_matrix(n, m, 2, seed)
+            else:
+                S = draws.gaussian_matrix(seed, 0, m, n)
+            acc[k] += S.T @ S
+    for k, v in acc.items():
+        assert np.abs(v / T - np.eye(n)).max() < 0.12, k
+
+
+def test_gaussian_inverse_moments_monte_carlo():
+    # Condition 2.1 with Gupta's formulas: d^{-1} tr E[C_S^{-1}] = theta_1, d^{-1} tr E[C_S^{-2}] = theta_2
+    n, d, m, T = 64, 4, 24, 4000
+    U, _ = np.linalg.qr(np.random.default_rng(3).standard_normal((n, d)))
+    t1s, t2s = [], []
+    for seed in range(T):
+        S = draws.gaussian_matrix(seed, 0, m, n)
+        Ci = np.linalg.inv(theory.c_s(U, S))
+        t1s.append(np.trace(Ci) / d)
+        t2s.append(np.trace(Ci @ Ci) / d)
+    t1, t2 = theory.theta_gaussian(m, d)
+    se1 = np.std(t1s) / np.sqrt(T)
+    se2 = np.std(t2s) / np.sqrt(T)
+    assert abs(np.mean(t1s) - t1) < 4 * se1
+    assert abs(np.mean(t2s) - t2) < 4 * se2
+    # and the wrong normalisation (1/n instead of 1/m) would be far off
+    assert abs(np.mean(t1s) * m / n - t1) > 20 * se1
