@@ -1,0 +1,214 @@
+/*
+ * liblsq — sketch-preconditioned least squares for tall matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lacotte & Pilanci, "Faster Least Squares Optimization" (arXiv 1911.02675).
+ *   Problem (Section 1):  x* = argmin_x 1/2 <x, H x> - <b, x>,  H = A^T A, A in R^{n x d}, n >= d.
+ *   For least squares the caller passes y in R^n and b = A^T y, i.e. x* = argmin ||A x - y||_2.
+ *   Embeddings (Section 2): Gaussian (entries N(0, 1/m)), SRHT (S = R H E with zero padding to a power
+ *   of two), SJLT (s nonzeros +-1/sqrt(s) per column).
+ *   Preconditioner (Section 1.2): H_S = (S A)^T (S A) = R^T R, R from a QR of S A.
+ *   Solvers: PCG with a fixed sketch (Section 1.2), IHS and Polyak-IHS (Section 1.1) with a fixed or a
+ *   refreshed sketch (Sections 3 and 4).
+ *
+ * Conventions for every entry point:
+ *   - Matrices are ROW-MAJOR.  A has n rows of d entries at stride lda >= d (elements).
+ *   - Pointers are DEVICE pointers unless marked (host).  The caller owns every buffer; the library
+ *     never frees caller memory.  Internal workspace lives in the context, is allocated on first need
+ *     (hipMalloc) and reused; it grows when a larger problem arrives.
+ *   - Calls are synchronous with respect to the host: they return after the work queued on the
+ *     context's stream has completed.  Calls on one context must not overlap.
+ *   - No exception crosses the ABI.  On a non-OK status lsq_last_error() returns a thread-local message.
+ *   - Argument errors leave every output untouched.  LSQ_ERR_NOT_CONVERGED returns the last iterate.
+ *   - Random draws are pure functions of (seed, t, index) through Philox4x64-10 (Salmon et al., SC'11)
+ *     with key (seed, 0).  The draw specification (bit-exact for signs, row subsets and SJLT targets):
+ *       SRHT : row j of the zero-padded A (j < N = 2^ceil(log2 n)) uses block (j, 1, t, 0) -> w0..w3;
+ *              sign e_j = -1 iff bit 63 of w0; R keeps the m rows with the smallest (w1, j), in
+ *              increasing j.  S = m^{-1/2} R H_N E with the +-1 Sylvester Hadamard H_N.
+ *       SJLT : row j of A reads words w0..w3 of blocks (j, 2, t, 0), (j, 2, t, 1), ...; each word w
+ *              proposes h = ((w >> 32) * m) >> 32, rejected when ((w >> 32) * m) mod 2^32 < 2^32 mod m
+ *              (exact uniformity) or when h is already taken; the sign is -1 iff bit 0 of w.  s distinct
+ *              targets per row; entries +-1/sqrt(s).
+ *       GAUSS: S_ij (i < m, j < n) = g / sqrt(m), g from block (j >> 3, 3, t, i), word p = (j & 7) >> 1,
+ *              a = low 32 bits, b = high 32 bits, u1 = (a + 1) 2^-32, u2 = b 2^-32,
+ *              g = sqrt(-2 ln u1) cos(2 pi u2) for even j, sin(...) for odd j (Box-Muller, evaluated in
+ *              single precision on the GPU).
+ */
+#ifndef LSQ_H
+#define LSQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LSQ_OK = 0,
+  LSQ_ERR_INVALID_ARG = 1,   /* bad size, null pointer, unsupported combination of arguments        */
+  LSQ_ERR_RANK = 2,          /* zero pivot in R (S A rank deficient) or breakdown p^T H p <= 0       */
+  LSQ_ERR_NOT_CONVERGED = 3, /* iteration budget spent before the stop rule held; x = last iterate  */
+  LSQ_ERR_NONFINITE = 4,     /* NaN or Inf met in a reduction                                       */
+  LSQ_ERR_HIP = 5,           /* a HIP runtime call failed                                           */
+  LSQ_ERR_NOMEM = 6,         /* workspace allocation failed                                         */
+  LSQ_ERR_UNSUPPORTED = 7    /* valid request outside the implemented range (e.g. d > 1024)         */
+} lsq_status;
+
+typedef enum { LSQ_F64 = 0, LSQ_F32 = 1, LSQ_BF16 = 2 } lsq_dtype;
+typedef enum { LSQ_GAUSSIAN = 0, LSQ_SRHT = 1, LSQ_SJLT = 2 } lsq_sketch_kind;
+
+typedef struct lsq_ctx lsq_ctx; /* opaque: stream, workspace, device state, tuning table */
+
+/* A context bound to the current HIP device and to `stream` (a hipStream_t; NULL = default stream).
+ * ctx (host) receives the handle. */
+lsq_status lsq_create(lsq_ctx** ctx, void* stream);
+void lsq_destroy(lsq_ctx* ctx);
+
+/* The least-squares problem min ||A x - y||.  a_dtype is LSQ_F64 or LSQ_F32 (A stored in FP32 and
+ * promoted exactly; this is the "precision form" storage).  y is FP64, length n. */
+typedef struct {
+  int64_t n, d, lda;
+  int32_t a_dtype;
+  int32_t pad_;
+  const void* A;
+  const double* y;
+} lsq_problem;
+
+/* The embedding S (m x n).  s: nonzeros per column for the SJLT (1 <= s <= min(m, 32)).
+ * compute: arithmetic of the sketch: LSQ_F64, LSQ_F32 (SRHT transform in single precision), or
+ * LSQ_BF16 (Gaussian only: bf16 S times a three-term bf16 split of A on matrix cores, FP32
+ * accumulation).  t: refresh counter (independent draws for every t). */
+typedef struct {
+  int32_t kind;
+  int32_t s;
+  int64_t m;
+  int32_t compute;
+  int32_t pad_;
+  uint64_t seed;
+  uint64_t t;
+} lsq_sketch_desc;
+
+/* PCG options.
+ *   tol:        target relative A-norm error ||A (x - x*)|| / ||A x*||.  The stop rule uses
+ *               rho_t = r_t^T H_S^{-1} r_t = Delta_t^T C_S^{-1} Delta_t: it stops when
+ *               sqrt(rho_t / rho_0) <= tol / 4, which implies the target whenever the eigenvalues of
+ *               C_S = U^T S^T S U span a ratio of at most 16 (the subspace-embedding event of Section 3).
+ *   max_iter:   PCG iteration budget (per inner solve in the mixed form).
+ *   stop_rule:  0 = the rule above; 1 = exactly max_iter iterations.
+ *   mixed:      0 = plain form (A as given, FP64 arithmetic);
+ *               1 = iterative refinement: FP64 residual A^T (y - A x) with A read in its storage type,
+ *                   inner PCG on the correction, x += dx in FP64.
+ *   max_refine: outer refinement steps (mixed = 1).
+ *   inner_f32:  mixed = 1 only: 1 = inner matrix-vector products in FP32 arithmetic (p rounded to
+ *               FP32); 0 = FP32 storage read into FP64 registers.
+ *   x_ref:      optional device pointer to the exact minimiser; when given, err_trace holds the exact
+ *               relative A-norm error per iteration (computed as sqrt(-(x_t - x*)^T r_t / x*^T b)),
+ *               otherwise the stop-rule estimate 4 sqrt(rho_t / rho_0). */
+typedef struct {
+  double tol;
+  int32_t max_iter;
+  int32_t stop_rule;
+  int32_t mixed;
+  int32_t max_refine;
+  int32_t inner_f32;
+  int32_t check_every; /* iterations queued between host checks of the device stop flag (0 = 8) */
+  const double* x_ref;
+} lsq_pcg_opts;
+
+/* IHS / Polyak-IHS options (x_{t+1} = x_t - mu H_{S_t}^{-1} grad f(x_t) + beta (x_t - x_{t-1}),
+ * x_{-1} = x_0).
+ *   refresh: 1 = S_t drawn with refresh counter desc.t + t (Section 4); 0 = S_t = S fixed (Section 3).
+ *   mu_rule: 0 = mu = theta_1 / theta_2 from the inverse moments (Theorem 4.1): the Gaussian closed
+ *            form for LSQ_GAUSSIAN (needs m >= d + 4), the Haar/SRHT trace approximation for LSQ_SRHT
+ *            rescaled to S S^T = (N/m) I, i.e. mu = (N/m) theta_1/theta_2; LSQ_SJLT has no closed form
+ *            and needs mu_rule = 1.  1 = use `mu` as given.
+ *   x_ref:   optional; when given err_trace[t] = ||A (x_t - x_ref)|| / ||A x_ref|| for t = 0..iters
+ *            (one extra pass over A per iteration; use it for studies, not for timing). */
+typedef struct {
+  double mu;
+  double beta;
+  int32_t iters;
+  int32_t refresh;
+  int32_t mu_rule;
+  int32_t pad_;
+  const double* x_ref;
+} lsq_ihs_opts;
+
+/* Per-call report (host).  Times are HIP-event times on the context stream. */
+typedef struct {
+  int32_t iters;       /* PCG iterations (summed over inner solves) or IHS iterations  */
+  int32_t refinements; /* outer refinement steps (mixed form)                           */
+  double est_rel_err;  /* final stop-rule estimate (or exact error when x_ref was given) */
+  double t_sketch_ms, t_factor_ms, t_iter_ms, t_total_ms;
+  double bytes_streamed; /* algorithmic bytes of A read by the iteration passes           */
+  double mu;             /* step used by lsq_ihs_solve                                     */
+} lsq_info;
+
+/* S A (m x d) into SA (device, row-major, leading dimension ldsa >= d).  sa_dtype must be LSQ_F64.
+ * Section 2.  Errors: INVALID_ARG for m < 1, m > N (SRHT), s outside [1, min(m, 32)] (SJLT),
+ * lda < d, null pointers; UNSUPPORTED for d > 1024. */
+lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc, void* SA,
+                      int64_t ldsa, int32_t sa_dtype);
+
+/* Upper-triangular R (d x d, row-major, positive diagonal) with R^T R = (SA)^T (SA), by Householder QR
+ * of SA (m x d, row-major, ld lds, m >= d), and W = R^{-1} (d x d, row-major).  Section 1.2 (the
+ * paper names QR of S A or a Cholesky factor of H_S).  R or W may be NULL.  RANK on a zero pivot. */
+lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int64_t lds, double* R,
+                      double* W);
+
+/* One fused pass over A (Section 1.2: each PCG step multiplies by A and A^T):
+ *   mode 0: w = A^T (A v), scal = ||A v||^2            (v = p,  H p and p^T H p)
+ *   mode 1: w = A^T (y - A v), scal = ||y - A v||^2    (v = x,  b - H x and the residual norm)
+ * with FP64 arithmetic (FP32 A promoted exactly), or FP32 arithmetic when f32_math = 1 (FP32 A only).
+ * w (device, d), scal (device, 1). */
+lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, int32_t f32_math,
+                          const double* v, double* w, double* scal);
+
+/* PCG with a fixed sketch (Section 1.2): x (device, d) holds x_0 on entry (zeros are a valid start)
+ * and the solution on exit.  err_trace (device, optional) receives max_iter+1 values per inner solve
+ * (see lsq_pcg_opts.x_ref); info (host, optional). */
+lsq_status lsq_pcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
+                         const lsq_pcg_opts* opts, double* x, double* err_trace, lsq_info* info);
+
+/* IHS / Polyak-IHS (Section 1.1) for opts->iters iterations from x (device, in: x_0, out: x_iters).
+ * err_trace (device, optional, iters+1 values) needs opts->x_ref. */
+lsq_status lsq_ihs_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
+                         const lsq_ihs_opts* opts, double* x, double* err_trace, lsq_info* info);
+
+/* `count` independent problems solved together: SJLT sketch, QR and (mixed) PCG of every problem run
+ * inside one persistent kernel, one workgroup per problem taken from a work queue ordered by
+ * decreasing n*d, the launch captured in a HIP graph and replayed.  probs, descs and xs are host
+ * arrays of length count (xs[i]: device pointer to x_i, d_i entries, in: x_0, out: solution);
+ * infos (host, optional).  Limits: d_i <= 256, 4 d_i <= m_i <= 1024, n_i <= 2^24.  Every problem
+ * must use LSQ_SJLT; opts is shared. */
+lsq_status lsq_pcg_solve_batched(lsq_ctx* ctx, int32_t count, const lsq_problem* probs,
+                                 const lsq_sketch_desc* descs, const lsq_pcg_opts* opts,
+                                 double* const* xs, lsq_info* infos);
+
+/* Draw-level entry points (the specification above), for bit-exact checks.
+ *   lsq_draw_srht: signs (device int8, N entries, may be NULL) and rows (device int64, m entries,
+ *                  increasing).  N must be a power of two.
+ *   lsq_draw_sjlt: targets (device int32, n*s, row-major by row of A, in draw order) and signs
+ *                  (device int8, n*s).
+ *   lsq_draw_gaussian: g(i, j0 + c) for i < m, c < ncols into G (device FP32, m x ncols row-major),
+ *                  unscaled standard normals. */
+lsq_status lsq_draw_srht(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t N, int64_t m, int8_t* signs,
+                         int64_t* rows);
+lsq_status lsq_draw_sjlt(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t n, int64_t m, int32_t s,
+                         int32_t* targets, int8_t* signs);
+lsq_status lsq_draw_gaussian(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
+                             int64_t ncols, float* G);
+
+/* Wall time (ms, HIP events on the context stream) of the last fused pass launched by the library,
+ * and the average over all fused-pass launches since the last reset (for roofline reporting). */
+lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, double* avg_ms,
+                                 int64_t* launches);
+
+const char* lsq_status_string(lsq_status s);
+const char* lsq_last_error(void);
+const char* lsq_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSQ_H */

@@ -1,0 +1,710 @@
+// Host driver and C ABI of liblsq (declared in include/lsq.h).
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <map>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace lsq;
+
+static thread_local std::string g_err;
+
+static lsq_status fail(lsq_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(LSQ_ERR_HIP, std::string(#expr) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define CHK(expr)                                                                             \
+  do {                                                                                        \
+    lsq_status s_ = (expr);                                                                   \
+    if (s_ != LSQ_OK) return s_;                                                              \
+  } while (0)
+
+struct EvPair {
+  hipEvent_t a, b;
+};
+
+struct lsq_ctx {
+  hipStream_t st = nullptr;
+  int dev = 0;
+  std::map<std::string, std::pair<void*, size_t>> bufs;
+  DevState* ds = nullptr;   // device
+  DevState* hds = nullptr;  // pinned host mirror
+  int* dflags = nullptr;    // device ints: [0] factor status, [1] SJLT draw error, [2] nneeded
+  int* hflags = nullptr;    // pinned host mirror (4 ints)
+  hipEvent_t ev[6] = {};
+  std::vector<EvPair> fused_ev;  // events around fused passes of the current call
+  size_t fused_used = 0;
+  double fused_total_ms = 0.0, fused_last_ms = 0.0;
+  int64_t fused_count = 0;
+};
+
+// ------------------------------------------------------------------------------------------------
+// workspace
+// ------------------------------------------------------------------------------------------------
+static lsq_status ws(lsq_ctx* c, const char* name, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 16;
+  auto& b = c->bufs[name];
+  if (b.second < bytes) {
+    if (b.first) {
+      HIPCHK(hipStreamSynchronize(c->st));
+      HIPCHK(hipFree(b.first));
+      b.first = nullptr;
+      b.second = 0;
+    }
+    const size_t cap = bytes + bytes / 8 + 256;
+    if (hipMalloc(&b.first, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(LSQ_ERR_NOMEM, std::string("workspace allocation failed: ") + name);
+    }
+    b.second = cap;
+  }
+  *out = b.first;
+  return LSQ_OK;
+}
+
+template <typename T>
+static lsq_status wsT(lsq_ctx* c, const char* name, size_t count, T** out) {
+  void* p;
+  CHK(ws(c, name, count * sizeof(T), &p));
+  *out = (T*)p;
+  return LSQ_OK;
+}
+
+static lsq_status sync_state(lsq_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->hds, c->ds, sizeof(DevState), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LSQ_OK;
+}
+
+static int64_t next_pow2(int64_t n) {
+  int64_t N = 1;
+  while (N < n) N <<= 1;
+  return N;
+}
+
+// ------------------------------------------------------------------------------------------------
+// validation
+// ------------------------------------------------------------------------------------------------
+static lsq_status check_problem(const lsq_ctx* c, const lsq_problem* p) {
+  if (!c) return fail(LSQ_ERR_INVALID_ARG, "null context");
+  if (!p || !p->A || !p->y) return fail(LSQ_ERR_INVALID_ARG, "null problem, A or y");
+  if (p->d < 1 || p->n < p->d) return fail(LSQ_ERR_INVALID_ARG, "need n >= d >= 1");
+  if (p->lda < p->d) return fail(LSQ_ERR_INVALID_ARG, "lda < d");
+  if (p->a_dtype != LSQ_F64 && p->a_dtype != LSQ_F32)
+    return fail(LSQ_ERR_INVALID_ARG, "a_dtype must be LSQ_F64 or LSQ_F32");
+  if (p->d > 1024) return fail(LSQ_ERR_UNSUPPORTED, "d > 1024 is not implemented");
+  if (p->n >= (int64_t)1 << 31) return fail(LSQ_ERR_UNSUPPORTED, "n >= 2^31 is not implemented");
+  return LSQ_OK;
+}
+
+static lsq_status check_sketch(const lsq_problem* p, const lsq_sketch_desc* s, bool need_factor) {
+  if (!s) return fail(LSQ_ERR_INVALID_ARG, "null sketch descriptor");
+  if (s->m < 1) return fail(LSQ_ERR_INVALID_ARG, "m < 1");
+  if (need_factor && s->m < p->d) return fail(LSQ_ERR_INVALID_ARG, "m < d: S A cannot have full rank");
+  if (need_factor && s->m > 8192) return fail(LSQ_ERR_UNSUPPORTED, "m > 8192 is not implemented");
+  switch (s->kind) {
+    case LSQ_SRHT:
+      if (s->m > next_pow2(p->n)) return fail(LSQ_ERR_INVALID_ARG, "SRHT needs m <= N");
+      if (s->compute != LSQ_F64 && s->compute != LSQ_F32)
+        return fail(LSQ_ERR_INVALID_ARG, "SRHT compute must be LSQ_F64 or LSQ_F32");
+      break;
+    case LSQ_SJLT:
+      if (s->s < 1 || s->s > s->m || s->s > MAX_SJLT_S)
+        return fail(LSQ_ERR_INVALID_ARG, "SJLT needs 1 <= s <= min(m, 32)");
+      if (s->m > 16384) return fail(LSQ_ERR_UNSUPPORTED, "SJLT with m > 16384 is not implemented");
+      if ((int64_t)p->n * s->s >= ((int64_t)1 << 31))
+        return fail(LSQ_ERR_UNSUPPORTED, "SJLT with n*s >= 2^31 is not implemented");
+      break;
+    case LSQ_GAUSSIAN:
+      if (s->compute != LSQ_F64 && s->compute != LSQ_BF16 && s->compute != LSQ_F32)
+        return fail(LSQ_ERR_INVALID_ARG, "Gaussian compute must be LSQ_F64, LSQ_F32 or LSQ_BF16");
+      break;
+    default:
+      return fail(LSQ_ERR_INVALID_ARG, "unknown sketch kind");
+  }
+  return LSQ_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// sketch
+// ------------------------------------------------------------------------------------------------
+static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s, uint64_t t,
+                            double* SA, int64_t ldsa) {
+  const hipStream_t st = c->st;
+  const int a_f32 = p->a_dtype == LSQ_F32;
+  if (s->kind == LSQ_SRHT) {
+    const int64_t N = next_pow2(p->n);
+    int8_t* signs;
+    uint64_t* keys;
+    int64_t* rows;
+    int *hist, *bcount, *slot, *order, *bstart;
+    void* state;
+    CHK(wsT(c, "srht_signs", N, &signs));
+    CHK(wsT(c, "srht_keys", N, &keys));
+    CHK(wsT(c, "srht_rows", s->m, &rows));
+    CHK(wsT(c, "sel_hist", 65536, &hist));
+    CHK(wsT(c, "sel_bcount", srht_select_bcount_len(N), &bcount));
+    CHK(ws(c, "sel_state", 64, &state));
+    launch_srht_draw(st, s->seed, t, N, signs, keys);
+    srht_select(st, keys, N, s->m, rows, SelectScratch{hist, bcount, state});
+    SrhtPlan plan;
+    plan.N = N;
+    plan.N1 = N < 512 ? N : 512;
+    plan.N2 = N / plan.N1;
+    plan.m = s->m;
+    CHK(wsT(c, "srht_slot", plan.N1, &slot));
+    CHK(wsT(c, "srht_order", s->m, &order));
+    CHK(wsT(c, "srht_bstart", plan.N1 + 1, &bstart));
+    srht_plan_groups(st, rows, s->m, plan.N1, slot, order, bstart, c->dflags + 2);
+    HIPCHK(hipMemcpyAsync(c->hflags + 2, c->dflags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    plan.nneeded = c->hflags[2];
+    const int cf32 = s->compute == LSQ_F32;
+    void* tbuf;
+    CHK(ws(c, "srht_tbuf", srht_tbuf_bytes(plan.N2, plan.nneeded, p->d, cf32), &tbuf));
+    srht_apply(st, p->A, a_f32, p->n, p->d, p->lda, cf32, plan, signs, rows, slot, order, bstart, tbuf,
+               SA, ldsa);
+  } else if (s->kind == LSQ_SJLT) {
+    SjltScratch sc;
+    const int64_t nblk = sjlt_nblk(p->n);
+    const int64_t ns = p->n * s->s;
+    CHK(wsT(c, "sjlt_targets", ns, &sc.targets));
+    CHK(wsT(c, "sjlt_signs", ns, &sc.signs));
+    CHK(wsT(c, "sjlt_cnt", s->m * nblk, &sc.cnt));
+    CHK(wsT(c, "sjlt_off", s->m * nblk, &sc.off));
+    CHK(wsT(c, "sjlt_scan", scan_tmp_len(s->m * nblk), &sc.scan_tmp));
+    CHK(wsT(c, "sjlt_sorted", ns, &sc.sorted));
+    CHK(wsT(c, "sjlt_bstart", s->m + 1, &sc.bstart));
+    sc.err = c->dflags + 1;
+    HIPCHK(hipMemsetAsync(sc.err, 0, sizeof(int), st));
+    sjlt_apply(st, s->seed, t, p->A, a_f32, p->n, p->d, p->lda, s->m, s->s, sc, SA, ldsa);
+    HIPCHK(hipMemcpyAsync(c->hflags + 1, c->dflags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->hflags[1]) return fail(LSQ_ERR_INVALID_ARG, "SJLT draw limit exhausted (s too close to m)");
+  } else {
+    double* part;
+    const int bf16 = s->compute == LSQ_BF16;
+    CHK(wsT(c, "gauss_part", gauss_partial_bytes(s->m, p->d, p->n, bf16) / sizeof(double) + 1, &part));
+    gauss_apply(st, s->seed, t, p->A, a_f32, p->n, p->d, p->lda, s->m, bf16, part, SA, ldsa);
+  }
+  HIPCHK(hipGetLastError());
+  return LSQ_OK;
+}
+
+// Factor S A -> R, W = R^{-1}, W^T.
+static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, int64_t lds,
+                            double* R, double* W, double* WT) {
+  double* X;
+  CHK(wsT(c, "qr_x", (size_t)m * d + (size_t)d * d, &X));
+  HIPCHK(hipMemsetAsync(c->dflags, 0, sizeof(int), c->st));
+  householder_qr(c->st, SA, m, d, lds, X, R, c->dflags);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (c->hflags[0]) return fail(LSQ_ERR_RANK, "S A is numerically rank deficient (zero pivot in R)");
+  tri_inverse(c->st, R, d, W, WT);
+  HIPCHK(hipGetLastError());
+  return LSQ_OK;
+}
+
+static EvPair* fused_event(lsq_ctx* c) {
+  if (c->fused_used == c->fused_ev.size()) {
+    EvPair e;
+    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return nullptr;
+    c->fused_ev.push_back(e);
+  }
+  return &c->fused_ev[c->fused_used++];
+}
+
+// Sum the first `count` recorded fused-pass event pairs (the stream has been synchronised).
+static void fused_account(lsq_ctx* c, size_t first, size_t count) {
+  for (size_t i = first; i < first + count && i < c->fused_used; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->fused_ev[i].a, c->fused_ev[i].b) == hipSuccess) {
+      c->fused_total_ms += ms;
+      c->fused_last_ms = ms;
+      c->fused_count += 1;
+    }
+  }
+}
+
+struct SolveBufs {
+  double *r, *rhat, *u, *p, *part, *dotpart, *red, *dx;
+  int nwg;
+};
+
+static lsq_status solve_bufs(lsq_ctx* c, int64_t n, int64_t d, SolveBufs* b) {
+  b->nwg = fused_nwg(n, d);
+  CHK(wsT(c, "v_r", d, &b->r));
+  CHK(wsT(c, "v_rhat", d, &b->rhat));
+  CHK(wsT(c, "v_u", d, &b->u));
+  CHK(wsT(c, "v_p", d, &b->p));
+  CHK(wsT(c, "v_dx", d, &b->dx));
+  CHK(wsT(c, "v_red", d + 1, &b->red));
+  CHK(wsT(c, "part", (size_t)b->nwg * (d + 1), &b->part));
+  CHK(wsT(c, "dotpart", (d + 3) / 4 + 1, &b->dotpart));
+  return LSQ_OK;
+}
+
+// PCG iterations on H z = r_0 from the state prepared by pcg_init (r, rhat, p already set).
+// z accumulates the iterate.  Returns the number of iterations run; fused passes are timed.
+static lsq_status pcg_loop(lsq_ctx* c, const lsq_problem* pr, int f32_math, const double* W,
+                           const double* WT, SolveBufs& b, double* z, int max_iter, int check_every,
+                           const double* x_ref, double* trace, int trace_len, int* iters_out) {
+  const int64_t d = pr->d;
+  const int a_f32 = pr->a_dtype == LSQ_F32;
+  const size_t ev0 = c->fused_used;
+  int it = 0;
+  CHK(sync_state(c));
+  bool done = c->hds->done != 0;
+  while (!done && it < max_iter) {
+    const int k = std::min(check_every, max_iter - it);
+    for (int q = 0; q < k; ++q) {
+      EvPair* e = fused_event(c);
+      if (e) HIPCHK(hipEventRecord(e->a, c->st));
+      fused_pass(c->st, pr->A, a_f32, f32_math, pr->n, d, pr->lda, 0, b.p, nullptr, b.part, b.nwg,
+                 &c->ds->done);
+      if (e) HIPCHK(hipEventRecord(e->b, c->st));
+      pcg_update_xr(c->st, b.part, b.nwg, d, z, b.r, b.p, c->ds);
+      int ndot;
+      precond_apply(c->st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, &c->ds->done);
+      pcg_update_p(c->st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, z, b.r, x_ref, trace, trace_len);
+    }
+    HIPCHK(hipGetLastError());
+    CHK(sync_state(c));
+    it += k;
+    done = c->hds->done != 0;
+  }
+  *iters_out = c->hds->iters;
+  fused_account(c, ev0, (size_t)c->hds->iters);
+  c->fused_used = ev0;  // recycle the events
+  return LSQ_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// C ABI
+// ------------------------------------------------------------------------------------------------
+extern "C" {
+
+const char* lsq_version(void) { return "liblsq 0.1 (gfx950)"; }
+
+const char* lsq_status_string(lsq_status s) {
+  switch (s) {
+    case LSQ_OK: return "ok";
+    case LSQ_ERR_INVALID_ARG: return "invalid argument";
+    case LSQ_ERR_RANK: return "rank deficient or breakdown";
+    case LSQ_ERR_NOT_CONVERGED: return "not converged";
+    case LSQ_ERR_NONFINITE: return "non-finite value";
+    case LSQ_ERR_HIP: return "HIP runtime error";
+    case LSQ_ERR_NOMEM: return "out of device memory";
+    case LSQ_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* lsq_last_error(void) { return g_err.c_str(); }
+
+lsq_status lsq_create(lsq_ctx** out, void* stream) {
+  if (!out) return fail(LSQ_ERR_INVALID_ARG, "null output pointer");
+  lsq_ctx* c = new lsq_ctx();
+  c->st = (hipStream_t)stream;
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    return fail(LSQ_ERR_HIP, "hipGetDevice failed");
+  }
+  bool ok = hipMalloc(&c->ds, sizeof(DevState)) == hipSuccess &&
+            hipHostMalloc(&c->hds, sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
+            hipMalloc(&c->dflags, 4 * sizeof(int)) == hipSuccess &&
+            hipHostMalloc(&c->hflags, 4 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+  for (int i = 0; ok && i < 6; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
+  if (!ok) {
+    lsq_destroy(c);
+    return fail(LSQ_ERR_HIP, "context allocation failed");
+  }
+  hipMemset(c->ds, 0, sizeof(DevState));
+  hipMemset(c->dflags, 0, 4 * sizeof(int));
+  *out = c;
+  return LSQ_OK;
+}
+
+void lsq_destroy(lsq_ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  else (void)hipDeviceSynchronize();
+  for (auto& kv : c->bufs)
+    if (kv.second.first) (void)hipFree(kv.second.first);
+  for (auto& e : c->fused_ev) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (int i = 0; i < 6; ++i)
+    if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  if (c->ds) (void)hipFree(c->ds);
+  if (c->dflags) (void)hipFree(c->dflags);
+  if (c->hds) (void)hipHostFree(c->hds);
+  if (c->hflags) (void)hipHostFree(c->hflags);
+  delete c;
+}
+
+lsq_status lsq_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s, void* SA,
+                      int64_t ldsa, int32_t sa_dtype) {
+  CHK(check_problem(c, p));
+  CHK(check_sketch(p, s, false));
+  if (!SA) return fail(LSQ_ERR_INVALID_ARG, "null SA");
+  if (ldsa < p->d) return fail(LSQ_ERR_INVALID_ARG, "ldsa < d");
+  if (sa_dtype != LSQ_F64) return fail(LSQ_ERR_INVALID_ARG, "sa_dtype must be LSQ_F64");
+  CHK(do_sketch(c, p, s, s->t, (double*)SA, ldsa));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LSQ_OK;
+}
+
+lsq_status lsq_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, int64_t lds, double* R,
+                      double* W) {
+  if (!c || !SA) return fail(LSQ_ERR_INVALID_ARG, "null context or SA");
+  if (d < 1 || m < d || lds < d) return fail(LSQ_ERR_INVALID_ARG, "need m >= d >= 1 and lds >= d");
+  if (d > 1024 || m > 8192) return fail(LSQ_ERR_UNSUPPORTED, "factor limited to d <= 1024, m <= 8192");
+  double *Rb, *Wb, *WTb;
+  CHK(wsT(c, "f_R", (size_t)d * d, &Rb));
+  CHK(wsT(c, "f_W", (size_t)d * d, &Wb));
+  CHK(wsT(c, "f_WT", (size_t)d * d, &WTb));
+  CHK(do_factor(c, SA, m, d, lds, Rb, Wb, WTb));
+  if (R) HIPCHK(hipMemcpyAsync(R, Rb, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->st));
+  if (W) HIPCHK(hipMemcpyAsync(W, Wb, sizeof(double) * d * d, hipMemcpyDeviceToDevice, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LSQ_OK;
+}
+
+lsq_status lsq_fused_pass(lsq_ctx* c, const lsq_problem* p, int32_t mode, int32_t f32_math,
+                          const double* v, double* w, double* scal) {
+  CHK(check_problem(c, p));
+  if (!v || !w || !scal) return fail(LSQ_ERR_INVALID_ARG, "null v, w or scal");
+  if (mode != 0 && mode != 1) return fail(LSQ_ERR_INVALID_ARG, "mode must be 0 or 1");
+  if (f32_math && p->a_dtype != LSQ_F32)
+    return fail(LSQ_ERR_INVALID_ARG, "f32_math needs an FP32 matrix");
+  SolveBufs b;
+  CHK(solve_bufs(c, p->n, p->d, &b));
+  EvPair* e = fused_event(c);
+  const size_t ev0 = c->fused_used - 1;
+  if (e) HIPCHK(hipEventRecord(e->a, c->st));
+  fused_pass(c->st, p->A, p->a_dtype == LSQ_F32, f32_math, p->n, p->d, p->lda, mode, v, p->y, b.part,
+             b.nwg, nullptr);
+  if (e) HIPCHK(hipEventRecord(e->b, c->st));
+  reduce_partials(c->st, b.part, b.nwg, p->d, b.red, nullptr);
+  vec_copy(c->st, w, b.red, p->d);
+  vec_copy(c->st, scal, b.red + p->d, 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (e) fused_account(c, ev0, 1);
+  c->fused_used = ev0;
+  return LSQ_OK;
+}
+
+lsq_status lsq_fused_pass_timing(lsq_ctx* c, int32_t reset, double* last_ms, double* avg_ms,
+                                 int64_t* launches) {
+  if (!c) return fail(LSQ_ERR_INVALID_ARG, "null context");
+  if (last_ms) *last_ms = c->fused_last_ms;
+  if (avg_ms) *avg_ms = c->fused_count ? c->fused_total_ms / c->fused_count : 0.0;
+  if (launches) *launches = c->fused_count;
+  if (reset) {
+    c->fused_total_ms = 0.0;
+    c->fused_count = 0;
+  }
+  return LSQ_OK;
+}
+
+// Solve the correction system H z = s (s = A^T (y - A x) held in b.r) with PCG from z = 0 and the
+// relative tolerance tol_in; returns iterations.  b.rhat / b.p / dotpart prepared here.
+static lsq_status inner_pcg(lsq_ctx* c, const lsq_problem* p, int f32_math, const double* W,
+                            const double* WT, SolveBufs& b, double* z, double tol_in, int max_iter,
+                            int check_every, const double* x_ref, double* trace, int trace_len,
+                            int* iters) {
+  int ndot;
+  precond_apply(c->st, W, WT, p->d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+  pcg_init(c->st, p->d, b.rhat, b.p, b.dotpart, ndot, c->ds, tol_in, z, b.r, x_ref, trace);
+  HIPCHK(hipGetLastError());
+  return pcg_loop(c, p, f32_math, W, WT, b, z, max_iter, check_every, x_ref, trace, trace_len, iters);
+}
+
+lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
+                         const lsq_pcg_opts* o, double* x, double* err_trace, lsq_info* info) {
+  CHK(check_problem(c, p));
+  CHK(check_sketch(p, s, true));
+  if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
+  if (o->max_iter < 1) return fail(LSQ_ERR_INVALID_ARG, "max_iter < 1");
+  if (!(o->tol > 0.0) && o->stop_rule == 0) return fail(LSQ_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->mixed && o->max_refine < 1) return fail(LSQ_ERR_INVALID_ARG, "max_refine < 1");
+  if (o->inner_f32 && (!o->mixed || p->a_dtype != LSQ_F32))
+    return fail(LSQ_ERR_INVALID_ARG, "inner_f32 needs mixed = 1 and an FP32 matrix");
+  const hipStream_t st = c->st;
+  const int64_t d = p->d, m = s->m;
+  const int check_every = o->check_every > 0 ? o->check_every : 8;
+  double *SA, *R, *W, *WT;
+  CHK(wsT(c, "SA", (size_t)m * d, &SA));
+  CHK(wsT(c, "f_R", (size_t)d * d, &R));
+  CHK(wsT(c, "f_W", (size_t)d * d, &W));
+  CHK(wsT(c, "f_WT", (size_t)d * d, &WT));
+  SolveBufs b;
+  CHK(solve_bufs(c, p->n, d, &b));
+  const double a_bytes = (double)p->n * d * (p->a_dtype == LSQ_F32 ? 4.0 : 8.0);
+
+  HIPCHK(hipEventRecord(c->ev[0], st));
+  CHK(do_sketch(c, p, s, s->t, SA, d));
+  HIPCHK(hipEventRecord(c->ev[1], st));
+  CHK(do_factor(c, SA, m, d, d, R, W, WT));
+  HIPCHK(hipEventRecord(c->ev[2], st));
+
+  const int a_f32 = p->a_dtype == LSQ_F32;
+  const double tol = o->stop_rule == 1 ? -1.0 : o->tol;
+  int total_iters = 0, refinements = 0;
+  double est = 0.0, passes = 0.0;
+  const int trace_len = o->max_iter + 1;
+
+  if (o->x_ref) {
+    // x_ref^T b with b = A^T y: one residual pass at v = 0
+    vec_zero(st, b.dx, d);
+    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, b.dx, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    dot_to_state(st, d, o->x_ref, b.red, c->ds);
+    passes += 1;
+  }
+
+  if (!o->mixed) {
+    // r_0 = A^T (y - A x_0)
+    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+    passes += 1;
+    int it = 0;
+    CHK(inner_pcg(c, p, 0, W, WT, b, x, tol, o->max_iter, check_every, o->x_ref, err_trace, trace_len,
+                  &it));
+    total_iters = it;
+    passes += it;
+    est = c->hds->est;
+  } else {
+    // iterative refinement: outer FP64 residual, inner PCG on the correction
+    double rho_b = -1.0;
+    const double floor_in = o->inner_f32 ? 1e-6 : 1e-13;
+    for (int k = 0; k < o->max_refine; ++k) {
+      fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+      reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+      passes += 1;
+      int ndot;
+      precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+      pcg_init(st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, 1.0, x, b.r, nullptr, nullptr);
+      CHK(sync_state(c));
+      const double rho_s = c->hds->rho0;
+      if (rho_b < 0.0) rho_b = rho_s;  // relative to the starting residual (x_0 = 0: to ||A x*||)
+      est = rho_b > 0.0 ? 4.0 * sqrt(fmax(rho_s, 0.0) / rho_b) : 0.0;
+      if (o->stop_rule == 0 && est <= o->tol) break;
+      if (o->stop_rule == 1 && k > 0) break;
+      refinements += 1;
+      const double tol_in = o->stop_rule == 1 ? -1.0 : fmax(0.5 * o->tol / fmax(est, 1e-300), floor_in);
+      vec_zero(st, b.dx, d);
+      int it = 0;
+      CHK(inner_pcg(c, p, o->inner_f32, W, WT, b, b.dx, tol_in, o->max_iter, check_every, nullptr,
+                    nullptr, 0, &it));
+      total_iters += it;
+      passes += it;
+      if (c->hds->status) break;
+      vec_axpy(st, x, b.dx, 1.0, d);
+    }
+  }
+  HIPCHK(hipEventRecord(c->ev[3], st));
+  HIPCHK(hipStreamSynchronize(st));
+  const int dev_status = c->hds->status;
+  if (info) {
+    float ms;
+    info->iters = total_iters;
+    info->refinements = refinements;
+    info->est_rel_err = est;
+    hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    info->t_sketch_ms = ms;
+    hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+    info->t_factor_ms = ms;
+    hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
+    info->t_iter_ms = ms;
+    hipEventElapsedTime(&ms, c->ev[0], c->ev[3]);
+    info->t_total_ms = ms;
+    info->bytes_streamed = passes * a_bytes;
+    info->mu = 0.0;
+  }
+  if (dev_status == LSQ_ERR_RANK) return fail(LSQ_ERR_RANK, "breakdown: p^T H p <= 0");
+  if (dev_status == LSQ_ERR_NONFINITE) return fail(LSQ_ERR_NONFINITE, "non-finite value in PCG");
+  if (o->stop_rule == 0) {
+    const bool ok = o->mixed ? (est <= o->tol) : (c->hds->done != 0);
+    if (!ok) return fail(LSQ_ERR_NOT_CONVERGED, "iteration budget spent before the stop rule held");
+  }
+  return LSQ_OK;
+}
+
+lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
+                         const lsq_ihs_opts* o, double* x, double* err_trace, lsq_info* info) {
+  CHK(check_problem(c, p));
+  CHK(check_sketch(p, s, true));
+  if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
+  if (o->iters < 0) return fail(LSQ_ERR_INVALID_ARG, "iters < 0");
+  if (err_trace && !o->x_ref) return fail(LSQ_ERR_INVALID_ARG, "err_trace needs x_ref");
+  const int64_t d = p->d, m = s->m;
+  double mu = o->mu;
+  if (o->mu_rule == 0) {
+    if (s->kind == LSQ_GAUSSIAN) {
+      if (m < d + 4) return fail(LSQ_ERR_INVALID_ARG, "Gaussian step rule needs m >= d + 4");
+      const double md = (double)m, dd = (double)d;
+      const double t1 = md / (md - dd - 1.0);
+      const double t2 = md * md * (md - 1.0) / ((md - dd) * (md - dd - 1.0) * (md - dd - 3.0));
+      mu = t1 / t2;
+    } else if (s->kind == LSQ_SRHT) {
+      if (m <= d) return fail(LSQ_ERR_INVALID_ARG, "SRHT step rule needs m > d");
+      const double N = (double)next_pow2(p->n), md = (double)m, dd = (double)d;
+      const double t1 = (N - dd) / (md - dd);
+      const double t2 = (N - dd) * (dd * dd + md * N - 2.0 * dd * md) / ((md - dd) * (md - dd) * (md - dd));
+      mu = (N / md) * t1 / t2;
+    } else {
+      return fail(LSQ_ERR_INVALID_ARG, "the SJLT has no closed-form step: use mu_rule = 1");
+    }
+  } else if (o->mu_rule != 1) {
+    return fail(LSQ_ERR_INVALID_ARG, "mu_rule must be 0 or 1");
+  }
+  const hipStream_t st = c->st;
+  const int a_f32 = p->a_dtype == LSQ_F32;
+  double *SA, *R, *W, *WT, *xprev, *diff, *errv;
+  CHK(wsT(c, "SA", (size_t)m * d, &SA));
+  CHK(wsT(c, "f_R", (size_t)d * d, &R));
+  CHK(wsT(c, "f_W", (size_t)d * d, &W));
+  CHK(wsT(c, "f_WT", (size_t)d * d, &WT));
+  CHK(wsT(c, "ihs_xprev", d, &xprev));
+  CHK(wsT(c, "ihs_diff", d, &diff));
+  CHK(wsT(c, "ihs_err", 1, &errv));
+  SolveBufs b;
+  CHK(solve_bufs(c, p->n, d, &b));
+  double ax2 = 0.0;
+  auto error_at = [&](int t) -> lsq_status {
+    // err_trace[t] = ||A (x - x_ref)|| / ||A x_ref||
+    vec_copy(st, diff, x, d);
+    vec_axpy(st, diff, o->x_ref, -1.0, d);
+    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, diff, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    error_from_resid(st, b.red + d, ax2, err_trace + t);
+    HIPCHK(hipGetLastError());
+    return LSQ_OK;
+  };
+  if (err_trace) {
+    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, o->x_ref, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    HIPCHK(hipMemcpyAsync(c->hflags, b.red + d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    memcpy(&ax2, c->hflags, sizeof(double));
+    CHK(error_at(0));
+  }
+  double t_sketch = 0.0, t_factor = 0.0, t_iter = 0.0;
+  HIPCHK(hipEventRecord(c->ev[4], st));
+  vec_copy(st, xprev, x, d);
+  for (int t = 0; t < o->iters; ++t) {
+    if (t == 0 || o->refresh) {
+      float ms;
+      HIPCHK(hipEventRecord(c->ev[0], st));
+      CHK(do_sketch(c, p, s, s->t + (o->refresh ? (uint64_t)t : 0), SA, d));
+      HIPCHK(hipEventRecord(c->ev[1], st));
+      CHK(do_factor(c, SA, m, d, d, R, W, WT));
+      HIPCHK(hipEventRecord(c->ev[2], st));
+      HIPCHK(hipEventSynchronize(c->ev[2]));
+      hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+      t_sketch += ms;
+      hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+      t_factor += ms;
+    }
+    HIPCHK(hipEventRecord(c->ev[0], st));
+    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+    int ndot;
+    precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+    ihs_update(st, d, x, xprev, b.rhat, mu, o->beta);
+    HIPCHK(hipEventRecord(c->ev[1], st));
+    HIPCHK(hipEventSynchronize(c->ev[1]));
+    float ms;
+    hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    t_iter += ms;
+    if (err_trace) CHK(error_at(t + 1));
+  }
+  HIPCHK(hipEventRecord(c->ev[5], st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info) {
+    float ms;
+    info->iters = o->iters;
+    info->refinements = 0;
+    info->est_rel_err = 0.0;
+    if (err_trace && o->iters >= 0) {
+      double e;
+      hipMemcpy(&e, err_trace + o->iters, sizeof(double), hipMemcpyDeviceToHost);
+      info->est_rel_err = e;
+    }
+    info->t_sketch_ms = t_sketch;
+    info->t_factor_ms = t_factor;
+    info->t_iter_ms = t_iter;
+    hipEventElapsedTime(&ms, c->ev[4], c->ev[5]);
+    info->t_total_ms = ms;
+    info->bytes_streamed = (double)o->iters * p->n * d * (a_f32 ? 4.0 : 8.0);
+    info->mu = mu;
+  }
+  return LSQ_OK;
+}
+
+lsq_status lsq_draw_srht(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t N, int64_t m, int8_t* signs,
+                         int64_t* rows) {
+  if (!c) return fail(LSQ_ERR_INVALID_ARG, "null context");
+  if (N < 1 || (N & (N - 1))) return fail(LSQ_ERR_INVALID_ARG, "N must be a power of two");
+  if (m < 1 || m > N) return fail(LSQ_ERR_INVALID_ARG, "need 1 <= m <= N");
+  uint64_t* keys;
+  int *hist, *bcount;
+  void* state;
+  CHK(wsT(c, "srht_keys", N, &keys));
+  CHK(wsT(c, "sel_hist", 65536, &hist));
+  CHK(wsT(c, "sel_bcount", srht_select_bcount_len(N), &bcount));
+  CHK(ws(c, "sel_state", 64, &state));
+  launch_srht_draw(c->st, seed, t, N, signs, keys);
+  if (rows) srht_select(c->st, keys, N, m, rows, SelectScratch{hist, bcount, state});
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LSQ_OK;
+}
+
+lsq_status lsq_draw_sjlt(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t n, int64_t m, int32_t s,
+                         int32_t* targets, int8_t* signs) {
+  if (!c || !targets || !signs) return fail(LSQ_ERR_INVALID_ARG, "null argument");
+  if (n < 1 || m < 1 || s < 1 || s > m || s > MAX_SJLT_S)
+    return fail(LSQ_ERR_INVALID_ARG, "need n, m >= 1 and 1 <= s <= min(m, 32)");
+  HIPCHK(hipMemsetAsync(c->dflags + 1, 0, sizeof(int), c->st));
+  launch_sjlt_draw(c->st, seed, t, n, m, s, targets, signs, c->dflags + 1);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hflags + 1, c->dflags + 1, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  if (c->hflags[1]) return fail(LSQ_ERR_INVALID_ARG, "SJLT draw limit exhausted");
+  return LSQ_OK;
+}
+
+lsq_status lsq_draw_gaussian(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
+                             int64_t ncols, float* G) {
+  if (!c || !G) return fail(LSQ_ERR_INVALID_ARG, "null argument");
+  if (m < 1 || ncols < 1 || j0 < 0) return fail(LSQ_ERR_INVALID_ARG, "bad sizes");
+  launch_gauss_draw(c->st, seed, t, m, j0, ncols, G);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->st));
+  return LSQ_OK;
+}
+
+lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* probs,
+                                 const lsq_sketch_desc* descs, const lsq_pcg_opts* opts,
+                                 double* const* xs, lsq_info* infos);
+
+}  // extern "C"

@@ -1,0 +1,128 @@
+// Shared device helpers of liblsq (gfx950, wave64).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/lsq.h"
+
+#define LSQ_WAVE 64
+
+namespace lsq {
+
+// ---------------------------------------------------------------------------------------------------
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11).  One round maps (c0, c1, c2, c3) to
+// (hi(M1 c2) ^ c1 ^ k0, lo(M1 c2), hi(M0 c0) ^ c3 ^ k1, lo(M0 c0)); the key is bumped by the Weyl
+// constants between rounds.
+// ---------------------------------------------------------------------------------------------------
+struct u64x4 {
+  uint64_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __umul64hi(a, b);
+#else
+  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                        uint64_t c3, uint64_t k0, uint64_t k1) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * c0, hi0 = mulhi64(M0, c0);
+    const uint64_t lo1 = M1 * c2, hi1 = mulhi64(M1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return {c0, c1, c2, c3};
+}
+
+enum : uint64_t { TAG_SRHT = 1, TAG_SJLT = 2, TAG_GAUSS = 3 };
+constexpr int MAX_SJLT_WORDS = 4096;
+constexpr int MAX_SJLT_S = 32;
+
+// Uniform target in [0, m) from the high 32 bits of a word (multiply-shift with rejection).
+__device__ __forceinline__ bool sjlt_propose(uint64_t w, uint32_t m, uint32_t thr, uint32_t* h) {
+  const uint64_t P = (w >> 32) * (uint64_t)m;
+  *h = (uint32_t)(P >> 32);
+  return (uint32_t)P >= thr;
+}
+
+// Standard normal from one 64-bit word by Box-Muller in single precision: a = low 32 bits,
+// b = high 32 bits, u1 = (a + 1) 2^-32 in (0, 1], u2 = b 2^-32; cos branch for even columns, sin for odd.
+__device__ __forceinline__ float box_muller_f32(uint64_t w, int odd) {
+  const uint32_t a = (uint32_t)w, b = (uint32_t)(w >> 32);
+  // ln u1 with u1 = (a + 1) 2^-32: for u1 >= 1/2 use log1p(-(1 - u1)) with 1 - u1 = (~a) 2^-32
+  // exact as an integer, so small radii keep their absolute accuracy.
+  const float lnu1 = (a >= 0x80000000u) ? log1pf(-(float)(~a) * 2.3283064365386963e-10f)
+                                        : logf(((float)a + 1.0f) * 2.3283064365386963e-10f);
+  const float u2 = (float)b * 2.3283064365386963e-10f;
+  const float r = sqrtf(-2.0f * lnu1);
+  float sn, cs;
+  sincospif(2.0f * u2, &sn, &cs);
+  return odd ? r * sn : r * cs;
+}
+
+// ---------------------------------------------------------------------------------------------------
+// Reductions.  All are fixed-order butterflies, so results are bitwise reproducible.
+// ---------------------------------------------------------------------------------------------------
+template <int WIDTH, typename T>
+__device__ __forceinline__ T group_sum(T v) {
+#pragma unroll
+  for (int off = WIDTH / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, WIDTH);
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum(double v) { return group_sum<LSQ_WAVE>(v); }
+
+// Block-wide sum of K values per thread (NT threads); every thread receives the K totals.
+// scratch: at least (NT/64) * K + K doubles of shared memory.
+template <int NT, int K>
+__device__ __forceinline__ void block_sum(double (&v)[K], double* scratch) {
+  constexpr int NW = NT / LSQ_WAVE;
+  const int lane = threadIdx.x & (LSQ_WAVE - 1), wv = threadIdx.x / LSQ_WAVE;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) scratch[wv * K + k] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < NW; ++w) s += scratch[w * K + threadIdx.x];
+    scratch[NW * K + threadIdx.x] = s;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = scratch[NW * K + k];
+  __syncthreads();
+}
+
+// Device-side solver state shared by the iteration kernels.
+struct DevState {
+  int done;       // stop rule met (or fatal): later kernels of the queued iterations are no-ops
+  int iters;      // iterations completed
+  int status;     // lsq_status detected on the device (RANK, NONFINITE)
+  int pad;
+  double rho;     // r^T rhat
+  double rho0;    // r_0^T rhat_0
+  double alpha;
+  double pHp;
+  double est;     // current stop-rule estimate (or exact error)
+  double tol;     // stop when est <= tol
+  double xrefb;   // x_ref^T b (exact-error trace)
+  double scal;    // scalar result of the last residual pass
+};
+
+}  // namespace lsq

@@ -1,0 +1,281 @@
+// Factor step of the preconditioner (Section 1.2): H_S = (S A)^T (S A) = R^T R with R from a
+// Householder QR of S A (m x d, m >= d), sign-normalised so that diag(R) > 0, and W = R^{-1}.
+//
+// Blocked Householder with panels of BW columns, one launch per panel.  Every workgroup (1024
+// threads, one per CU) redundantly factors the m x BW panel in registers, builds the compact-WY
+// factor T (Q_panel = I - V T V^T), and applies Q_panel^T to its own share of the trailing columns.
+// No grid-wide synchronisation is needed inside a launch; the panel is re-read from L2/MALL by each
+// workgroup instead.  Column-major scratch X keeps every column contiguous.
+#include "internal.h"
+
+namespace lsq {
+
+constexpr int QR_NT = 1024;
+
+__global__ void k_to_colmajor(const double* __restrict__ SA, int64_t m, int64_t d, int64_t lds,
+                              double* __restrict__ X) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    tile[k][tx] = (r < m && c < d) ? SA[r * lds + c] : 0.0;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (r < m && c < d) X[c * m + r] = tile[tx][k];
+  }
+}
+
+template <int RPT, int BW, int CB>
+__global__ __launch_bounds__(QR_NT) void k_qr_panel(double* __restrict__ X, int64_t m, int64_t d,
+                                                    int64_t k0, double* __restrict__ Rraw) {
+  __shared__ double red[(QR_NT / 64) * (BW * CB > BW * (BW - 1) / 2 ? BW * CB : BW * (BW - 1) / 2 + 1) + 64];
+  __shared__ double Ts[BW][BW];
+  const int tid = threadIdx.x;
+  const int bw = (int)min((int64_t)BW, d - k0);
+  double P[RPT][BW];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int64_t r = tid + (int64_t)QR_NT * i;
+#pragma unroll
+    for (int j = 0; j < BW; ++j) P[i][j] = (j < bw && r >= k0 && r < m) ? X[(k0 + j) * m + r] : 0.0;
+  }
+  double tau[BW];
+#pragma unroll
+  for (int j = 0; j < BW; ++j) {
+    tau[j] = 0.0;
+    if (j >= bw) continue;
+    const int64_t diag = k0 + j;
+    double s2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t r = tid + (int64_t)QR_NT * i;
+      if (r > diag) s2[0] += P[i][j] * P[i][j];
+      if (r == diag) s2[1] = P[i][j];
+    }
+    block_sum<QR_NT, 2>(s2, red);
+    const double sigma = s2[0], x0 = s2[1];
+    const double nrm = sqrt(x0 * x0 + sigma);
+    const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0.0 ? -nrm : nrm);
+    const double v0 = x0 - alpha;
+    const double vtv = sigma + v0 * v0;
+    tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    // rows above the diagonal hold final R entries of this panel column
+    if (blockIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = tid + (int64_t)QR_NT * i;
+        if (r >= k0 && r < diag) Rraw[r * d + diag] = P[i][j];
+      }
+      if (tid == 0) Rraw[diag * d + diag] = alpha;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int64_t r = tid + (int64_t)QR_NT * i;
+      if (r < diag) P[i][j] = 0.0;
+      else if (r == diag) P[i][j] = v0;
+    }
+    double w[BW];
+#pragma unroll
+    for (int jj = 0; jj < BW; ++jj) {
+      w[jj] = 0.0;
+      if (jj > j) {
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) w[jj] += P[i][j] * P[i][jj];
+      }
+    }
+    block_sum<QR_NT, BW>(w, red);
+#pragma unroll
+    for (int jj = 0; jj < BW; ++jj) {
+      if (jj > j) {
+        const double f = tau[j] * w[jj];
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) P[i][jj] -= f * P[i][j];
+      }
+    }
+  }
+  // T of the compact WY form, from the Gram of the Householder vectors
+  constexpr int NG = BW * (BW - 1) / 2 > 0 ? BW * (BW - 1) / 2 : 1;
+  double g[NG];
+  {
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < BW; ++a)
+#pragma unroll
+      for (int b = a + 1; b < BW; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) s += P[i][a] * P[i][b];
+        g[k++] = s;
+      }
+    if (NG == 1 && BW == 1) g[0] = 0.0;
+  }
+  block_sum<QR_NT, NG>(g, red);
+  if (tid == 0) {
+    for (int a = 0; a < BW; ++a)
+      for (int b = 0; b < BW; ++b) Ts[a][b] = 0.0;
+    for (int j = 0; j < BW; ++j) {
+      Ts[j][j] = tau[j];
+      // T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j)
+      double vtv[BW];
+      for (int a = 0; a < j; ++a) {
+        // index of pair (a, j) in the packed upper Gram
+        const int idx = a * BW - a * (a + 1) / 2 + (j - a - 1);
+        vtv[a] = g[idx];
+      }
+      for (int a = 0; a < j; ++a) {
+        double s = 0.0;
+        for (int b = a; b < j; ++b) s += Ts[a][b] * vtv[b];
+        Ts[a][j] = -tau[j] * s;
+      }
+    }
+  }
+  __syncthreads();
+  // trailing columns of this workgroup
+  const int64_t t0 = k0 + bw;
+  const int64_t ntrail = d - t0;
+  if (ntrail <= 0) return;
+  const int64_t per = (ntrail + gridDim.x - 1) / gridDim.x;
+  const int64_t cb = t0 + per * blockIdx.x, ce = min(d, cb + per);
+  for (int64_t c = cb; c < ce; c += CB) {
+    double x[RPT][CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q)
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = tid + (int64_t)QR_NT * i;
+        x[i][q] = (c + q < ce && r >= k0 && r < m) ? X[(c + q) * m + r] : 0.0;
+      }
+    double z[BW * CB];
+#pragma unroll
+    for (int a = 0; a < BW; ++a)
+#pragma unroll
+      for (int q = 0; q < CB; ++q) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) s += P[i][a] * x[i][q];
+        z[a * CB + q] = s;
+      }
+    block_sum<QR_NT, BW * CB>(z, red);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      double y[BW];
+#pragma unroll
+      for (int a = 0; a < BW; ++a) {
+        double s = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) s += Ts[b][a] * z[b * CB + q];
+        y[a] = s;
+      }
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < BW; ++a) s += P[i][a] * y[a];
+        x[i][q] -= s;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+      if (c + q >= ce) break;
+#pragma unroll
+      for (int i = 0; i < RPT; ++i) {
+        const int64_t r = tid + (int64_t)QR_NT * i;
+        if (r >= k0 && r < m) {
+          X[(c + q) * m + r] = x[i][q];
+          if (r < t0) Rraw[r * d + (c + q)] = x[i][q];
+        }
+      }
+    }
+  }
+}
+
+// R = diag(sign(Rraw_kk)) Rraw, lower triangle zeroed; rank check on the diagonal.
+__global__ void k_qr_finish(const double* __restrict__ Rraw, int64_t d, double* __restrict__ R,
+                            int* __restrict__ status) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * d) return;
+  const int64_t k = idx / d, c = idx % d;
+  const double dk = Rraw[k * d + k];
+  R[idx] = c < k ? 0.0 : (dk < 0.0 ? -Rraw[idx] : Rraw[idx]);
+  if (c == k && !(fabs(dk) > 0.0)) atomicOr(status, 1);
+}
+
+// Relative pivot check: |R_kk| <= 8 d eps max_j |R_jj| means S A is numerically rank deficient.
+__global__ __launch_bounds__(1024) void k_qr_rankcheck(const double* __restrict__ R, int64_t d,
+                                                       int* __restrict__ status) {
+  __shared__ double red[17 + 64];
+  double mx[1] = {0.0};
+  for (int64_t k = threadIdx.x; k < d; k += 1024) mx[0] = fmax(mx[0], fabs(R[k * d + k]));
+  // max-reduction via a sum of per-wave maxima is not valid; do a max butterfly explicitly
+  for (int off = 32; off >= 1; off >>= 1) mx[0] = fmax(mx[0], __shfl_xor(mx[0], off, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx[0];
+  __syncthreads();
+  double gmx = 0.0;
+  for (int w = 0; w < 16; ++w) gmx = fmax(gmx, red[w]);
+  const double thr = 8.0 * (double)d * 2.220446049250313e-16 * gmx;
+  for (int64_t k = threadIdx.x; k < d; k += 1024)
+    if (!(fabs(R[k * d + k]) > thr)) atomicOr(status, 1);
+}
+
+void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* X,
+                    double* R, int* status) {
+  double* Rraw = X + m * d;  // caller provides m*d + d*d doubles of scratch
+  hipLaunchKernelGGL(k_to_colmajor, dim3((unsigned)((m + 31) / 32), (unsigned)((d + 31) / 32)),
+                     dim3(256), 0, st, SA, m, d, lds, X);
+#define LSQ_QR(RPT, BW, CB)                                                                        \
+  for (int64_t k0 = 0; k0 < d; k0 += BW) {                                                         \
+    const int64_t ntrail = d - k0 - min((int64_t)BW, d - k0);                                      \
+    int64_t g = (ntrail + CB - 1) / CB;                                                            \
+    g = g < 1 ? 1 : (g > 256 ? 256 : g);                                                           \
+    hipLaunchKernelGGL((k_qr_panel<RPT, BW, CB>), dim3((unsigned)g), dim3(QR_NT), 0, st, X, m, d, k0, \
+                       Rraw);                                                                      \
+  }
+  if (m <= 1024) {
+    LSQ_QR(1, 8, 4)
+  } else if (m <= 2048) {
+    LSQ_QR(2, 8, 2)
+  } else if (m <= 4096) {
+    LSQ_QR(4, 8, 2)
+  } else {
+    LSQ_QR(8, 4, 2)
+  }
+#undef LSQ_QR
+  hipLaunchKernelGGL(k_qr_finish, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rraw, d, R,
+                     status);
+  hipLaunchKernelGGL(k_qr_rankcheck, dim3(1), dim3(1024), 0, st, R, d, status);
+}
+
+// W = R^{-1}: one wavefront per column j solves R w = e_j from the bottom up; W and W^T written.
+__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int64_t d,
+                                               double* __restrict__ W, double* __restrict__ WT) {
+  __shared__ double wcol[4][1024];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 4 + wv;
+  if (j >= d) return;
+  double* w = wcol[wv];
+  const double wj = 1.0 / R[j * d + j];
+  if (lane == 0) w[j] = wj;
+  for (int64_t i = j - 1; i >= 0; --i) {
+    double s = 0.0;
+    for (int64_t k = i + 1 + lane; k <= j; k += 64) s += R[i * d + k] * w[k];
+    s = wave_sum(s);
+    const double wi = -s / R[i * d + i];
+    if (lane == 0) w[i] = wi;
+    __builtin_amdgcn_wave_barrier();
+  }
+  __builtin_amdgcn_wave_barrier();
+  for (int64_t i = lane; i < d; i += 64) {
+    const double v = i <= j ? w[i] : 0.0;
+    W[i * d + j] = v;
+    WT[j * d + i] = v;
+  }
+}
+
+void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT) {
+  hipLaunchKernelGGL(k_trinv, dim3((unsigned)((d + 3) / 4)), dim3(256), 0, st, R, d, W, WT);
+}
+
+}  // namespace lsq

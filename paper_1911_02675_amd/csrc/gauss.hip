@@ -1,0 +1,108 @@
+// Gaussian sketch S A with S_ij = g(i, j) / sqrt(m), g standard normal from the counter-based
+// specification (Section 2: i.i.d. N(0, 1/m) entries).  S is never stored: every workgroup generates
+// its block of S in LDS from Philox words and multiplies it with a tile of A.  The reduction over the
+// long dimension n is split across workgroups (partials), then summed in a fixed order.
+#include "internal.h"
+
+namespace lsq {
+
+constexpr int GT_M = 64, GT_D = 64, GT_K = 32;
+
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gauss_tile(uint64_t seed, uint64_t t, const TA* __restrict__ A,
+                                                    int64_t n, int64_t d, int64_t lda, int64_t m,
+                                                    int64_t kchunk, double* __restrict__ part) {
+  __shared__ double Gs[GT_M][GT_K + 1];
+  __shared__ double As[GT_K][GT_D + 1];
+  const int tid = threadIdx.x;
+  const int tx = tid & 15, ty = tid >> 4;
+  const int64_t i0 = (int64_t)blockIdx.x * GT_M, c0 = (int64_t)blockIdx.y * GT_D;
+  const int64_t k0 = (int64_t)blockIdx.z * kchunk, k1 = min(n, k0 + kchunk);
+  double acc[4][4] = {};
+  for (int64_t kb = k0; kb < k1; kb += GT_K) {
+    __syncthreads();
+    {
+      // 64 rows x 32 columns of S: one Philox block (8 normals) per thread
+      const int gi = tid >> 2, gq = (tid & 3) * 8;
+      const int64_t i = i0 + gi, jb = kb + gq;
+      const u64x4 w = philox4x64_10((uint64_t)(jb >> 3), TAG_GAUSS, t, (uint64_t)i, seed, 0);
+      const uint64_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int64_t j = jb + q;
+        Gs[gi][gq + q] = (i < m && j < k1) ? (double)box_muller_f32(ws[q >> 1], q & 1) : 0.0;
+      }
+    }
+    for (int idx = tid; idx < GT_K * GT_D; idx += 256) {
+      const int kk = idx / GT_D, cc = idx % GT_D;
+      const int64_t j = kb + kk, col = c0 + cc;
+      As[kk][cc] = (j < k1 && col < d) ? (double)A[j * lda + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int kk = 0; kk < GT_K; ++kk) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = Gs[ty * 4 + u][kk];
+        b[u] = As[kk][tx * 4 + u];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
+    }
+  }
+  double* out = part + (int64_t)blockIdx.z * m * d;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t i = i0 + ty * 4 + u, col = c0 + tx * 4 + v;
+      if (i < m && col < d) out[i * d + col] = acc[u][v];
+    }
+}
+
+__global__ void k_gauss_reduce(const double* __restrict__ part, int64_t nks, int64_t m, int64_t d,
+                               double scale, double* __restrict__ SA, int64_t ldsa) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * d) return;
+  double s = 0.0;
+  for (int64_t k = 0; k < nks; ++k) s += part[k * m * d + idx];
+  const int64_t i = idx / d, c = idx % d;
+  SA[i * ldsa + c] = s * scale;
+}
+
+static int64_t gauss_nks(int64_t m, int64_t d, int64_t n) {
+  const int64_t tiles = ((m + GT_M - 1) / GT_M) * ((d + GT_D - 1) / GT_D);
+  int64_t nks = (2048 + tiles - 1) / tiles;
+  const int64_t maxks = (n + GT_K - 1) / GT_K;
+  if (nks > maxks) nks = maxks;
+  if (nks > 256) nks = 256;
+  return nks < 1 ? 1 : nks;
+}
+
+size_t gauss_partial_bytes(int64_t m, int64_t d, int64_t n, int bf16) {
+  (void)bf16;
+  return (size_t)gauss_nks(m, d, n) * m * d * sizeof(double);
+}
+
+void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_f32, int64_t n,
+                 int64_t d, int64_t lda, int64_t m, int bf16, double* partials, double* SA,
+                 int64_t ldsa) {
+  (void)bf16;
+  const int64_t nks = gauss_nks(m, d, n);
+  int64_t kchunk = (n + nks - 1) / nks;
+  kchunk = (kchunk + GT_K - 1) / GT_K * GT_K;  // multiple of 8: Philox blocks never straddle chunks
+  dim3 g((unsigned)((m + GT_M - 1) / GT_M), (unsigned)((d + GT_D - 1) / GT_D), (unsigned)nks);
+  if (a_f32)
+    hipLaunchKernelGGL(k_gauss_tile<float>, g, dim3(256), 0, st, seed, t, (const float*)A, n, d, lda, m,
+                       kchunk, partials);
+  else
+    hipLaunchKernelGGL(k_gauss_tile<double>, g, dim3(256), 0, st, seed, t, (const double*)A, n, d, lda,
+                       m, kchunk, partials);
+  hipLaunchKernelGGL(k_gauss_reduce, dim3((unsigned)((m * d + 255) / 256)), dim3(256), 0, st, partials,
+                     nks, m, d, 1.0 / sqrt((double)m), SA, ldsa);
+}
+
+}  // namespace lsq

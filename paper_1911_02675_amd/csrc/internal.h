@@ -1,0 +1,109 @@
+// Internal launcher interface between the kernels (*.hip) and the host driver (api.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace lsq {
+
+// ---- draws.hip ----------------------------------------------------------------------------------
+// Per padded row j < N: sign (int8 +-1) and 64-bit selection key (SRHT specification).
+void launch_srht_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t N, int8_t* signs,
+                      uint64_t* keys);
+// Scratch for srht_select (device): hist 65536 ints, sel state, block counts.
+struct SelectScratch {
+  int* hist;       // 65536
+  int* bcount;     // nblocks(N) + 1
+  void* state;     // SelState
+};
+size_t srht_select_bcount_len(int64_t N);
+// rows (device int64, m entries, increasing) = the m padded rows with the smallest (key, j).
+void srht_select(hipStream_t st, const uint64_t* keys, int64_t N, int64_t m, int64_t* rows,
+                 SelectScratch sc);
+// s targets and signs per row of A, in draw order; err set to 1 if a row exhausts its draws.
+void launch_sjlt_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, int s,
+                      int32_t* targets, int8_t* signs, int* err);
+void launch_gauss_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
+                       int64_t ncols, float* G);
+// Exclusive prefix sum of len int32 values; tmp needs scan_tmp_len(len) ints.
+size_t scan_tmp_len(int64_t len);
+void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, int* tmp);
+
+// ---- sketch.hip ---------------------------------------------------------------------------------
+// Column slices of 128 bytes are transformed in LDS: 512-row Walsh-Hadamard blocks (fewer when N is
+// smaller), then the remaining high bits are summed directly for the selected rows only.
+struct SrhtPlan {
+  int64_t N, N1, N2, m;
+  int nneeded;             // distinct k_lo among the selected rows
+};
+size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32);
+// Groups the selected rows by k_lo: slot (N1 ints, -1 if unused), order (m ints), bstart (N1+1 ints).
+// Host-side planning needs nneeded: computed on device and copied back (one sync).
+void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1, int* slot,
+                      int* order, int* bstart, int* nneeded_dev);
+void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
+                int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
+                const int* slot, const int* order, const int* bstart, void* tbuf, double* SA,
+                int64_t ldsa);
+
+struct SjltScratch {
+  int32_t* targets;  // n*s
+  int8_t* signs;     // n*s
+  int* cnt;          // m * nblk
+  int* off;          // m * nblk
+  int* scan_tmp;
+  uint32_t* sorted;  // n*s entries (row << 1 | negative)
+  int* bstart;       // m + 1 (bucket starts, = off[h * nblk])
+  int* err;
+};
+int64_t sjlt_nblk(int64_t n);
+void sjlt_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_f32, int64_t n,
+                int64_t d, int64_t lda, int64_t m, int s, SjltScratch sc, double* SA, int64_t ldsa);
+
+// Gaussian sketch SA = G A with G generated in registers (FP64 matrix cores; bf16 split on request).
+size_t gauss_partial_bytes(int64_t m, int64_t d, int64_t n, int bf16);
+void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_f32, int64_t n,
+                 int64_t d, int64_t lda, int64_t m, int bf16, double* partials, double* SA,
+                 int64_t ldsa);
+
+// ---- factor.hip ---------------------------------------------------------------------------------
+// Householder QR of SA (m x d, row-major) -> R (d x d row-major, positive diagonal).  X: m*d doubles of
+// scratch.  status: device int, set to LSQ_ERR_RANK on a zero pivot.
+void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* X,
+                    double* R, int* status);
+// W = R^{-1} and WT = W^T (both d x d row-major).
+void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT);
+
+// ---- iter.hip -----------------------------------------------------------------------------------
+int fused_nwg(int64_t n, int64_t d);
+// mode 0: part[g] = (sum_j (a_j.v) a_j, sum_j (a_j.v)^2), mode 1: with q_j = y_j - a_j.v.
+// part: nwg * (d + 1) doubles.  done: optional device flag (skip when set).
+void fused_pass(hipStream_t st, const void* A, int a_f32, int f32_math, int64_t n, int64_t d,
+                int64_t lda, int mode, const double* v, const double* y, double* part, int nwg,
+                const int* done);
+// out[c] = sum_g part[g][c] for c <= d (fixed order).
+void reduce_partials(hipStream_t st, const double* part, int nwg, int64_t d, double* out,
+                     const int* done);
+// PCG building blocks (see iter.hip for the exact steps).
+void pcg_update_xr(hipStream_t st, const double* part, int nwg, int64_t d, double* x, double* r,
+                   const double* p, DevState* ds);
+void precond_apply(hipStream_t st, const double* W, const double* WT, int64_t d, const double* r,
+                   double* u, double* rhat, double* dotpart, int* ndot, const int* done);
+void pcg_update_p(hipStream_t st, int64_t d, const double* rhat, double* p, const double* dotpart,
+                  int ndot, DevState* ds, const double* x, const double* r, const double* x_ref,
+                  double* trace, int trace_len);
+void pcg_init(hipStream_t st, int64_t d, const double* rhat, double* p, const double* dotpart,
+              int ndot, DevState* ds, double tol, const double* x, const double* r,
+              const double* x_ref, double* trace);
+void dot_to_state(hipStream_t st, int64_t d, const double* a, const double* b, DevState* ds);
+void vec_copy(hipStream_t st, double* dst, const double* src, int64_t len);
+void vec_zero(hipStream_t st, double* dst, int64_t len);
+void vec_axpy(hipStream_t st, double* y, const double* x, double a, int64_t len);
+// IHS: x_new = x - mu * hinvg + beta (x - xprev); xprev <- x; x <- x_new.
+void ihs_update(hipStream_t st, int64_t d, double* x, double* xprev, const double* hinvg, double mu,
+                double beta);
+// out = sqrt(a[0] / b) style scalar helpers evaluated on the device
+void error_from_resid(hipStream_t st, const double* scal, double denom, double* out);
+
+}  // namespace lsq

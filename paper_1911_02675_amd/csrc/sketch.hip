@@ -1,0 +1,421 @@
+// SRHT and SJLT sketches S A (Section 2).
+//
+// SRHT, S = m^{-1/2} R H_N E with the +-1 Sylvester Hadamard H_N[k, j] = (-1)^popcount(k & j) and A
+// zero-padded to N rows.  Writing j = j_hi N1 + j_lo and k = k_hi N1 + k_lo gives
+// H_N = H_{N2} (x) H_{N1}, so
+//     (H E A)[k] = sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo],
+//     T[j_hi, k_lo] = sum_{j_lo} H_{N1}[k_lo, j_lo] e_j A[j].
+// Pass A computes T block by block in LDS (a 128-byte column slice of N1 <= 512 consecutive rows),
+// keeping only the k_lo that some selected row needs.  Pass B evaluates the high-bit sum for the
+// selected rows only, grouped by k_lo so that every needed T row is read once.  HBM traffic is about
+// |A| + 2 f |T| with f the fraction of k_lo values used; the flop count of pass B is m N2 d.
+//
+// SJLT: the hashed scatter is done as a stable counting sort of the (target, row) pairs followed by
+// a segmented reduction per target row, in increasing row order: no atomics touch S A, and the
+// result is bitwise reproducible.
+#include "internal.h"
+
+namespace lsq {
+
+constexpr int SRHT_N1_MAX = 512;
+
+// --------------------------------------------------------------------------------------------------
+// Grouping of the selected rows by k_lo (single workgroup).
+// --------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void k_srht_groups(const int64_t* __restrict__ rows, int64_t m,
+                                                      int N1, int* __restrict__ slot,
+                                                      int* __restrict__ order,
+                                                      int* __restrict__ bstart,
+                                                      int* __restrict__ nneeded) {
+  __shared__ int cnt[SRHT_N1_MAX];
+  __shared__ int cur[SRHT_N1_MAX];
+  __shared__ int sh[17];
+  const int tid = threadIdx.x;
+  if (tid < N1) cnt[tid] = 0;
+  __syncthreads();
+  for (int64_t q = tid; q < m; q += 1024) atomicAdd(&cnt[rows[q] & (N1 - 1)], 1);
+  __syncthreads();
+  // exclusive scans of cnt and of (cnt > 0): one entry per thread (N1 <= 512 < 1024)
+  const int c = tid < N1 ? cnt[tid] : 0;
+  const int lane = tid & 63, wv = tid >> 6;
+  int inc = c, incu = c > 0 ? 1 : 0;
+  const int used = incu;
+  for (int off = 1; off < 64; off <<= 1) {
+    const int o = __shfl_up(inc, off, 64), ou = __shfl_up(incu, off, 64);
+    if (lane >= off) {
+      inc += o;
+      incu += ou;
+    }
+  }
+  __shared__ int wsum[16], wsumu[16];
+  if (lane == 63) {
+    wsum[wv] = inc;
+    wsumu[wv] = incu;
+  }
+  __syncthreads();
+  int pre = 0, preu = 0;
+  for (int w = 0; w < wv; ++w) {
+    pre += wsum[w];
+    preu += wsumu[w];
+  }
+  const int ex = pre + inc - c, exu = preu + incu - used;
+  if (tid < N1) {
+    bstart[tid] = ex;
+    slot[tid] = used ? exu : -1;
+    cur[tid] = ex;
+  }
+  if (tid == N1 - 1) {
+    bstart[N1] = ex + c;
+    *nneeded = exu + used;
+  }
+  __syncthreads();
+  for (int64_t q = tid; q < m; q += 1024) {
+    const int pos = atomicAdd(&cur[rows[q] & (N1 - 1)], 1);
+    order[pos] = (int)q;
+  }
+  __threadfence_block();
+  __syncthreads();
+  // insertion sort inside each bucket (buckets hold about m / N1 entries)
+  if (tid < N1) {
+    const int b0 = bstart[tid], b1 = b0 + c;
+    for (int i = b0 + 1; i < b1; ++i) {
+      const int v = order[i];
+      int k = i - 1;
+      while (k >= b0 && order[k] > v) {
+        order[k + 1] = order[k];
+        --k;
+      }
+      order[k + 1] = v;
+    }
+  }
+  (void)sh;
+}
+
+void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1, int* slot,
+                      int* order, int* bstart, int* nneeded_dev) {
+  hipLaunchKernelGGL(k_srht_groups, dim3(1), dim3(1024), 0, st, rows, m, (int)N1, slot, order, bstart,
+                     nneeded_dev);
+}
+
+size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32) {
+  return (size_t)N2 * (size_t)nneeded * (size_t)d * (compute_f32 ? 4 : 8);
+}
+
+// --------------------------------------------------------------------------------------------------
+// Pass A: sign flip + zero padding + Walsh-Hadamard transform of N1 consecutive rows, in LDS.
+// --------------------------------------------------------------------------------------------------
+template <typename TA, typename TC>
+__global__ __launch_bounds__(256) void k_srht_passA(const TA* __restrict__ A, int64_t n, int64_t d,
+                                                    int64_t lda, int N1, int L1,
+                                                    const int8_t* __restrict__ signs,
+                                                    const int* __restrict__ slot, int nneeded,
+                                                    TC* __restrict__ T) {
+  constexpr int DC = 128 / sizeof(TC);
+  __shared__ TC tile[SRHT_N1_MAX * DC];
+  const int64_t jhi = blockIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.y * DC;
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < N1 * DC; idx += 256) {
+    const int r = idx / DC, c = idx % DC;
+    const int64_t row = jhi * N1 + r, col = c0 + c;
+    TC v = 0;
+    if (row < n && col < d) {
+      v = (TC)A[row * lda + col];
+      if (signs[row] < 0) v = -v;
+    }
+    tile[idx] = v;
+  }
+  for (int h = 1; h < N1; h <<= 1) {
+    __syncthreads();
+    for (int pidx = tid; pidx < (N1 / 2) * DC; pidx += 256) {
+      const int c = pidx % DC, pr = pidx / DC;
+      const int i0 = ((pr / h) * 2 * h) + (pr % h), i1 = i0 + h;
+      const TC u = tile[i0 * DC + c], v = tile[i1 * DC + c];
+      tile[i0 * DC + c] = u + v;
+      tile[i1 * DC + c] = u - v;
+    }
+  }
+  __syncthreads();
+  (void)L1;
+  for (int idx = tid; idx < N1 * DC; idx += 256) {
+    const int r = idx / DC, c = idx % DC;
+    const int sl = slot[r];
+    const int64_t col = c0 + c;
+    if (sl >= 0 && col < d) T[(jhi * nneeded + sl) * d + col] = tile[idx];
+  }
+}
+
+// --------------------------------------------------------------------------------------------------
+// Pass B: for the selected rows sharing k_lo, sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo].
+// One workgroup per k_lo; chunks of CH rows; columns spread over the threads.
+// --------------------------------------------------------------------------------------------------
+constexpr int SRHT_CH = 16;
+
+template <typename TC, int NCOL>
+__global__ __launch_bounds__(256) void k_srht_passB(const TC* __restrict__ T, int64_t N2, int64_t d,
+                                                    int L1, const int64_t* __restrict__ rows,
+                                                    const int* __restrict__ slot,
+                                                    const int* __restrict__ order,
+                                                    const int* __restrict__ bstart, int nneeded,
+                                                    double scale, double* __restrict__ SA,
+                                                    int64_t ldsa) {
+  const int klo = blockIdx.x;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int tid = threadIdx.x;
+  __shared__ uint64_t khi_s[SRHT_CH];
+  __shared__ int pos_s[SRHT_CH];
+  for (int cb = b0; cb < b1; cb += SRHT_CH) {
+    const int nq = min(SRHT_CH, b1 - cb);
+    __syncthreads();
+    if (tid < nq) {
+      const int q = order[cb + tid];
+      pos_s[tid] = q;
+      khi_s[tid] = (uint64_t)rows[q] >> L1;
+    }
+    __syncthreads();
+    uint64_t khi[SRHT_CH];
+#pragma unroll
+    for (int q = 0; q < SRHT_CH; ++q) khi[q] = q < nq ? khi_s[q] : 0;
+    double acc[SRHT_CH][NCOL];
+#pragma unroll
+    for (int q = 0; q < SRHT_CH; ++q)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc[q][c] = 0.0;
+    const TC* base = T + (int64_t)sl * d;
+    const int64_t stride = (int64_t)nneeded * d;
+    int64_t jh = 0;
+    for (; jh + 2 <= N2; jh += 2) {
+      double v0[NCOL], v1[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int64_t col = tid + 256 * c;
+        v0[c] = col < d ? (double)base[jh * stride + col] : 0.0;
+        v1[c] = col < d ? (double)base[(jh + 1) * stride + col] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < SRHT_CH; ++q) {
+        const double s0 = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
+        const double s1 = (__popcll(khi[q] & (uint64_t)(jh + 1)) & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) acc[q][c] = fma(s1, v1[c], fma(s0, v0[c], acc[q][c]));
+      }
+    }
+    for (; jh < N2; ++jh) {
+      double v0[NCOL];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int64_t col = tid + 256 * c;
+        v0[c] = col < d ? (double)base[jh * stride + col] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < SRHT_CH; ++q) {
+        const double s0 = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) acc[q][c] = fma(s0, v0[c], acc[q][c]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < SRHT_CH; ++q) {
+      if (q >= nq) break;
+      const int64_t r = pos_s[q];
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int64_t col = tid + 256 * c;
+        if (col < d) SA[r * ldsa + col] = acc[q][c] * scale;
+      }
+    }
+  }
+}
+
+template <typename TA, typename TC>
+static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda,
+                         const SrhtPlan& p, const int8_t* signs, const int64_t* rows,
+                         const int* slot, const int* order, const int* bstart, TC* T, double* SA,
+                         int64_t ldsa) {
+  constexpr int DC = 128 / sizeof(TC);
+  int L1 = 0;
+  while ((1ll << L1) < p.N1) ++L1;
+  dim3 ga((unsigned)p.N2, (unsigned)((d + DC - 1) / DC));
+  hipLaunchKernelGGL((k_srht_passA<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, (int)p.N1, L1, signs,
+                     slot, p.nneeded, T);
+  const double scale = 1.0 / sqrt((double)p.m);
+  const int ncol = (int)((d + 255) / 256);
+  dim3 gb((unsigned)p.N1);
+#define LSQ_PASSB(NC)                                                                              \
+  hipLaunchKernelGGL((k_srht_passB<TC, NC>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot,      \
+                     order, bstart, p.nneeded, scale, SA, ldsa)
+  if (ncol <= 1)
+    LSQ_PASSB(1);
+  else if (ncol <= 2)
+    LSQ_PASSB(2);
+  else
+    LSQ_PASSB(4);
+#undef LSQ_PASSB
+}
+
+void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
+                int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
+                const int* slot, const int* order, const int* bstart, void* tbuf, double* SA,
+                int64_t ldsa) {
+  if (a_f32 && compute_f32)
+    srht_apply_t<float, float>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order, bstart,
+                               (float*)tbuf, SA, ldsa);
+  else if (a_f32)
+    srht_apply_t<float, double>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order,
+                                bstart, (double*)tbuf, SA, ldsa);
+  else if (compute_f32)
+    srht_apply_t<double, float>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
+                                bstart, (float*)tbuf, SA, ldsa);
+  else
+    srht_apply_t<double, double>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
+                                 bstart, (double*)tbuf, SA, ldsa);
+}
+
+// --------------------------------------------------------------------------------------------------
+// SJLT: stable counting sort of (target, row, sign) by target, then per-target reduction.
+// --------------------------------------------------------------------------------------------------
+constexpr int SJLT_RB = 4096;  // rows of A per counting block
+constexpr int SJLT_MMAX = 16384;
+
+int64_t sjlt_nblk(int64_t n) { return (n + SJLT_RB - 1) / SJLT_RB; }
+
+__global__ __launch_bounds__(256) void k_sjlt_count(const int32_t* __restrict__ targets, int64_t n,
+                                                    int s, int m, int64_t nblk,
+                                                    int* __restrict__ cnt) {
+  __shared__ int hist[SJLT_MMAX];
+  const int tid = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  for (int h = tid; h < m; h += 256) hist[h] = 0;
+  __syncthreads();
+  const int64_t q0 = b * SJLT_RB * s;
+  const int64_t q1 = min(n * s, (b + 1) * SJLT_RB * (int64_t)s);
+  for (int64_t q = q0 + tid; q < q1; q += 256) atomicAdd(&hist[targets[q]], 1);
+  __syncthreads();
+  for (int h = tid; h < m; h += 256) cnt[(int64_t)h * nblk + b] = hist[h];
+}
+
+// One wavefront per counting block: ranks equal targets in (row, k) order with ballots.
+__global__ __launch_bounds__(64) void k_sjlt_scatter(const int32_t* __restrict__ targets,
+                                                     const int8_t* __restrict__ signs, int64_t n,
+                                                     int s, int m, int nbits, int64_t nblk,
+                                                     const int* __restrict__ off,
+                                                     uint32_t* __restrict__ sorted) {
+  __shared__ int base[SJLT_MMAX];
+  const int lane = threadIdx.x;
+  const int64_t b = blockIdx.x;
+  for (int h = lane; h < m; h += 64) base[h] = off[(int64_t)h * nblk + b];
+  __syncthreads();
+  const int64_t q0 = b * SJLT_RB * s;
+  const int64_t q1 = min(n * s, (b + 1) * SJLT_RB * (int64_t)s);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t gt = (lane == 63) ? 0ull : (~0ull << (lane + 1));
+  for (int64_t qb = q0; qb < q1; qb += 64) {
+    const int64_t q = qb + lane;
+    const bool act = q < q1;
+    const int h = act ? targets[q] : 0;
+    uint64_t same = __ballot(act);
+    for (int bit = 0; bit < nbits; ++bit) {
+      const bool on = (h >> bit) & 1;
+      const uint64_t bal = __ballot(on);
+      same &= on ? bal : ~bal;
+    }
+    int pos = 0;
+    if (act) pos = base[h] + __popcll(same & lt);
+    __syncthreads();
+    if (act) {
+      const int64_t row = q / s;
+      sorted[pos] = ((uint32_t)row << 1) | (signs[q] < 0 ? 1u : 0u);
+      if ((same & gt) == 0) base[h] = pos + 1;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void k_sjlt_bstart(const int* __restrict__ off, int m, int64_t nblk, int64_t total,
+                              int* __restrict__ bstart) {
+  const int h = blockIdx.x * blockDim.x + threadIdx.x;
+  if (h < m) bstart[h] = off[(int64_t)h * nblk];
+  if (h == m) bstart[m] = (int)total;
+}
+
+template <typename TA, int NCOL>
+__global__ __launch_bounds__(256) void k_sjlt_reduce(const TA* __restrict__ A, int64_t d,
+                                                     int64_t lda, const uint32_t* __restrict__ sorted,
+                                                     const int* __restrict__ bstart, double scale,
+                                                     double* __restrict__ SA, int64_t ldsa) {
+  const int h = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int e0 = bstart[h], e1 = bstart[h + 1];
+  double acc[NCOL];
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) acc[c] = 0.0;
+  int e = e0;
+  for (; e + 4 <= e1; e += 4) {
+    uint32_t en[4];
+    double v[4][NCOL];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) en[u] = sorted[e + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const TA* row = A + (int64_t)(en[u] >> 1) * lda;
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) {
+        const int64_t col = tid + 256 * c;
+        v[u][c] = col < d ? (double)row[col] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < NCOL; ++c) acc[c] += (en[u] & 1u) ? -v[u][c] : v[u][c];
+  }
+  for (; e < e1; ++e) {
+    const uint32_t en = sorted[e];
+    const TA* row = A + (int64_t)(en >> 1) * lda;
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) {
+      const int64_t col = tid + 256 * c;
+      const double v = col < d ? (double)row[col] : 0.0;
+      acc[c] += (en & 1u) ? -v : v;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < NCOL; ++c) {
+    const int64_t col = tid + 256 * c;
+    if (col < d) SA[(int64_t)h * ldsa + col] = acc[c] * scale;
+  }
+}
+
+void sjlt_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_f32, int64_t n,
+                int64_t d, int64_t lda, int64_t m, int s, SjltScratch sc, double* SA, int64_t ldsa) {
+  const int64_t nblk = sjlt_nblk(n);
+  launch_sjlt_draw(st, seed, t, n, m, s, sc.targets, sc.signs, sc.err);
+  hipLaunchKernelGGL(k_sjlt_count, dim3((unsigned)nblk), dim3(256), 0, st, sc.targets, n, s, (int)m,
+                     nblk, sc.cnt);
+  exclusive_scan_i32(st, sc.cnt, sc.off, m * nblk, sc.scan_tmp);
+  int nbits = 0;
+  while ((1ll << nbits) < m) ++nbits;
+  hipLaunchKernelGGL(k_sjlt_scatter, dim3((unsigned)nblk), dim3(64), 0, st, sc.targets, sc.signs, n,
+                     s, (int)m, nbits, nblk, sc.off, sc.sorted);
+  hipLaunchKernelGGL(k_sjlt_bstart, dim3((unsigned)((m + 256) / 256)), dim3(256), 0, st, sc.off,
+                     (int)m, nblk, n * (int64_t)s, sc.bstart);
+  const double scale = 1.0 / sqrt((double)s);
+  const int ncol = (int)((d + 255) / 256);
+#define LSQ_RED(TA, NC)                                                                           \
+  hipLaunchKernelGGL((k_sjlt_reduce<TA, NC>), dim3((unsigned)m), dim3(256), 0, st, (const TA*)A, d, \
+                     lda, sc.sorted, sc.bstart, scale, SA, ldsa)
+  if (a_f32) {
+    if (ncol <= 1) LSQ_RED(float, 1);
+    else if (ncol <= 2) LSQ_RED(float, 2);
+    else LSQ_RED(float, 4);
+  } else {
+    if (ncol <= 1) LSQ_RED(double, 1);
+    else if (ncol <= 2) LSQ_RED(double, 2);
+    else LSQ_RED(double, 4);
+  }
+#undef LSQ_RED
+}
+
+}  // namespace lsq

@@ -1,0 +1,370 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle, element by element, on
+seeded inputs at sizes the oracle finishes in seconds, spanning several tiles and ragged tails.
+
+Tolerances come from the arithmetic: integer draws are bit-exact; floating-point results are
+compared against bounds of the form c * eps * (|S| |A|) that any summation order satisfies; solves
+against the relative A-norm error 1e-10 (or, where FP64 conditioning limits every solver, four
+times the disagreement of two backward-stable FP64 solvers on the same input)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+def _torch():
+    import torch
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_02675_amd import lsq
+    c = lsq.Context()
+    yield c
+    c.close()
+
+
+def dev(a):
+    torch = _torch()
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+# ----------------------------------------------------------------------------------------------
+# draws: bit-exact
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("N,m,seed,t", [(8, 8, 1, 0), (4096, 256, 7, 0), (1 << 16, 1000, 3, 5),
+                                        (1 << 20, 4096, 11, 2)])
+def test_srht_draws_bit_exact(ctx, N, m, seed, t):
+    from oracle import draws
+    torch = _torch()
+    say("srht draws", N, m, seed, t)
+    signs = torch.empty(N, dtype=torch.int8, device="cuda")
+    rows = torch.empty(m, dtype=torch.int64, device="cuda")
+    ctx.draw_srht(seed, t, N, m, signs, rows)
+    assert np.array_equal(host(signs).astype(np.float64), draws.srht_signs(seed, t, N))
+    assert np.array_equal(host(rows), draws.srht_rows(seed, t, N, m))
+
+
+@pytest.mark.parametrize("n,m,s,seed,t", [(1, 1, 1, 0, 0), (5000, 64, 4, 3, 1), (30000, 1024, 8, 9, 0),
+                                          (777, 16, 16, 2, 3), (4096, 3, 2, 5, 0)])
+def test_sjlt_draws_bit_exact(ctx, n, m, s, seed, t):
+    from oracle import draws
+    torch = _torch()
+    say("sjlt draws", n, m, s)
+    tg = torch.empty(n * s, dtype=torch.int32, device="cuda")
+    sg = torch.empty(n * s, dtype=torch.int8, device="cuda")
+    ctx.draw_sjlt(seed, t, n, m, s, tg, sg)
+    otg, osg = draws.sjlt_draws(seed, t, n, m, s)
+    assert np.array_equal(host(tg).reshape(n, s), otg)
+    assert np.array_equal(host(sg).reshape(n, s).astype(np.float64), osg)
+
+
+def test_gaussian_draws_close(ctx):
+    from oracle import draws
+    torch = _torch()
+    m, j0, nc = 37, 5, 1003
+    say("gaussian draws")
+    G = torch.empty((m, nc), dtype=torch.float32, device="cuda")
+    ctx.draw_gaussian(123, 4, m, j0, nc, G)
+    ref = draws.gaussian_normals(123, 4, np.arange(m)[:, None], np.arange(j0, j0 + nc)[None, :])
+    err = np.abs(host(G).astype(np.float64) - ref)
+    # single-precision Box-Muller: absolute error a few 1e-6 (radius up to ~6.5, angle from 32 bits)
+    assert err.max() < 8e-6, err.max()
+
+
+# ----------------------------------------------------------------------------------------------
+# fused pass
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("n,d", [(1, 1), (777, 7), (1000, 33), (3001, 64), (2500, 100), (4099, 512),
+                                 (2049, 1024), (513, 1023)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_fused_pass(ctx, n, d, dtype):
+    torch = _torch()
+    say("fused", n, d, dtype)
+    rng = np.random.default_rng(n * 7 + d)
+    A = rng.standard_normal((n, d))
+    if dtype == "f32":
+        A = A.astype(np.float32)
+    Ad = A.astype(np.float64)
+    v = rng.standard_normal(d)
+    y = rng.standard_normal(n)
+    tA, ty, tv = dev(A), dev(y), dev(v)
+    w = torch.empty(d, dtype=torch.float64, device="cuda")
+    sc = torch.empty(1, dtype=torch.float64, device="cuda")
+    for mode in (0, 1):
+        ctx.fused_pass(tA, ty, tv, w, sc, mode=mode)
+        q = Ad @ v if mode == 0 else y - Ad @ v
+        wr = Ad.T @ q
+        bound = (np.abs(Ad).T @ (np.abs(Ad) @ np.abs(v) + (0 if mode == 0 else np.abs(y))))
+        tol = 4 * (d + n) * EPS * bound + 1e-300
+        assert np.all(np.abs(host(w) - wr) <= tol)
+        assert abs(host(sc)[0] - q @ q) <= 4 * (d + n) * EPS * ((np.abs(Ad) @ np.abs(v) + (mode * np.abs(y))) ** 2).sum()
+    if dtype == "f32":
+        ctx.fused_pass(tA, ty, tv, w, sc, mode=0, f32_math=True)
+        wr = Ad.T @ (Ad @ v)
+        bound = np.abs(Ad).T @ (np.abs(Ad) @ np.abs(v))
+        assert np.all(np.abs(host(w) - wr) <= 8 * (d + n) * 2.0 ** -24 * bound + 1e-30)
+
+
+# ----------------------------------------------------------------------------------------------
+# sketches
+# ----------------------------------------------------------------------------------------------
+def _sa(ctx, A, kind, m, seed, t=0, s=1, compute="f64"):
+    from paper_1911_02675_amd import lsq
+    torch = _torch()
+    n, d = A.shape
+    SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc(kind, m, seed=seed, t=t, s=s, compute=compute)
+    ctx.sketch(dev(A), dev(np.zeros(n)), desc, SA)
+    return host(SA)
+
+
+@pytest.mark.parametrize("n,d,m", [(100, 3, 16), (4096, 64, 256), (3000, 70, 300), (20000, 129, 700),
+                                   (1 << 14, 256, 2048)])
+def test_srht_sketch(ctx, n, d, m):
+    from oracle import draws, sketch
+    say("srht sketch", n, d, m)
+    A = np.random.default_rng(n + d).standard_normal((n, d))
+    got = _sa(ctx, A, "srht", m, seed=17, t=1)
+    ref = sketch.srht_sketch(A, m, 17, 1)
+    N = draws.padded_length(n)
+    scale = np.abs(A).sum(axis=0)[None, :] / math.sqrt(m)
+    assert np.all(np.abs(got - ref) <= 8 * (math.log2(N) + 2) * EPS * scale)
+    # FP32 transform: single-precision butterflies, same bound with eps_32
+    A32 = A.astype(np.float32)
+    got32 = _sa(ctx, A32, "srht", m, seed=17, t=1, compute="f32")
+    ref32 = sketch.srht_sketch(A32.astype(np.float64), m, 17, 1)
+    assert np.all(np.abs(got32 - ref32) <= 8 * (math.log2(N) + 2) * 2.0 ** -24 * scale)
+
+
+@pytest.mark.parametrize("n,d,m,s", [(100, 3, 16, 1), (5000, 64, 256, 4), (20001, 100, 512, 8),
+                                     (9000, 257, 64, 2), (4096, 32, 4096, 1)])
+def test_sjlt_sketch(ctx, n, d, m, s):
+    from oracle import sketch
+    say("sjlt sketch", n, d, m, s)
+    A = np.random.default_rng(n + s).standard_normal((n, d))
+    got = _sa(ctx, A, "sjlt", m, seed=5, t=3, s=s)
+    ref = sketch.sjlt_sketch(A, m, s, 5, 3)
+    S = sketch.sjlt_matrix(n, m, s, 5, 3) if n * m <= 5e7 else None
+    bound = (np.abs(S) @ np.abs(A)) if S is not None else np.abs(A).sum(axis=0)[None, :]
+    assert np.all(np.abs(got - ref) <= 4 * (n * s / m + 2) * EPS * bound + 1e-300)
+    # deterministic: bitwise identical on a second run
+    assert np.array_equal(got, _sa(ctx, A, "sjlt", m, seed=5, t=3, s=s))
+
+
+@pytest.mark.parametrize("n,d,m", [(100, 3, 16), (3000, 64, 256), (5001, 129, 200)])
+def test_gaussian_sketch(ctx, n, d, m):
+    from oracle import draws, sketch
+    say("gauss sketch", n, d, m)
+    A = np.random.default_rng(n).standard_normal((n, d))
+    got = _sa(ctx, A, "gaussian", m, seed=21, t=2)
+    ref = sketch.gaussian_sketch(A, m, 21, 2)
+    G = draws.gaussian_matrix(21, 2, m, n)
+    bound = 8e-6 / math.sqrt(m) * np.abs(A).sum(axis=0)[None, :] + 4 * n * EPS * (np.abs(G) @ np.abs(A))
+    assert np.all(np.abs(got - ref) <= bound)
+
+
+# ----------------------------------------------------------------------------------------------
+# factor
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("m,d,kappa", [(16, 3, 10.0), (256, 64, 1e3), (700, 129, 1e6), (1500, 300, 1e4),
+                                       (2048, 512, 1e8), (4100, 1024, 1e4)])
+def test_factor(ctx, m, d, kappa):
+    from oracle.householder import householder_qr
+    from synth import make_problem
+    torch = _torch()
+    say("factor", m, d, kappa)
+    X = make_problem(m, d, kappa, seed=m)["A"]
+    R = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    W = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    ctx.factor(dev(X), R, W)
+    Rg, Wg = host(R), host(W)
+    Ro = householder_qr(X)
+    assert np.all(np.diag(Rg) > 0) and np.allclose(np.tril(Rg, -1), 0)
+    # backward-stable QR: R^T R reproduces X^T X to O(eps) relative to ||X||^2
+    nx2 = np.linalg.norm(X, 2) ** 2
+    assert np.abs(Rg.T @ Rg - X.T @ X).max() <= 50 * m * EPS * nx2
+    # R itself is unique; rows agree to O(eps kappa)
+    assert np.abs(Rg - Ro).max() <= 50 * m * EPS * kappa * np.abs(Ro).max()
+    # X R^{-1} has orthonormal columns
+    Q = X @ Wg
+    assert np.abs(Q.T @ Q - np.eye(d)).max() <= 1e3 * m * EPS * kappa
+
+
+def test_factor_rank_deficient(ctx):
+    from paper_1911_02675_amd import lsq
+    torch = _torch()
+    X = np.random.default_rng(0).standard_normal((200, 10))
+    X[:, 7] = X[:, 2]
+    R = torch.empty((10, 10), dtype=torch.float64, device="cuda")
+    with pytest.raises(lsq.LsqError) as e:
+        ctx.factor(dev(X), R, None)
+    assert e.value.status == lsq.LSQ_ERR_RANK
+
+
+# ----------------------------------------------------------------------------------------------
+# solves
+# ----------------------------------------------------------------------------------------------
+def _floor(A, y):
+    """Disagreement of two backward-stable FP64 solvers (Householder, LAPACK SVD) in e_A."""
+    from oracle.solve import a_norm_error, lstsq_householder
+    x1 = lstsq_householder(A, y, block_rows=8192)
+    x2 = np.linalg.lstsq(A, y, rcond=None)[0]
+    return x1, a_norm_error(A, x2, x1)
+
+
+@pytest.mark.parametrize("kind,s", [("srht", 1), ("sjlt", 4), ("gaussian", 1)])
+def test_pcg_small_config(ctx, kind, s):
+    """n = 4096, d = 64, kappa = 1e3, m = 4d, noise 0.01: PCG to relative A-norm error 1e-10."""
+    from oracle.pcg import pcg, sketch_factor
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    say("pcg small", kind)
+    P = make_problem(4096, 64, 1e3, sigma=0.01, seed=1)
+    A, y = P["A"], P["y"]
+    xs, fl = _floor(A, y)
+    x = torch.zeros(64, dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc(kind, 256, seed=3, s=s)
+    st, info = ctx.pcg_solve(dev(A), dev(y), desc, x, tol=1e-10)
+    e = a_norm_error(A, host(x), xs)
+    say("  e_A", e, "floor", fl, "iters", info.iters)
+    assert e <= max(1e-10, 4 * fl)
+    # same sketch on the oracle: iteration counts agree to within a couple of steps
+    _, its = pcg(A, y, sketch_factor(A, kind, 256, 3, s=s), tol=1e-10)
+    assert abs((len(its) - 1) - info.iters) <= 2
+
+
+@pytest.mark.parametrize("n,d,m,kind,kappa", [(30001, 128, 512, "srht", 1e4), (20000, 100, 400, "sjlt", 1e6),
+                                              (16384, 256, 1024, "srht", 1e2), (9000, 33, 140, "gaussian", 1e5)])
+def test_pcg_medium(ctx, n, d, m, kind, kappa):
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    say("pcg medium", n, d, m, kind, kappa)
+    P = make_problem(n, d, kappa, sigma=0.01, seed=n)
+    A, y = P["A"], P["y"]
+    xs, fl = _floor(A, y)
+    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+    st, info = ctx.pcg_solve(dev(A), dev(y), lsq.sketch_desc(kind, m, seed=9, s=2), x, tol=1e-10)
+    e = a_norm_error(A, host(x), xs)
+    say("  e_A", e, "floor", fl, "iters", info.iters)
+    assert e <= max(1e-10, 4 * fl)
+
+
+@pytest.mark.parametrize("inner_f32,kappa", [(0, 1e4), (0, 1e6), (1, 1e3)])
+def test_pcg_mixed_fp32_storage(ctx, inner_f32, kappa):
+    """Precision form: FP32 A (the problem is A32 promoted exactly), FP32 SRHT, FP64 residual + IR."""
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    torch = _torch()
+    say("mixed", inner_f32, kappa)
+    P = make_planted(1 << 15, 128, kappa, sigma=0.01, seed=4, want64=False, want32=True)
+    A32, y, xs = P["A32"], P["y32"], P["x_star"]
+    x = torch.zeros(128, dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc("srht", 512, seed=2, compute="f32")
+    st, info = ctx.pcg_solve(dev(A32), dev(y), desc, x, tol=1e-10, mixed=1, inner_f32=inner_f32,
+                             max_refine=30)
+    A64 = A32.astype(np.float64)
+    e = a_norm_error(A64, host(x), xs)
+    say("  e_A", e, "iters", info.iters, "refinements", info.refinements)
+    floor = 4 * EPS * kappa * np.linalg.norm(y - A64 @ xs) / np.linalg.norm(A64 @ xs)
+    assert e <= max(1e-10, floor)
+
+
+def test_pcg_planted_exact(ctx):
+    """Planted problem (noise orthogonal to range(A)): x* is known exactly."""
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    torch = _torch()
+    P = make_planted(1 << 16, 200, 1e5, sigma=0.01, seed=8)
+    A, y, xs = P["A64"], P["y64"], P["x_star"]
+    x = torch.zeros(200, dtype=torch.float64, device="cuda")
+    trace = torch.zeros(201, dtype=torch.float64, device="cuda")
+    st, info = ctx.pcg_solve(dev(A), dev(y), lsq.sketch_desc("srht", 800, seed=1), x, tol=1e-10,
+                             x_ref=dev(xs), err_trace=trace)
+    e = a_norm_error(A, host(x), xs)
+    say("planted e_A", e, info.iters)
+    assert e <= 1e-10
+    tr = host(trace)[: info.iters + 1]
+    assert abs(tr[0] - 1.0) < 1e-12 and tr[-1] <= 1e-10 * 1.5
+
+
+def test_pcg_errors(ctx):
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    P = make_problem(2000, 20, 1e8, seed=3)
+    A, y = dev(P["A"]), dev(P["y"])
+    x = torch.zeros(20, dtype=torch.float64, device="cuda")
+    for desc, code in [(lsq.sketch_desc("srht", 10), lsq.LSQ_ERR_INVALID_ARG),
+                       (lsq.sketch_desc("srht", 4096), lsq.LSQ_ERR_INVALID_ARG),
+                       (lsq.sketch_desc("sjlt", 64, s=0), lsq.LSQ_ERR_INVALID_ARG),
+                       (lsq.sketch_desc("sjlt", 64, s=65), lsq.LSQ_ERR_INVALID_ARG)]:
+        st, _ = ctx.pcg_solve(A, y, desc, x, raise_on_error=False)
+        assert st == code
+    assert np.all(host(x) == 0)  # argument errors leave x untouched
+    st, info = ctx.pcg_solve(A, y, lsq.sketch_desc("srht", 80), x, tol=1e-10, max_iter=3,
+                             raise_on_error=False)
+    assert st == lsq.LSQ_ERR_NOT_CONVERGED and info.iters == 3
+    Xb = P["A"].copy()
+    Xb[:, 5] = Xb[:, 9]
+    st, _ = ctx.pcg_solve(dev(Xb), y, lsq.sketch_desc("gaussian", 80), x, raise_on_error=False)
+    assert st == lsq.LSQ_ERR_RANK
+
+
+# ----------------------------------------------------------------------------------------------
+# IHS / Polyak-IHS
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,beta,refresh", [("gaussian", 0.0, 1), ("gaussian", 0.5, 1), ("srht", 0.1, 1),
+                                               ("srht", 0.0, 0)])
+def test_ihs_iterates(ctx, kind, beta, refresh):
+    """Same draws on both sides: the iterates agree to the rounding of the sketches."""
+    from oracle import theory
+    from oracle.ihs import ihs
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    say("ihs", kind, beta, refresh)
+    n, d, m, T = 4096, 32, 128, 8
+    P = make_problem(n, d, 1e4, sigma=0.01, seed=6)
+    A, y = P["A"], P["y"]
+    if kind == "gaussian":
+        t1, t2 = theory.theta_gaussian(m, d)
+        mu = t1 / t2
+    else:
+        t1, t2 = theory.srht_thetas_scaled(n, d, m)
+        mu = t1 / t2
+    its = ihs(A, y, kind, m, seed=77, mu=mu, beta=beta, iters=T, refresh=bool(refresh))
+    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+    info = ctx.ihs_solve(dev(A), dev(y), lsq.sketch_desc(kind, m, seed=77), x, iters=T, beta=beta,
+                         refresh=refresh, mu_rule=0)
+    assert abs(info.mu - mu) <= 1e-12 * mu
+    xo = its[-1]
+    xs = np.linalg.lstsq(A, y, rcond=None)[0]
+    diff = a_norm_error(A, host(x), xo) * np.linalg.norm(A @ xo) / np.linalg.norm(A @ xs)
+    say("  diff", diff, "err", a_norm_error(A, xo, xs))
+    # the Gaussian entries are evaluated in single precision on the GPU (about 1e-6 absolute), so the
+    # preconditioners differ at that level; the SRHT sketch is FP64 on both sides
+    tol = 1e-5 if kind == "gaussian" else 1e-10
+    assert diff <= tol
