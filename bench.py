@@ -1,0 +1,206 @@
+"""Time-to-solve of sketch-preconditioned least squares on one MI355X, plain FP64 vs mixed precision.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--kappa 1e6] [--sketch srht] [--m 4096]
+
+Workload: n = 2^22 rows, d = 1024 columns, A = U diag(s) V^T with geometric singular values
+(condition number --kappa), noise sigma = 0.01, planted so that the exact minimiser is known
+(synth.make_planted).  A step is one complete solve to relative A-norm error 1e-10: sketch S A,
+Householder factor of S A, PCG (plain FP64 form: A in FP64; mixed form: A in FP32 with an FP32
+SRHT, FP64 factor, FP64 residuals and iterative refinement).  Inputs are resident in HBM before the
+timed region.  One JSON line is printed; `value` is the mixed-form time-to-solve in seconds.
+
+The roofline block reports the dominant kernel (the fused A^T(A p) pass of the mixed form): its
+algorithmic bytes per launch (n d 4 bytes of FP32 A) over its average launch time, measured with HIP
+events recorded around every launch on the library's stream inside the timed region.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 22)
+    ap.add_argument("--d", type=int, default=1024)
+    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--kappa", type=float, default=1e6)
+    ap.add_argument("--sigma", type=float, default=0.01)
+    ap.add_argument("--sketch", default="srht", choices=["srht", "sjlt", "gaussian"])
+    ap.add_argument("--s", type=int, default=4, help="SJLT nonzeros per column")
+    ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--seed", type=int, default=3001)
+    ap.add_argument("--forms", default="fp64,mixed")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
+    return ap.parse_args()
+
+
+def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
+    """The CPU oracle as it stands, on a bounded sample of the same workload: its sketch of the first
+    `rows` rows (scaled linearly to n), its Householder QR of the m x d sketch, and one of its PCG
+    iterations on the full matrix (times the GPU's iteration count)."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import householder, sketch
+    from oracle.pcg import apply_hs_inv
+
+    n, d = A64.shape
+    rows = min(n, rows)
+    t0 = time.perf_counter()
+    SA = sketch.sketch(A64[:rows], kind, m, seed, 0, s)
+    t_sk = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    R = householder.householder_qr(SA)
+    t_qr = time.perf_counter() - t0
+    p = np.random.default_rng(0).standard_normal(d)
+    t0 = time.perf_counter()
+    q = A64 @ p
+    Hp = A64.T @ q
+    rhat = apply_hs_inv(R, Hp)
+    t_it = time.perf_counter() - t0
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    total = t_sk * (n / rows) + t_qr + iters * t_it
+    return {
+        "value": round(total, 3), "unit": "s", "cores": threads, "kind": "oracle",
+        "sample": (f"oracle {kind} sketch of the first {rows} rows ({t_sk:.2f} s, scaled x{n / rows:.0f}), "
+                   f"its Householder QR of the {m}x{d} sketch ({t_qr:.2f} s), one oracle PCG iteration "
+                   f"on the full {n}x{d} FP64 matrix ({t_it:.2f} s) x {iters} iterations"),
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "
+              "built: see the design notes on row-block sharding.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+
+    forms = [f for f in a.forms.split(",") if f]
+    log(f"[bench] generating planted problem n={a.n} d={a.d} kappa={a.kappa:g}")
+    t0 = time.time()
+    P = make_planted(a.n, a.d, a.kappa, sigma=a.sigma, seed=a.seed, want64=True,
+                     want32="mixed" in forms)
+    log(f"[bench] generated in {time.time() - t0:.1f} s; uploading")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    A64 = torch.from_numpy(P["A64"]).to(dev)
+    y64 = torch.from_numpy(P["y64"]).to(dev)
+    xs = torch.from_numpy(P["x_star"]).to(dev)
+    A32 = y32 = None
+    if "mixed" in forms:
+        A32 = torch.from_numpy(P["A32"]).to(dev)
+        y32 = torch.from_numpy(P["y32"]).to(dev)
+    torch.cuda.synchronize()
+    ctx = lsq.Context()
+    ax = torch.linalg.norm(A64 @ xs)
+
+    def solve(form):
+        x = torch.zeros(a.d, dtype=torch.float64, device=dev)
+        if form == "fp64":
+            desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute="f64")
+            _, info = ctx.pcg_solve(A64, y64, desc, x, tol=a.tol, max_iter=200)
+        else:
+            comp = "f32" if a.sketch == "srht" else "f64"
+            desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute=comp)
+            _, info = ctx.pcg_solve(A32, y32, desc, x, tol=a.tol, max_iter=200, mixed=1, max_refine=8)
+        return x, info
+
+    res = {}
+    for form in forms:
+        for _ in range(a.warmup):
+            solve(form)
+        ctx.fused_pass_timing(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for _ in range(a.steps):
+            x, info = solve(form)
+            infos.append(info.as_dict())
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        _, fused_ms, launches = ctx.fused_pass_timing()
+        Aref = A64 if form == "fp64" else A32.double()
+        e = float(torch.linalg.norm(Aref @ (x - xs)) / ax)
+        if form != "fp64":
+            del Aref
+        bytes_per_pass = a.n * a.d * (8 if form == "fp64" else 4)
+        res[form] = dict(s=dt, err=e, info=infos[-1], fused_ms=fused_ms, launches=launches,
+                         fused_gbs=bytes_per_pass / (fused_ms * 1e-3) / 1e9 if fused_ms > 0 else None,
+                         bytes_per_pass=bytes_per_pass)
+        log(f"[bench] {form}: {dt * 1e3:.1f} ms/solve  e_A={e:.2e}  iters={info.iters} "
+            f"refine={info.refinements} sketch={info.t_sketch_ms:.1f} factor={info.t_factor_ms:.1f} "
+            f"iter={info.t_iter_ms:.1f} ms  fused {fused_ms:.3f} ms/launch "
+            f"({res[form]['fused_gbs']:.0f} GB/s)")
+    ctx.close()
+
+    head = "mixed" if "mixed" in res else forms[0]
+    h = res[head]
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("[bench] timing the CPU oracle on a bounded sample")
+        cpu = cpu_baseline(P["A64"], P["y64"], a.m, a.sketch, a.s, a.seed, h["info"]["iters"],
+                           a.cpu_sample_rows)
+    out = {
+        "metric": "time-to-solve (s) + HBM GB/s, n=2^22 d=1024 to 1e-10; mixed vs FP64",
+        "value": round(h["s"], 5),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(h["s"] * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 storage + f64" if head == "mixed" else "f64",
+        "data": "synthetic (planted, exact minimiser known)",
+        "config": {"workload": f"least squares n={a.n} d={a.d} kappa={a.kappa:g} sigma={a.sigma} "
+                               f"{a.sketch} m={a.m} tol={a.tol:g}",
+                   "n": a.n, "d": a.d, "m": a.m, "kappa": a.kappa, "sketch": a.sketch,
+                   "parallelism": "single GPU"},
+        "rel_a_norm_error": h["err"],
+        "fp64": ({"time_s": round(res["fp64"]["s"], 5), "rel_a_norm_error": res["fp64"]["err"],
+                  "iters": res["fp64"]["info"]["iters"], "fused_gbs": round(res["fp64"]["fused_gbs"], 1),
+                  "phases_ms": {k: round(res["fp64"]["info"][k], 3) for k in
+                                ("t_sketch_ms", "t_factor_ms", "t_iter_ms")}}
+                 if "fp64" in res else None),
+        "mixed": ({"time_s": round(res["mixed"]["s"], 5), "rel_a_norm_error": res["mixed"]["err"],
+                   "iters": res["mixed"]["info"]["iters"], "refinements": res["mixed"]["info"]["refinements"],
+                   "fused_gbs": round(res["mixed"]["fused_gbs"], 1),
+                   "phases_ms": {k: round(res["mixed"]["info"][k], 3) for k in
+                                 ("t_sketch_ms", "t_factor_ms", "t_iter_ms")}}
+                  if "mixed" in res else None),
+        "speedup_mixed_vs_fp64": (round(res["fp64"]["s"] / res["mixed"]["s"], 3)
+                                  if "fp64" in res and "mixed" in res else None),
+        "roofline": {"bound": "hbm", "achieved": round(h["fused_gbs"], 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(h["fused_gbs"] / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": "k_fused (A^T(A p), one pass)",
+                     "bytes_per_launch": h["bytes_per_pass"], "avg_launch_ms": round(h["fused_ms"], 4),
+                     "launches": h["launches"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
