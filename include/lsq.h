@@ -203,6 +203,11 @@ lsq_status lsq_draw_gaussian(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t m,
 lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, double* avg_ms,
                                  int64_t* launches);
 
+/* Process-wide tuning parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
+ * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
+ * default 8).  INVALID_ARG for an unknown key or an out-of-range value. */
+lsq_status lsq_tune(const char* key, int64_t value);
+
 const char* lsq_status_string(lsq_status s);
 const char* lsq_last_error(void);
 const char* lsq_version(void);

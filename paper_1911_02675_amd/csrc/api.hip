@@ -161,7 +161,7 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     srht_select(st, keys, N, s->m, rows, SelectScratch{hist, bcount, state});
     SrhtPlan plan;
     plan.N = N;
-    plan.N1 = N < 512 ? N : 512;
+    plan.N1 = N < 256 ? N : 256;
     plan.N2 = N / plan.N1;
     plan.m = s->m;
     CHK(wsT(c, "srht_slot", plan.N1, &slot));
@@ -174,8 +174,10 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     const int cf32 = s->compute == LSQ_F32;
     void* tbuf;
     CHK(ws(c, "srht_tbuf", srht_tbuf_bytes(plan.N2, plan.nneeded, p->d, cf32), &tbuf));
+    double* partial;
+    CHK(wsT(c, "srht_partial", srht_partial_bytes(plan.N2, s->m, p->d) / sizeof(double), &partial));
     srht_apply(st, p->A, a_f32, p->n, p->d, p->lda, cf32, plan, signs, rows, slot, order, bstart, tbuf,
-               SA, ldsa);
+               partial, SA, ldsa);
   } else if (s->kind == LSQ_SJLT) {
     SjltScratch sc;
     const int64_t nblk = sjlt_nblk(p->n);
@@ -222,7 +224,10 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
 static EvPair* fused_event(lsq_ctx* c) {
   if (c->fused_used == c->fused_ev.size()) {
     EvPair e;
-    if (hipEventCreate(&e.a) != hipSuccess || hipEventCreate(&e.b) != hipSuccess) return nullptr;
+    // device-scope release: timing events must not add system-scope cache flushes between kernels
+    if (hipEventCreateWithFlags(&e.a, hipEventDisableSystemFence) != hipSuccess ||
+        hipEventCreateWithFlags(&e.b, hipEventDisableSystemFence) != hipSuccess)
+      return nullptr;
     c->fused_ev.push_back(e);
   }
   return &c->fused_ev[c->fused_used++];
@@ -241,7 +246,7 @@ static void fused_account(lsq_ctx* c, size_t first, size_t count) {
 }
 
 struct SolveBufs {
-  double *r, *rhat, *u, *p, *part, *dotpart, *red, *dx;
+  double *r, *rhat, *u, *p, *part, *part2, *dotpart, *red, *dx;
   int nwg;
 };
 
@@ -254,6 +259,7 @@ static lsq_status solve_bufs(lsq_ctx* c, int64_t n, int64_t d, SolveBufs* b) {
   CHK(wsT(c, "v_dx", d, &b->dx));
   CHK(wsT(c, "v_red", d + 1, &b->red));
   CHK(wsT(c, "part", (size_t)b->nwg * (d + 1), &b->part));
+  CHK(wsT(c, "part2", (size_t)REDUCE_SPLIT * (d + 1), &b->part2));
   CHK(wsT(c, "dotpart", (d + 3) / 4 + 1, &b->dotpart));
   return LSQ_OK;
 }
@@ -269,15 +275,32 @@ static lsq_status pcg_loop(lsq_ctx* c, const lsq_problem* pr, int f32_math, cons
   int it = 0;
   CHK(sync_state(c));
   bool done = c->hds->done != 0;
+  // Batches of iterations are queued between host checks of the device stop flag.  After the first
+  // batch the remaining count is predicted from the observed contraction of the stop-rule estimate,
+  // so that almost no iterations are queued past convergence.
+  double prev_proxy = -1.0;
+  int prev_it = 0;
+  const double tol = c->hds->tol;
   while (!done && it < max_iter) {
-    const int k = std::min(check_every, max_iter - it);
+    int k = std::min(check_every, max_iter - it);
+    const double proxy = c->hds->rho0 > 0.0 ? 4.0 * sqrt(fmax(c->hds->rho, 0.0) / c->hds->rho0) : 0.0;
+    if (tol > 0.0 && prev_proxy > 0.0 && proxy > 0.0 && proxy < prev_proxy && it > prev_it) {
+      const double rate = pow(proxy / prev_proxy, 1.0 / (it - prev_it));
+      if (rate < 1.0 && rate > 0.0) {
+        const double need = ceil(log(tol / proxy) / log(rate));
+        if (need >= 1.0 && need < k) k = (int)need;
+      }
+    }
+    prev_proxy = proxy;
+    prev_it = it;
     for (int q = 0; q < k; ++q) {
       EvPair* e = fused_event(c);
       if (e) HIPCHK(hipEventRecord(e->a, c->st));
-      fused_pass(c->st, pr->A, a_f32, f32_math, pr->n, d, pr->lda, 0, b.p, nullptr, b.part, b.nwg,
+      const int ng_ = fused_pass(c->st, pr->A, a_f32, f32_math, pr->n, d, pr->lda, 0, b.p, nullptr, b.part, b.nwg,
                  &c->ds->done);
       if (e) HIPCHK(hipEventRecord(e->b, c->st));
-      pcg_update_xr(c->st, b.part, b.nwg, d, z, b.r, b.p, c->ds);
+      reduce_stage1(c->st, b.part, ng_, d, b.part2, &c->ds->done);
+      pcg_update_xr(c->st, b.part2, REDUCE_SPLIT, d, z, b.r, b.p, c->ds);
       int ndot;
       precond_apply(c->st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, &c->ds->done);
       pcg_update_p(c->st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, z, b.r, x_ref, trace, trace_len);
@@ -398,10 +421,10 @@ lsq_status lsq_fused_pass(lsq_ctx* c, const lsq_problem* p, int32_t mode, int32_
   EvPair* e = fused_event(c);
   const size_t ev0 = c->fused_used - 1;
   if (e) HIPCHK(hipEventRecord(e->a, c->st));
-  fused_pass(c->st, p->A, p->a_dtype == LSQ_F32, f32_math, p->n, p->d, p->lda, mode, v, p->y, b.part,
+  const int ng_ = fused_pass(c->st, p->A, p->a_dtype == LSQ_F32, f32_math, p->n, p->d, p->lda, mode, v, p->y, b.part,
              b.nwg, nullptr);
   if (e) HIPCHK(hipEventRecord(e->b, c->st));
-  reduce_partials(c->st, b.part, b.nwg, p->d, b.red, nullptr);
+  reduce_partials(c->st, b.part, b.part2, ng_, p->d, b.red, nullptr);
   vec_copy(c->st, w, b.red, p->d);
   vec_copy(c->st, scal, b.red + p->d, 1);
   HIPCHK(hipGetLastError());
@@ -474,16 +497,16 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   if (o->x_ref) {
     // x_ref^T b with b = A^T y: one residual pass at v = 0
     vec_zero(st, b.dx, d);
-    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, b.dx, p->y, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, b.dx, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
     dot_to_state(st, d, o->x_ref, b.red, c->ds);
     passes += 1;
   }
 
   if (!o->mixed) {
     // r_0 = A^T (y - A x_0)
-    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
     passes += 1;
     int it = 0;
     CHK(inner_pcg(c, p, 0, W, WT, b, x, tol, o->max_iter, check_every, o->x_ref, err_trace, trace_len,
@@ -496,8 +519,8 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     double rho_b = -1.0;
     const double floor_in = o->inner_f32 ? 1e-6 : 1e-13;
     for (int k = 0; k < o->max_refine; ++k) {
-      fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
-      reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+      const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+      reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
       passes += 1;
       int ndot;
       precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
@@ -509,7 +532,10 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       if (o->stop_rule == 0 && est <= o->tol) break;
       if (o->stop_rule == 1 && k > 0) break;
       refinements += 1;
-      const double tol_in = o->stop_rule == 1 ? -1.0 : fmax(0.5 * o->tol / fmax(est, 1e-300), floor_in);
+      // the inner stop rule bounds the error of the correction relative to the current error, whose
+      // estimate is est = 4 sqrt(rho_s / rho_b): asking 0.9 tol / (est / 4) of it lands at 0.9 tol
+      const double rel = fmax(est / 4.0, 1e-300);
+      const double tol_in = o->stop_rule == 1 ? -1.0 : fmax(0.9 * o->tol / rel, floor_in);
       vec_zero(st, b.dx, d);
       int it = 0;
       CHK(inner_pcg(c, p, o->inner_f32, W, WT, b, b.dx, tol_in, o->max_iter, check_every, nullptr,
@@ -593,15 +619,15 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     // err_trace[t] = ||A (x - x_ref)|| / ||A x_ref||
     vec_copy(st, diff, x, d);
     vec_axpy(st, diff, o->x_ref, -1.0, d);
-    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, diff, nullptr, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, diff, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
     error_from_resid(st, b.red + d, ax2, err_trace + t);
     HIPCHK(hipGetLastError());
     return LSQ_OK;
   };
   if (err_trace) {
-    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, o->x_ref, nullptr, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.nwg, d, b.red, nullptr);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, o->x_ref, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
     HIPCHK(hipMemcpyAsync(c->hflags, b.red + d, sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     memcpy(&ax2, c->hflags, sizeof(double));
@@ -625,8 +651,8 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       t_factor += ms;
     }
     HIPCHK(hipEventRecord(c->ev[0], st));
-    fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.nwg, d, b.r, nullptr);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
     int ndot;
     precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
     ihs_update(st, d, x, xprev, b.rhat, mu, o->beta);
@@ -701,6 +727,17 @@ lsq_status lsq_draw_gaussian(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t m, i
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(c->st));
   return LSQ_OK;
+}
+
+lsq_status lsq_tune(const char* key, int64_t value) {
+  if (!key) return fail(LSQ_ERR_INVALID_ARG, "null key");
+  const std::string k(key);
+  if (k == "fused_groups_per_cu") {
+    if (value < 1 || value > 64) return fail(LSQ_ERR_INVALID_ARG, "fused_groups_per_cu in [1, 64]");
+    g_fused_groups_per_cu = (int)value;
+    return LSQ_OK;
+  }
+  return fail(LSQ_ERR_INVALID_ARG, "unknown tuning key: " + k);
 }
 
 lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* probs,

@@ -1,8 +1,8 @@
 // Factor step of the preconditioner (Section 1.2): H_S = (S A)^T (S A) = R^T R with R from a
 // Householder QR of S A (m x d, m >= d), sign-normalised so that diag(R) > 0, and W = R^{-1}.
 //
-// Blocked Householder with panels of BW columns, one launch per panel.  Every workgroup (1024
-// threads, one per CU) redundantly factors the m x BW panel in registers, builds the compact-WY
+// Blocked Householder with panels of BW columns, one launch per panel.  Every workgroup (512
+// threads) redundantly factors the m x BW panel in registers, builds the compact-WY
 // factor T (Q_panel = I - V T V^T), and applies Q_panel^T to its own share of the trailing columns.
 // No grid-wide synchronisation is needed inside a launch; the panel is re-read from L2/MALL by each
 // workgroup instead.  Column-major scratch X keeps every column contiguous.
@@ -10,7 +10,7 @@
 
 namespace lsq {
 
-constexpr int QR_NT = 1024;
+constexpr int QR_NT = 512;
 
 __global__ void k_to_colmajor(const double* __restrict__ SA, int64_t m, int64_t d, int64_t lds,
                               double* __restrict__ X) {
@@ -31,7 +31,7 @@ __global__ void k_to_colmajor(const double* __restrict__ SA, int64_t m, int64_t 
 template <int RPT, int BW, int CB>
 __global__ __launch_bounds__(QR_NT) void k_qr_panel(double* __restrict__ X, int64_t m, int64_t d,
                                                     int64_t k0, double* __restrict__ Rraw) {
-  __shared__ double red[(QR_NT / 64) * (BW * CB > BW * (BW - 1) / 2 ? BW * CB : BW * (BW - 1) / 2 + 1) + 64];
+  __shared__ double red[(QR_NT / 64) * (BW * CB > BW ? BW * CB : BW) + 64];
   __shared__ double Ts[BW][BW];
   const int tid = threadIdx.x;
   const int bw = (int)min((int64_t)BW, d - k0);
@@ -42,10 +42,11 @@ __global__ __launch_bounds__(QR_NT) void k_qr_panel(double* __restrict__ X, int6
 #pragma unroll
     for (int j = 0; j < BW; ++j) P[i][j] = (j < bw && r >= k0 && r < m) ? X[(k0 + j) * m + r] : 0.0;
   }
-  double tau[BW];
+  // Ts (compact WY factor, Q_panel = I - V T V^T) is built column by column by thread 0 from the
+  // Gram entries v_a^T v_j, which ride along in the same reduction as the update dot products.
+  if (tid < BW * BW) Ts[tid / BW][tid % BW] = 0.0;
 #pragma unroll
   for (int j = 0; j < BW; ++j) {
-    tau[j] = 0.0;
     if (j >= bw) continue;
     const int64_t diag = k0 + j;
     double s2[2] = {0.0, 0.0};
@@ -61,7 +62,7 @@ __global__ __launch_bounds__(QR_NT) void k_qr_panel(double* __restrict__ X, int6
     const double alpha = nrm == 0.0 ? 0.0 : (x0 >= 0.0 ? -nrm : nrm);
     const double v0 = x0 - alpha;
     const double vtv = sigma + v0 * v0;
-    tau[j] = vtv > 0.0 ? 2.0 / vtv : 0.0;
+    const double tau = vtv > 0.0 ? 2.0 / vtv : 0.0;
     // rows above the diagonal hold final R entries of this panel column
     if (blockIdx.x == 0) {
 #pragma unroll
@@ -77,58 +78,32 @@ __global__ __launch_bounds__(QR_NT) void k_qr_panel(double* __restrict__ X, int6
       if (r < diag) P[i][j] = 0.0;
       else if (r == diag) P[i][j] = v0;
     }
+    // w[jj] = v_j^T (column jj) for jj > j (update), = v_jj^T v_j for jj < j (Gram column of T)
     double w[BW];
 #pragma unroll
     for (int jj = 0; jj < BW; ++jj) {
       w[jj] = 0.0;
-      if (jj > j) {
+      if (jj != j) {
 #pragma unroll
         for (int i = 0; i < RPT; ++i) w[jj] += P[i][j] * P[i][jj];
       }
     }
     block_sum<QR_NT, BW>(w, red);
+    if (tid == 0) {
+      // T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j);  T[j, j] = tau_j
+      for (int a = 0; a < j; ++a) {
+        double acc = 0.0;
+        for (int b = a; b < j; ++b) acc += Ts[a][b] * w[b];
+        Ts[a][j] = -tau * acc;
+      }
+      Ts[j][j] = tau;
+    }
 #pragma unroll
     for (int jj = 0; jj < BW; ++jj) {
       if (jj > j) {
-        const double f = tau[j] * w[jj];
+        const double f = tau * w[jj];
 #pragma unroll
         for (int i = 0; i < RPT; ++i) P[i][jj] -= f * P[i][j];
-      }
-    }
-  }
-  // T of the compact WY form, from the Gram of the Householder vectors
-  constexpr int NG = BW * (BW - 1) / 2 > 0 ? BW * (BW - 1) / 2 : 1;
-  double g[NG];
-  {
-    int k = 0;
-#pragma unroll
-    for (int a = 0; a < BW; ++a)
-#pragma unroll
-      for (int b = a + 1; b < BW; ++b) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = 0; i < RPT; ++i) s += P[i][a] * P[i][b];
-        g[k++] = s;
-      }
-    if (NG == 1 && BW == 1) g[0] = 0.0;
-  }
-  block_sum<QR_NT, NG>(g, red);
-  if (tid == 0) {
-    for (int a = 0; a < BW; ++a)
-      for (int b = 0; b < BW; ++b) Ts[a][b] = 0.0;
-    for (int j = 0; j < BW; ++j) {
-      Ts[j][j] = tau[j];
-      // T[0:j, j] = -tau_j T[0:j, 0:j] (V[:, 0:j]^T v_j)
-      double vtv[BW];
-      for (int a = 0; a < j; ++a) {
-        // index of pair (a, j) in the packed upper Gram
-        const int idx = a * BW - a * (a + 1) / 2 + (j - a - 1);
-        vtv[a] = g[idx];
-      }
-      for (int a = 0; a < j; ++a) {
-        double s = 0.0;
-        for (int b = a; b < j; ++b) s += Ts[a][b] * vtv[b];
-        Ts[a][j] = -tau[j] * s;
       }
     }
   }
@@ -206,7 +181,7 @@ __global__ void k_qr_finish(const double* __restrict__ Rraw, int64_t d, double* 
 // Relative pivot check: |R_kk| <= 8 d eps max_j |R_jj| means S A is numerically rank deficient.
 __global__ __launch_bounds__(1024) void k_qr_rankcheck(const double* __restrict__ R, int64_t d,
                                                        int* __restrict__ status) {
-  __shared__ double red[17 + 64];
+  __shared__ double red[17 + 64];  // k_qr_rankcheck runs with 1024 threads
   double mx[1] = {0.0};
   for (int64_t k = threadIdx.x; k < d; k += 1024) mx[0] = fmax(mx[0], fabs(R[k * d + k]));
   // max-reduction via a sum of per-wave maxima is not valid; do a max butterfly explicitly
@@ -233,14 +208,16 @@ void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int6
     hipLaunchKernelGGL((k_qr_panel<RPT, BW, CB>), dim3((unsigned)g), dim3(QR_NT), 0, st, X, m, d, k0, \
                        Rraw);                                                                      \
   }
-  if (m <= 1024) {
+  if (m <= 512) {
     LSQ_QR(1, 8, 4)
+  } else if (m <= 1024) {
+    LSQ_QR(2, 8, 4)
   } else if (m <= 2048) {
-    LSQ_QR(2, 8, 2)
-  } else if (m <= 4096) {
     LSQ_QR(4, 8, 2)
+  } else if (m <= 4096) {
+    LSQ_QR(8, 8, 1)
   } else {
-    LSQ_QR(8, 4, 2)
+    LSQ_QR(16, 4, 1)
   }
 #undef LSQ_QR
   hipLaunchKernelGGL(k_qr_finish, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rraw, d, R,

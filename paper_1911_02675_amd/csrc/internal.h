@@ -31,8 +31,8 @@ size_t scan_tmp_len(int64_t len);
 void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, int* tmp);
 
 // ---- sketch.hip ---------------------------------------------------------------------------------
-// Column slices of 128 bytes are transformed in LDS: 512-row Walsh-Hadamard blocks (fewer when N is
-// smaller), then the remaining high bits are summed directly for the selected rows only.
+// Column slices of 128 bytes: 256-row Walsh-Hadamard blocks (N rows when N is smaller), then the
+// remaining high bits are summed directly for the selected rows only.
 struct SrhtPlan {
   int64_t N, N1, N2, m;
   int nneeded;             // distinct k_lo among the selected rows
@@ -42,10 +42,11 @@ size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32);
 // Host-side planning needs nneeded: computed on device and copied back (one sync).
 void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1, int* slot,
                       int* order, int* bstart, int* nneeded_dev);
+size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d);
 void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
                 int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
-                const int* slot, const int* order, const int* bstart, void* tbuf, double* SA,
-                int64_t ldsa);
+                const int* slot, const int* order, const int* bstart, void* tbuf, double* partial,
+                double* SA, int64_t ldsa);
 
 struct SjltScratch {
   int32_t* targets;  // n*s
@@ -77,16 +78,23 @@ void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* 
 
 // ---- iter.hip -----------------------------------------------------------------------------------
 int fused_nwg(int64_t n, int64_t d);
+extern int g_fused_groups_per_cu;   // tuning: fused-pass workgroups per CU
+// Partial sums are reduced in two fixed-order stages: nwg rows -> REDUCE_SPLIT rows -> 1.
+constexpr int REDUCE_SPLIT = 32;
+void reduce_stage1(hipStream_t st, const double* part, int nwg, int64_t d, double* part2,
+                   const int* done);
 // mode 0: part[g] = (sum_j (a_j.v) a_j, sum_j (a_j.v)^2), mode 1: with q_j = y_j - a_j.v.
 // part: nwg * (d + 1) doubles.  done: optional device flag (skip when set).
-void fused_pass(hipStream_t st, const void* A, int a_f32, int f32_math, int64_t n, int64_t d,
-                int64_t lda, int mode, const double* v, const double* y, double* part, int nwg,
-                const int* done);
-// out[c] = sum_g part[g][c] for c <= d (fixed order).
-void reduce_partials(hipStream_t st, const double* part, int nwg, int64_t d, double* out,
-                     const int* done);
+// Returns the number of workgroups launched (= partial rows to reduce), at most nwg.
+int fused_pass(hipStream_t st, const void* A, int a_f32, int f32_math, int64_t n, int64_t d,
+               int64_t lda, int mode, const double* v, const double* y, double* part, int nwg,
+               const int* done);
+// out[c] = sum_g part[g][c] for c <= d (fixed order); part2: REDUCE_SPLIT * (d + 1) scratch.
+void reduce_partials(hipStream_t st, const double* part, double* part2, int nwg, int64_t d,
+                     double* out, const int* done);
 // PCG building blocks (see iter.hip for the exact steps).
-void pcg_update_xr(hipStream_t st, const double* part, int nwg, int64_t d, double* x, double* r,
+// part2: the REDUCE_SPLIT rows left by reduce_stage1.
+void pcg_update_xr(hipStream_t st, const double* part2, int nrows, int64_t d, double* x, double* r,
                    const double* p, DevState* ds);
 void precond_apply(hipStream_t st, const double* W, const double* WT, int64_t d, const double* r,
                    double* u, double* rhat, double* dotpart, int* ndot, const int* done);

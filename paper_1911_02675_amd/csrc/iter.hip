@@ -42,7 +42,7 @@ constexpr int FUSED_NT = 256;
 
 // TA: storage type of A; TM: arithmetic type of the products; G lanes per row; NCH chunks of VEC
 // contiguous elements per lane (d <= G * NCH * VEC); MODE 0: q = a.v, MODE 1: q = y_j - a.v.
-template <typename TA, typename TM, int G, int NCH, int VEC, int MODE>
+template <typename TA, typename TM, int G, int NCH, int VEC, int MODE, int UNR, bool FULL>
 __global__ __launch_bounds__(FUSED_NT) void k_fused(const TA* __restrict__ A, int64_t n, int d,
                                                     int64_t lda, const double* __restrict__ v,
                                                     const double* __restrict__ y,
@@ -67,53 +67,61 @@ __global__ __launch_bounds__(FUSED_NT) void k_fused(const TA* __restrict__ A, in
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(n, r0 + rows_per_wg);
   int64_t r = r0 + grp;
-  // two rows in flight per group
-  for (; r + NGRP < r1; r += 2 * NGRP) {
-    TA a0[NCH][VEC], a1[NCH][VEC];
-    const TA* p0 = A + r * lda;
-    const TA* p1 = A + (r + NGRP) * lda;
+  // Lanes whose chunk lies past d load from the row start instead and discard the value: the loads
+  // are unconditional (no branches), so the compiler can issue all of them back to back.
+  bool ok[NCH];
+  int off[NCH];
 #pragma unroll
-    for (int i = 0; i < NCH; ++i) {
-      const int e = (gl + G * i) * VEC;
-      if (e < d) {
-        VecLoad<TA, VEC>::get(p0 + e, a0[i]);
-        VecLoad<TA, VEC>::get(p1 + e, a1[i]);
-      } else {
-#pragma unroll
-        for (int u = 0; u < VEC; ++u) a0[i][u] = a1[i][u] = (TA)0;
-      }
-    }
-    TM q0 = (TM)0, q1 = (TM)0;
-#pragma unroll
-    for (int i = 0; i < NCH; ++i)
-#pragma unroll
-      for (int u = 0; u < VEC; ++u) {
-        q0 = fma((TM)a0[i][u], pv[i][u], q0);
-        q1 = fma((TM)a1[i][u], pv[i][u], q1);
-      }
-    q0 = group_sum<G>(q0);
-    q1 = group_sum<G>(q1);
-    if (MODE == 1) {
-      q0 = (TM)(y[r] - (double)q0);
-      q1 = (TM)(y[r + NGRP] - (double)q1);
-    }
-#pragma unroll
-    for (int i = 0; i < NCH; ++i)
-#pragma unroll
-      for (int u = 0; u < VEC; ++u) wacc[i][u] = fma(q1, (TM)a1[i][u], fma(q0, (TM)a0[i][u], wacc[i][u]));
-    if (gl == 0) sacc = fma(q1, q1, fma(q0, q0, sacc));
+  for (int i = 0; i < NCH; ++i) {
+    const int e = (gl + G * i) * VEC;
+    ok[i] = FULL || e < d;
+    off[i] = ok[i] ? e : 0;
   }
-  if (r < r1) {
+  // UNR rows in flight per group
+  for (; r + (UNR - 1) * NGRP < r1; r += UNR * NGRP) {
+    TA a[UNR][NCH][VEC];
+#pragma unroll
+    for (int i = 0; i < NCH; ++i)
+#pragma unroll
+      for (int k = 0; k < UNR; ++k) {
+        VecLoad<TA, VEC>::get(A + (r + k * NGRP) * lda + off[i], a[k][i]);
+        if (!FULL) {
+#pragma unroll
+          for (int u = 0; u < VEC; ++u) a[k][i][u] = ok[i] ? a[k][i][u] : (TA)0;
+        }
+      }
+    TM q[UNR];
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) q[k] = (TM)0;
+#pragma unroll
+    for (int i = 0; i < NCH; ++i)
+#pragma unroll
+      for (int u = 0; u < VEC; ++u)
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) q[k] = fma((TM)a[k][i][u], pv[i][u], q[k]);
+#pragma unroll
+    for (int k = 0; k < UNR; ++k) {
+      q[k] = group_sum<G>(q[k]);
+      if (MODE == 1) q[k] = (TM)(y[r + k * NGRP] - (double)q[k]);
+    }
+#pragma unroll
+    for (int i = 0; i < NCH; ++i)
+#pragma unroll
+      for (int u = 0; u < VEC; ++u)
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) wacc[i][u] = fma(q[k], (TM)a[k][i][u], wacc[i][u]);
+    if (gl == 0)
+#pragma unroll
+      for (int k = 0; k < UNR; ++k) sacc = fma(q[k], q[k], sacc);
+  }
+  for (; r < r1; r += NGRP) {
     TA a0[NCH][VEC];
-    const TA* p0 = A + r * lda;
 #pragma unroll
     for (int i = 0; i < NCH; ++i) {
-      const int e = (gl + G * i) * VEC;
-      if (e < d) {
-        VecLoad<TA, VEC>::get(p0 + e, a0[i]);
-      } else {
+      VecLoad<TA, VEC>::get(A + r * lda + off[i], a0[i]);
+      if (!FULL) {
 #pragma unroll
-        for (int u = 0; u < VEC; ++u) a0[i][u] = (TA)0;
+        for (int u = 0; u < VEC; ++u) a0[i][u] = ok[i] ? a0[i][u] : (TA)0;
       }
     }
     TM q0 = (TM)0;
@@ -167,150 +175,174 @@ __global__ __launch_bounds__(FUSED_NT) void k_fused(const TA* __restrict__ A, in
   }
 }
 
+// Grid of the fused pass: groups_per_cu x CUs workgroups (oversubscribed: workgroups that finish
+// early are replaced, which evens out the streaming across channels); small problems use fewer
+// groups of at least 64 rows.  groups_per_cu is a tuning parameter (lsq_tune "fused_groups_per_cu").
+static int g_num_cus = 0;
+int g_fused_groups_per_cu = 8;
+
 int fused_nwg(int64_t n, int64_t d) {
   (void)d;
-  const int64_t minrows = 64;
-  int64_t nwg = (n + minrows - 1) / minrows;
-  if (nwg > 2048) nwg = 2048;
-  if (nwg < 1) nwg = 1;
-  return (int)nwg;
+  if (g_num_cus == 0) {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      g_num_cus = cus;
+    else
+      g_num_cus = 256;
+  }
+  int64_t nwg = (n + 63) / 64;
+  const int64_t cap = (int64_t)g_num_cus * g_fused_groups_per_cu;
+  if (nwg > cap) nwg = cap;
+  return (int)(nwg < 1 ? 1 : nwg);
 }
 
 template <typename TA, typename TM, int G, int NCH, int VEC>
-static void fused_launch(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda, int mode,
-                         const double* v, const double* y, double* part, int nwg, const int* done) {
-  const int64_t rpw = (n + nwg - 1) / nwg;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_fused<TA, TM, G, NCH, VEC, 0>), dim3(nwg), dim3(FUSED_NT), 0, st, A, n,
-                       (int)d, lda, v, y, rpw, part, done);
-  else
-    hipLaunchKernelGGL((k_fused<TA, TM, G, NCH, VEC, 1>), dim3(nwg), dim3(FUSED_NT), 0, st, A, n,
-                       (int)d, lda, v, y, rpw, part, done);
+static int fused_launch(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda, int mode,
+                        const double* v, const double* y, double* part, int nwg, const int* done) {
+  constexpr int UNR = 2;
+  const int g = nwg;
+  const int64_t rpw = (n + g - 1) / g;
+  const bool full = d == (int64_t)G * NCH * VEC;
+#define LSQ_FUSED_GO(M, F)                                                                         \
+  hipLaunchKernelGGL((k_fused<TA, TM, G, NCH, VEC, M, UNR, F>), dim3(g), dim3(FUSED_NT), 0, st, A, n, \
+                     (int)d, lda, v, y, rpw, part, done)
+  if (mode == 0) {
+    if (full) LSQ_FUSED_GO(0, true);
+    else LSQ_FUSED_GO(0, false);
+  } else {
+    if (full) LSQ_FUSED_GO(1, true);
+    else LSQ_FUSED_GO(1, false);
+  }
+#undef LSQ_FUSED_GO
+  return g;
 }
 
 template <typename TA, typename TM, int VEC>
-static void fused_dispatch(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda, int mode,
+static int fused_dispatch(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda, int mode,
                            const double* v, const double* y, double* part, int nwg,
                            const int* done) {
   if (d <= 16 * VEC * 2) {
     if (d <= 16 * VEC)
-      fused_launch<TA, TM, 16, 1, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+      return fused_launch<TA, TM, 16, 1, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
     else
-      fused_launch<TA, TM, 16, 2, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
-    return;
+      return fused_launch<TA, TM, 16, 2, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
   }
   const int64_t nch = (d + 64 * VEC - 1) / (64 * VEC);
   if (nch <= 1)
-    fused_launch<TA, TM, 64, 1, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+    return fused_launch<TA, TM, 64, 1, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
   else if (nch <= 2)
-    fused_launch<TA, TM, 64, 2, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+    return fused_launch<TA, TM, 64, 2, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
   else if (nch <= 4)
-    fused_launch<TA, TM, 64, 4, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+    return fused_launch<TA, TM, 64, 4, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
   else if (nch <= 8)
-    fused_launch<TA, TM, 64, 8, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+    return fused_launch<TA, TM, 64, 8, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
   else
-    fused_launch<TA, TM, 64, 16, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
+    return fused_launch<TA, TM, 64, 16, VEC>(st, A, n, d, lda, mode, v, y, part, nwg, done);
 }
 
-void fused_pass(hipStream_t st, const void* A, int a_f32, int f32_math, int64_t n, int64_t d,
-                int64_t lda, int mode, const double* v, const double* y, double* part, int nwg,
-                const int* done) {
+int fused_pass(hipStream_t st, const void* A, int a_f32, int f32_math, int64_t n, int64_t d,
+               int64_t lda, int mode, const double* v, const double* y, double* part, int nwg,
+               const int* done) {
   const uintptr_t addr = (uintptr_t)A;
   if (a_f32) {
     const bool vec = (addr % 16 == 0) && (lda % 4 == 0) && (d % 4 == 0);
     const float* Af = (const float*)A;
     if (f32_math) {
-      if (vec) fused_dispatch<float, float, 4>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
-      else fused_dispatch<float, float, 1>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
+      if (vec) return fused_dispatch<float, float, 4>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
+      else return fused_dispatch<float, float, 1>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
     } else {
-      if (vec) fused_dispatch<float, double, 4>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
-      else fused_dispatch<float, double, 1>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
+      if (vec) return fused_dispatch<float, double, 4>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
+      else return fused_dispatch<float, double, 1>(st, Af, n, d, lda, mode, v, y, part, nwg, done);
     }
   } else {
     const bool vec = (addr % 16 == 0) && (lda % 2 == 0) && (d % 2 == 0);
     const double* Ad = (const double*)A;
-    if (vec) fused_dispatch<double, double, 2>(st, Ad, n, d, lda, mode, v, y, part, nwg, done);
-    else fused_dispatch<double, double, 1>(st, Ad, n, d, lda, mode, v, y, part, nwg, done);
+    if (vec) return fused_dispatch<double, double, 2>(st, Ad, n, d, lda, mode, v, y, part, nwg, done);
+    else return fused_dispatch<double, double, 1>(st, Ad, n, d, lda, mode, v, y, part, nwg, done);
   }
 }
 
 // --------------------------------------------------------------------------------------------------
-// Fixed-order column sums of the partials: out[c] = sum_g part[g][c], c <= d.
+// Fixed-order reduction of the per-workgroup partials.
 // --------------------------------------------------------------------------------------------------
-__device__ __forceinline__ double colsum(const double* part, int nwg, int64_t width, int64_t c,
-                                         int ph, double* sh) {
-  // 256 threads: 64 columns x 4 phases; thread (c, ph) sums rows ph, ph+4, ...
+// Stage 1: workgroup (column block, split) sums rows [split*chunk, (split+1)*chunk) of the partials.
+__global__ __launch_bounds__(256) void k_reduce_stage1(const double* __restrict__ part, int nwg,
+                                                       int64_t d, double* __restrict__ part2,
+                                                       const int* __restrict__ done) {
+  if (done && *done) return;
+  __shared__ double sh[256];
+  const int64_t width = d + 1;
+  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int ph = threadIdx.x >> 6;
+  const int chunk = (nwg + REDUCE_SPLIT - 1) / REDUCE_SPLIT;
+  const int g0 = blockIdx.y * chunk, g1 = min(nwg, g0 + chunk);
   double s = 0.0;
   if (c < width)
-    for (int g = ph; g < nwg; g += 4) s += part[(int64_t)g * width + c];
+    for (int g = g0 + ph; g < g1; g += 4) s += part[(int64_t)g * width + c];
   const int cl = threadIdx.x & 63;
   sh[ph * 64 + cl] = s;
   __syncthreads();
-  double t = sh[cl] + sh[64 + cl] + sh[128 + cl] + sh[192 + cl];
-  __syncthreads();
-  return t;
+  if (ph == 0 && c < width)
+    part2[(int64_t)blockIdx.y * width + c] = ((sh[cl] + sh[64 + cl]) + sh[128 + cl]) + sh[192 + cl];
 }
 
-__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part, int nwg,
+void reduce_stage1(hipStream_t st, const double* part, int nwg, int64_t d, double* part2,
+                   const int* done) {
+  hipLaunchKernelGGL(k_reduce_stage1, dim3((unsigned)((d + 1 + 63) / 64), REDUCE_SPLIT), dim3(256), 0, st,
+                     part, nwg, d, part2, done);
+}
+
+// Stage 2 for one column: sum of the REDUCE_SPLIT rows, in order.
+__device__ __forceinline__ double col2(const double* part2, int nrows, int64_t width, int64_t c) {
+  double s = 0.0;
+  for (int g = 0; g < nrows; ++g) s += part2[(int64_t)g * width + c];
+  return s;
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cols(const double* __restrict__ part2, int nrows,
                                                      int64_t d, double* __restrict__ out,
                                                      const int* __restrict__ done) {
   if (done && *done) return;
-  __shared__ double sh[256];
-  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int ph = threadIdx.x >> 6;
-  const double t = colsum(part, nwg, d + 1, c, ph, sh);
-  if (ph == 0 && c <= d) out[c] = t;
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (c <= d) out[c] = col2(part2, nrows, d + 1, c);
 }
 
-void reduce_partials(hipStream_t st, const double* part, int nwg, int64_t d, double* out,
-                     const int* done) {
-  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((d + 1 + 63) / 64)), dim3(256), 0, st, part, nwg,
-                     d, out, done);
+void reduce_partials(hipStream_t st, const double* part, double* part2, int nwg, int64_t d,
+                     double* out, const int* done) {
+  reduce_stage1(st, part, nwg, d, part2, done);
+  hipLaunchKernelGGL(k_reduce_cols, dim3((unsigned)((d + 1 + 255) / 256)), dim3(256), 0, st, part2,
+                     REDUCE_SPLIT, d, out, done);
 }
 
-// Sum of the scalar column (p^T H p) computed identically by every workgroup.
-__device__ double scalar_sum(const double* part, int nwg, int64_t d, double* sh) {
-  double s = 0.0;
-  for (int g = threadIdx.x; g < nwg; g += 256) s += part[(int64_t)g * (d + 1) + d];
-  s = wave_sum(s);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  const double t = sh[0] + sh[1] + sh[2] + sh[3];
-  __syncthreads();
-  return t;
-}
-
-// alpha = rho / p^T H p;  x += alpha p;  r -= alpha H p.
-__global__ __launch_bounds__(256) void k_pcg_xr(const double* __restrict__ part, int nwg, int64_t d,
+// alpha = rho / p^T H p;  x += alpha p;  r -= alpha H p  (H p and p^T H p from the stage-1 rows).
+__global__ __launch_bounds__(256) void k_pcg_xr(const double* __restrict__ part2, int nrows, int64_t d,
                                                 double* __restrict__ x, double* __restrict__ r,
                                                 const double* __restrict__ p, DevState* ds) {
   if (ds->done) return;
-  __shared__ double sh[256];
   const double rho = ds->rho;
-  const double pHp = scalar_sum(part, nwg, d, sh);
-  const int64_t c = (int64_t)blockIdx.x * 64 + (threadIdx.x & 63);
-  const int ph = threadIdx.x >> 6;
-  const double w = colsum(part, nwg, d + 1, c, ph, sh);
+  const int64_t width = d + 1;
+  const double pHp = col2(part2, nrows, width, d);
+  const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const bool bad = !(pHp > 0.0) || !isfinite(pHp);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ds->pHp = pHp;
-    if (bad) {
-      ds->status = isfinite(pHp) ? (int)LSQ_ERR_RANK : (int)LSQ_ERR_NONFINITE;
-    }
+    if (bad) ds->status = isfinite(pHp) ? (int)LSQ_ERR_RANK : (int)LSQ_ERR_NONFINITE;
   }
   if (bad) return;
   const double alpha = rho / pHp;
   if (blockIdx.x == 0 && threadIdx.x == 0) ds->alpha = alpha;
-  if (ph == 0 && c < d) {
+  if (c < d) {
+    const double w = col2(part2, nrows, width, c);
     x[c] = fma(alpha, p[c], x[c]);
     r[c] = fma(-alpha, w, r[c]);
   }
 }
 
-void pcg_update_xr(hipStream_t st, const double* part, int nwg, int64_t d, double* x, double* r,
+void pcg_update_xr(hipStream_t st, const double* part2, int nrows, int64_t d, double* x, double* r,
                    const double* p, DevState* ds) {
-  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((d + 63) / 64)), dim3(256), 0, st, part, nwg, d, x, r,
-                     p, ds);
+  hipLaunchKernelGGL(k_pcg_xr, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, part2, nrows, d, x,
+                     r, p, ds);
 }
 
 // --------------------------------------------------------------------------------------------------

@@ -5,10 +5,10 @@
 // H_N = H_{N2} (x) H_{N1}, so
 //     (H E A)[k] = sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo],
 //     T[j_hi, k_lo] = sum_{j_lo} H_{N1}[k_lo, j_lo] e_j A[j].
-// Pass A computes T block by block in LDS (a 128-byte column slice of N1 <= 512 consecutive rows),
-// keeping only the k_lo that some selected row needs.  Pass B evaluates the high-bit sum for the
-// selected rows only, grouped by k_lo so that every needed T row is read once.  HBM traffic is about
-// |A| + 2 f |T| with f the fraction of k_lo values used; the flop count of pass B is m N2 d.
+// Pass A computes T block by block (a 128-byte column slice of N1 = 256 consecutive rows, or N rows
+// when N < 256), keeping only the k_lo that some selected row needs.  Pass B evaluates the high-bit
+// sum for the selected rows only, grouped by k_lo so that every needed T row is read once.  HBM
+// traffic is about |A| + 2 f |T| with f the fraction of k_lo values used; pass B does m N2 d adds.
 //
 // SJLT: the hashed scatter is done as a stable counting sort of the (target, row) pairs followed by
 // a segmented reduction per target row, in increasing row order: no atomics touch S A, and the
@@ -102,6 +102,97 @@ size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32) 
 }
 
 // --------------------------------------------------------------------------------------------------
+// Pass A (N >= 256): blocks of SRHT_N1 = 256 rows, 128-byte column slices.  Layout 1: thread (c, g)
+// holds rows g + G i; butterflies over i transform the high row bits in registers.  One LDS
+// transpose to layout 2: thread (c, h) holds the G consecutive rows of each of its row groups;
+// butterflies over the low bits.  LDS traffic is one write and one read of the tile.
+// --------------------------------------------------------------------------------------------------
+constexpr int SRHT_N1 = 256;
+
+template <int V, typename T>
+__device__ __forceinline__ void fwht_regs(T (&x)[V]) {
+#pragma unroll
+  for (int h = 1; h < V; h <<= 1)
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      if ((i & h) == 0) {
+        const T u = x[i], v = x[i + h];
+        x[i] = u + v;
+        x[i + h] = u - v;
+      }
+}
+
+template <typename TA, typename TC, int V, int G>
+__device__ __forceinline__ void srht_load_slice(const TA* __restrict__ A, int64_t n, int64_t d,
+                                                int64_t lda, const int8_t* __restrict__ signs,
+                                                int64_t rbase, int g, int64_t col, TC (&x)[V]) {
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    const int64_t row = rbase + g + G * i;
+    TC v = 0;
+    if (row < n && col < d) {
+      v = (TC)A[row * lda + col];
+      if (signs[row] < 0) v = -v;
+    }
+    x[i] = v;
+  }
+}
+
+// grid (N2, slice groups): a workgroup walks the column slices blockIdx.y, blockIdx.y + gridDim.y, ...
+// of its 256-row block, loading the next slice while transforming the current one.
+template <typename TA, typename TC>
+__global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, int64_t n, int64_t d,
+                                                     int64_t lda, const int8_t* __restrict__ signs,
+                                                     const int* __restrict__ slot, int nneeded,
+                                                     TC* __restrict__ T) {
+  constexpr int DC = 128 / sizeof(TC);   // columns per slice
+  constexpr int G = 256 / DC;            // row groups (low row bits)
+  constexpr int V = SRHT_N1 / G;         // rows per thread
+  constexpr int K = V / G;               // row groups per thread in layout 2
+  __shared__ TC tile[SRHT_N1 * DC];
+  __shared__ int slot_s[SRHT_N1];
+  const int64_t jhi = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int c = tid % DC, g = tid / DC, h = g;
+  const int64_t rbase = jhi * SRHT_N1;
+  const int nslices = (int)((d + DC - 1) / DC);
+  slot_s[tid] = slot[tid];
+  int sidx = blockIdx.y;
+  if (sidx >= nslices) return;
+  TC x[V];
+  srht_load_slice<TA, TC, V, G>(A, n, d, lda, signs, rbase, g, (int64_t)sidx * DC + c, x);
+  for (; sidx < nslices; sidx += gridDim.y) {
+    const int64_t col = (int64_t)sidx * DC + c;
+    const int nxt = sidx + gridDim.y;
+    TC xn[V];
+    if (nxt < nslices) srht_load_slice<TA, TC, V, G>(A, n, d, lda, signs, rbase, g, (int64_t)nxt * DC + c, xn);
+    fwht_regs<V>(x);
+#pragma unroll
+    for (int i = 0; i < V; ++i) tile[(g + G * i) * DC + c] = x[i];
+    __syncthreads();
+    // layout 2: thread (c, h) holds rows G (h + G k) + j, j < G, k < K
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      TC z[G];
+#pragma unroll
+      for (int j = 0; j < G; ++j) z[j] = tile[(G * (h + G * k) + j) * DC + c];
+      fwht_regs<G>(z);
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int r = G * (h + G * k) + j;
+        const int sl = slot_s[r];
+        if (sl >= 0 && col < d) T[(jhi * nneeded + sl) * d + col] = z[j];
+      }
+    }
+    __syncthreads();
+    if (nxt < nslices) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) x[i] = xn[i];
+    }
+  }
+}
+
+// --------------------------------------------------------------------------------------------------
 // Pass A: sign flip + zero padding + Walsh-Hadamard transform of N1 consecutive rows, in LDS.
 // --------------------------------------------------------------------------------------------------
 template <typename TA, typename TC>
@@ -145,132 +236,179 @@ __global__ __launch_bounds__(256) void k_srht_passA(const TA* __restrict__ A, in
   }
 }
 
-// --------------------------------------------------------------------------------------------------
-// Pass B: for the selected rows sharing k_lo, sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo].
-// One workgroup per k_lo; chunks of CH rows; columns spread over the threads.
-// --------------------------------------------------------------------------------------------------
 constexpr int SRHT_CH = 16;
 
-template <typename TC, int NCOL>
-__global__ __launch_bounds__(256) void k_srht_passB(const TC* __restrict__ T, int64_t N2, int64_t d,
-                                                    int L1, const int64_t* __restrict__ rows,
-                                                    const int* __restrict__ slot,
-                                                    const int* __restrict__ order,
-                                                    const int* __restrict__ bstart, int nneeded,
-                                                    double scale, double* __restrict__ SA,
-                                                    int64_t ldsa) {
+// Pass B, split over the high-bit range: workgroup (k_lo, js) sums j_hi in its range for every
+// selected row of bucket k_lo into partial[js]; a final fixed-order sum over js scales by m^{-1/2}.
+// Each thread owns CPT contiguous columns; the sign (-1)^popcount(k_hi & j_hi) is uniform across
+// the workgroup and evaluated on the scalar unit.
+template <typename TC, int CPT>
+__device__ __forceinline__ void load_cpt(const TC* __restrict__ p, int64_t cbase, int64_t d, bool vec,
+                                         double (&v)[CPT]) {
+  if (CPT == 4 && vec) {
+    if (sizeof(TC) == 4) {
+      const float4 f = *(const float4*)(p + cbase);
+      v[0] = f.x;
+      v[1] = f.y;
+      v[2] = f.z;
+      v[3] = f.w;
+    } else {
+      const double2 a = *(const double2*)(p + cbase);
+      const double2 b = *(const double2*)(p + cbase + 2);
+      v[0] = a.x;
+      v[1] = a.y;
+      v[2 % CPT] = b.x;
+      v[3 % CPT] = b.y;
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) v[u] = cbase + u < d ? (double)p[cbase + u] : 0.0;
+  }
+}
+
+template <typename TC, int CPT>
+__global__ __launch_bounds__(256) void k_srht_passB2(const TC* __restrict__ T, int64_t N2, int64_t d,
+                                                     int L1, const int64_t* __restrict__ rows,
+                                                     const int* __restrict__ slot,
+                                                     const int* __restrict__ order,
+                                                     const int* __restrict__ bstart, int nneeded,
+                                                     int64_t m, double* __restrict__ partial) {
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
   const int tid = threadIdx.x;
-  __shared__ uint64_t khi_s[SRHT_CH];
-  __shared__ int pos_s[SRHT_CH];
+  const int64_t cbase = (int64_t)tid * CPT;
+  // vector loads need every thread's columns inside the row and 16-byte aligned rows
+  const bool vec = (CPT == 4) && (d % 4 == 0) && (cbase + CPT <= d);
+  const TC* base = T + (int64_t)sl * d;
+  const int64_t stride = (int64_t)nneeded * d;
   for (int cb = b0; cb < b1; cb += SRHT_CH) {
     const int nq = min(SRHT_CH, b1 - cb);
-    __syncthreads();
-    if (tid < nq) {
-      const int q = order[cb + tid];
-      pos_s[tid] = q;
-      khi_s[tid] = (uint64_t)rows[q] >> L1;
-    }
-    __syncthreads();
     uint64_t khi[SRHT_CH];
 #pragma unroll
-    for (int q = 0; q < SRHT_CH; ++q) khi[q] = q < nq ? khi_s[q] : 0;
-    double acc[SRHT_CH][NCOL];
+    for (int q = 0; q < SRHT_CH; ++q) {
+      const uint64_t v = q < nq ? ((uint64_t)rows[order[cb + q]] >> L1) : 0ull;
+      khi[q] = __builtin_amdgcn_readfirstlane((unsigned)v) |
+               ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32);
+    }
+    double acc[SRHT_CH][CPT];
 #pragma unroll
     for (int q = 0; q < SRHT_CH; ++q)
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c) acc[q][c] = 0.0;
-    const TC* base = T + (int64_t)sl * d;
-    const int64_t stride = (int64_t)nneeded * d;
-    int64_t jh = 0;
-    for (; jh + 2 <= N2; jh += 2) {
-      double v0[NCOL], v1[NCOL];
+      for (int u = 0; u < CPT; ++u) acc[q][u] = 0.0;
+    int64_t jh = jh0;
+    for (; jh + 4 <= jh1; jh += 4) {
+      double v[4][CPT];
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c) {
-        const int64_t col = tid + 256 * c;
-        v0[c] = col < d ? (double)base[jh * stride + col] : 0.0;
-        v1[c] = col < d ? (double)base[(jh + 1) * stride + col] : 0.0;
-      }
+      for (int k = 0; k < 4; ++k) load_cpt<TC, CPT>(base + (jh + k) * stride, cbase, d, vec, v[k]);
 #pragma unroll
       for (int q = 0; q < SRHT_CH; ++q) {
-        const double s0 = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
-        const double s1 = (__popcll(khi[q] & (uint64_t)(jh + 1)) & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int c = 0; c < NCOL; ++c) acc[q][c] = fma(s1, v1[c], fma(s0, v0[c], acc[q][c]));
+        for (int k = 0; k < 4; ++k) {
+          const double sg = (__popcll(khi[q] & (uint64_t)(jh + k)) & 1) ? -1.0 : 1.0;
+#pragma unroll
+          for (int u = 0; u < CPT; ++u) acc[q][u] = fma(sg, v[k][u], acc[q][u]);
+        }
       }
     }
-    for (; jh < N2; ++jh) {
-      double v0[NCOL];
-#pragma unroll
-      for (int c = 0; c < NCOL; ++c) {
-        const int64_t col = tid + 256 * c;
-        v0[c] = col < d ? (double)base[jh * stride + col] : 0.0;
-      }
+    for (; jh < jh1; ++jh) {
+      double v[CPT];
+      load_cpt<TC, CPT>(base + jh * stride, cbase, d, vec, v);
 #pragma unroll
       for (int q = 0; q < SRHT_CH; ++q) {
-        const double s0 = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
+        const double sg = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
 #pragma unroll
-        for (int c = 0; c < NCOL; ++c) acc[q][c] = fma(s0, v0[c], acc[q][c]);
+        for (int u = 0; u < CPT; ++u) acc[q][u] = fma(sg, v[u], acc[q][u]);
       }
     }
+    double* out = partial + (int64_t)js * m * d;
 #pragma unroll
     for (int q = 0; q < SRHT_CH; ++q) {
-      if (q >= nq) break;
-      const int64_t r = pos_s[q];
+      if (q < nq) {
+        const int64_t r = order[cb + q];
 #pragma unroll
-      for (int c = 0; c < NCOL; ++c) {
-        const int64_t col = tid + 256 * c;
-        if (col < d) SA[r * ldsa + col] = acc[q][c] * scale;
+        for (int u = 0; u < CPT; ++u)
+          if (cbase + u < d) out[r * d + cbase + u] = acc[q][u];
       }
     }
   }
 }
 
+__global__ void k_srht_final(const double* __restrict__ partial, int JS, int64_t m, int64_t d,
+                             double scale, double* __restrict__ SA, int64_t ldsa) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * d) return;
+  double s = 0.0;
+  for (int k = 0; k < JS; ++k) s += partial[(int64_t)k * m * d + idx];
+  SA[(idx / d) * ldsa + idx % d] = s * scale;
+}
+
+int srht_js(int64_t N2) { return N2 >= 256 ? 4 : 1; }
+
+size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d) {
+  return (size_t)srht_js(N2) * (size_t)m * (size_t)d * sizeof(double);
+}
+
 template <typename TA, typename TC>
 static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda,
                          const SrhtPlan& p, const int8_t* signs, const int64_t* rows,
-                         const int* slot, const int* order, const int* bstart, TC* T, double* SA,
-                         int64_t ldsa) {
+                         const int* slot, const int* order, const int* bstart, TC* T,
+                         double* partial, double* SA, int64_t ldsa) {
   constexpr int DC = 128 / sizeof(TC);
   int L1 = 0;
   while ((1ll << L1) < p.N1) ++L1;
-  dim3 ga((unsigned)p.N2, (unsigned)((d + DC - 1) / DC));
-  hipLaunchKernelGGL((k_srht_passA<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, (int)p.N1, L1, signs,
-                     slot, p.nneeded, T);
-  const double scale = 1.0 / sqrt((double)p.m);
-  const int ncol = (int)((d + 255) / 256);
-  dim3 gb((unsigned)p.N1);
-#define LSQ_PASSB(NC)                                                                              \
-  hipLaunchKernelGGL((k_srht_passB<TC, NC>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot,      \
-                     order, bstart, p.nneeded, scale, SA, ldsa)
-  if (ncol <= 1)
+  const int64_t nslices = (d + DC - 1) / DC;
+  if (p.N1 == SRHT_N1) {
+    // enough workgroups to fill the chip, each walking several column slices of its row block
+    int64_t sg = (4096 + p.N2 - 1) / p.N2;
+    if (sg > nslices) sg = nslices;
+    if (sg < 1) sg = 1;
+    dim3 ga((unsigned)p.N2, (unsigned)sg);
+    hipLaunchKernelGGL((k_srht_passA2<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, signs, slot,
+                       p.nneeded, T);
+  } else {
+    dim3 ga((unsigned)p.N2, (unsigned)nslices);
+    hipLaunchKernelGGL((k_srht_passA<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, (int)p.N1, L1, signs,
+                       slot, p.nneeded, T);
+  }
+  const int JS = srht_js(p.N2);
+  const int cpt = (int)((d + 255) / 256);
+  dim3 gb((unsigned)p.N1, (unsigned)JS);
+#define LSQ_PASSB(C)                                                                              \
+  hipLaunchKernelGGL((k_srht_passB2<TC, C>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot, order, \
+                     bstart, p.nneeded, p.m, partial)
+  if (cpt <= 1)
     LSQ_PASSB(1);
-  else if (ncol <= 2)
+  else if (cpt <= 2)
     LSQ_PASSB(2);
+  else if (cpt <= 3)
+    LSQ_PASSB(3);
   else
     LSQ_PASSB(4);
 #undef LSQ_PASSB
+  hipLaunchKernelGGL(k_srht_final, dim3((unsigned)((p.m * d + 255) / 256)), dim3(256), 0, st, partial, JS,
+                     p.m, d, 1.0 / sqrt((double)p.m), SA, ldsa);
 }
 
 void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
                 int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
-                const int* slot, const int* order, const int* bstart, void* tbuf, double* SA,
-                int64_t ldsa) {
+                const int* slot, const int* order, const int* bstart, void* tbuf, double* partial,
+                double* SA, int64_t ldsa) {
   if (a_f32 && compute_f32)
     srht_apply_t<float, float>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order, bstart,
-                               (float*)tbuf, SA, ldsa);
+                               (float*)tbuf, partial, SA, ldsa);
   else if (a_f32)
     srht_apply_t<float, double>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order,
-                                bstart, (double*)tbuf, SA, ldsa);
+                                bstart, (double*)tbuf, partial, SA, ldsa);
   else if (compute_f32)
     srht_apply_t<double, float>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
-                                bstart, (float*)tbuf, SA, ldsa);
+                                bstart, (float*)tbuf, partial, SA, ldsa);
   else
     srht_apply_t<double, double>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
-                                 bstart, (double*)tbuf, SA, ldsa);
+                                 bstart, (double*)tbuf, partial, SA, ldsa);
 }
 
 // --------------------------------------------------------------------------------------------------

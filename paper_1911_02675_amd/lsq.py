@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_timing", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_timing", "lsq_tune", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -88,6 +88,7 @@ def load():
         "lsq_draw_sjlt": ([P, U64, U64, I64, I64, I32, P, P], I32),
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
         "lsq_fused_pass_timing": ([P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)], I32),
+        "lsq_tune": ([C.c_char_p, I64], I32),
         "lsq_status_string": ([I32], C.c_char_p),
         "lsq_last_error": ([], C.c_char_p),
         "lsq_version": ([], C.c_char_p),
@@ -108,6 +109,11 @@ def _check(status):
     if status != LSQ_OK:
         raise LsqError(status, load().lsq_last_error().decode())
     return status
+
+
+def tune(key, value):
+    """Set a process-wide tuning parameter of the library (see lsq_tune in include/lsq.h)."""
+    _check(load().lsq_tune(key.encode(), int(value)))
 
 
 def _ptr(t):
