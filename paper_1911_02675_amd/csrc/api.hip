@@ -48,6 +48,7 @@ struct lsq_ctx {
   size_t fused_used = 0;
   double fused_total_ms = 0.0, fused_last_ms = 0.0;
   int64_t fused_count = 0;
+  double last_rate = -1.0;  // contraction per PCG iteration seen in the previous loop (batch sizing)
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -284,12 +285,15 @@ static lsq_status pcg_loop(lsq_ctx* c, const lsq_problem* pr, int f32_math, cons
   while (!done && it < max_iter) {
     int k = std::min(check_every, max_iter - it);
     const double proxy = c->hds->rho0 > 0.0 ? 4.0 * sqrt(fmax(c->hds->rho, 0.0) / c->hds->rho0) : 0.0;
-    if (tol > 0.0 && prev_proxy > 0.0 && proxy > 0.0 && proxy < prev_proxy && it > prev_it) {
-      const double rate = pow(proxy / prev_proxy, 1.0 / (it - prev_it));
-      if (rate < 1.0 && rate > 0.0) {
-        const double need = ceil(log(tol / proxy) / log(rate));
-        if (need >= 1.0 && need < k) k = (int)need;
-      }
+    double rate = -1.0;
+    if (prev_proxy > 0.0 && proxy > 0.0 && proxy < prev_proxy && it > prev_it)
+      rate = pow(proxy / prev_proxy, 1.0 / (it - prev_it));
+    else if (it == 0)
+      rate = c->last_rate;  // first batch: the rate of the previous solve on this context
+    if (tol > 0.0 && proxy > 0.0 && rate > 0.0 && rate < 1.0) {
+      const double need = ceil(log(tol / proxy) / log(rate));
+      if (need >= 1.0 && need < k) k = (int)need;
+      if (it > 0) c->last_rate = rate;
     }
     prev_proxy = proxy;
     prev_it = it;

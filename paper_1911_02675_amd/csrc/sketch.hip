@@ -124,18 +124,22 @@ __device__ __forceinline__ void fwht_regs(T (&x)[V]) {
 
 template <typename TA, typename TC, int V, int G>
 __device__ __forceinline__ void srht_load_slice(const TA* __restrict__ A, int64_t n, int64_t d,
-                                                int64_t lda, const int8_t* __restrict__ signs,
+                                                int64_t lda, const int8_t* __restrict__ sg_s,
                                                 int64_t rbase, int g, int64_t col, TC (&x)[V]) {
+  // row rbase + g + G i: one base pointer and a uniform stride G * lda
+  const TA* p = A + (rbase + g) * lda + col;
+  const int64_t step = (int64_t)G * lda;
+  if (rbase + SRHT_N1 <= n && col < d) {
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
-    const int64_t row = rbase + g + G * i;
-    TC v = 0;
-    if (row < n && col < d) {
-      v = (TC)A[row * lda + col];
-      if (signs[row] < 0) v = -v;
-    }
-    x[i] = v;
+    for (int i = 0; i < V; ++i) x[i] = (TC)__builtin_nontemporal_load(p + i * step);
+  } else {
+#pragma unroll
+    for (int i = 0; i < V; ++i)
+      x[i] = (rbase + g + G * i < n && col < d) ? (TC)__builtin_nontemporal_load(p + i * step) : (TC)0;
   }
+#pragma unroll
+  for (int i = 0; i < V; ++i)
+    if (sg_s[g + G * i] < 0) x[i] = -x[i];
 }
 
 // grid (N2, slice groups): a workgroup walks the column slices blockIdx.y, blockIdx.y + gridDim.y, ...
@@ -151,21 +155,24 @@ __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, i
   constexpr int K = V / G;               // row groups per thread in layout 2
   __shared__ TC tile[SRHT_N1 * DC];
   __shared__ int slot_s[SRHT_N1];
+  __shared__ int8_t sg_s[SRHT_N1];
   const int64_t jhi = blockIdx.x;
   const int tid = threadIdx.x;
   const int c = tid % DC, g = tid / DC, h = g;
   const int64_t rbase = jhi * SRHT_N1;
   const int nslices = (int)((d + DC - 1) / DC);
   slot_s[tid] = slot[tid];
+  sg_s[tid] = rbase + tid < n ? signs[rbase + tid] : (int8_t)1;
+  __syncthreads();
   int sidx = blockIdx.y;
   if (sidx >= nslices) return;
   TC x[V];
-  srht_load_slice<TA, TC, V, G>(A, n, d, lda, signs, rbase, g, (int64_t)sidx * DC + c, x);
+  srht_load_slice<TA, TC, V, G>(A, n, d, lda, sg_s, rbase, g, (int64_t)sidx * DC + c, x);
   for (; sidx < nslices; sidx += gridDim.y) {
     const int64_t col = (int64_t)sidx * DC + c;
     const int nxt = sidx + gridDim.y;
     TC xn[V];
-    if (nxt < nslices) srht_load_slice<TA, TC, V, G>(A, n, d, lda, signs, rbase, g, (int64_t)nxt * DC + c, xn);
+    if (nxt < nslices) srht_load_slice<TA, TC, V, G>(A, n, d, lda, sg_s, rbase, g, (int64_t)nxt * DC + c, xn);
     fwht_regs<V>(x);
 #pragma unroll
     for (int i = 0; i < V; ++i) tile[(g + G * i) * DC + c] = x[i];
@@ -181,7 +188,7 @@ __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, i
       for (int j = 0; j < G; ++j) {
         const int r = G * (h + G * k) + j;
         const int sl = slot_s[r];
-        if (sl >= 0 && col < d) T[(jhi * nneeded + sl) * d + col] = z[j];
+        if (sl >= 0 && col < d) __builtin_nontemporal_store(z[j], T + (jhi * nneeded + sl) * d + col);
       }
     }
     __syncthreads();
@@ -238,100 +245,82 @@ __global__ __launch_bounds__(256) void k_srht_passA(const TA* __restrict__ A, in
 
 constexpr int SRHT_CH = 16;
 
-// Pass B, split over the high-bit range: workgroup (k_lo, js) sums j_hi in its range for every
-// selected row of bucket k_lo into partial[js]; a final fixed-order sum over js scales by m^{-1/2}.
-// Each thread owns CPT contiguous columns; the sign (-1)^popcount(k_hi & j_hi) is uniform across
-// the workgroup and evaluated on the scalar unit.
-template <typename TC, int CPT>
-__device__ __forceinline__ void load_cpt(const TC* __restrict__ p, int64_t cbase, int64_t d, bool vec,
-                                         double (&v)[CPT]) {
-  if (CPT == 4 && vec) {
-    if (sizeof(TC) == 4) {
-      const float4 f = *(const float4*)(p + cbase);
-      v[0] = f.x;
-      v[1] = f.y;
-      v[2] = f.z;
-      v[3] = f.w;
-    } else {
-      const double2 a = *(const double2*)(p + cbase);
-      const double2 b = *(const double2*)(p + cbase + 2);
-      v[0] = a.x;
-      v[1] = a.y;
-      v[2 % CPT] = b.x;
-      v[3 % CPT] = b.y;
-    }
-  } else {
-#pragma unroll
-    for (int u = 0; u < CPT; ++u) v[u] = cbase + u < d ? (double)p[cbase + u] : 0.0;
-  }
-}
+// Pass B on FP64 matrix cores.  For the (up to 16) selected rows of bucket k_lo and 4 consecutive
+// j_hi, the +-1 signs form the 16 x 4 A operand of v_mfma_f64_16x16x4 (lane l: row l % 16, j_hi offset
+// l / 16) and 4 rows of T the 4 x 16 B operand (lane l: T row offset l / 16, column l % 16); the
+// 16 x 16 result block of a wavefront's column block accumulates over the j_hi range of this
+// workgroup (lane l, register v: selected row l / 16 + 4 v, column l % 16).  Grid: (k_lo, j_hi split,
+// 512-column group).
+typedef double lsq_d4 __attribute__((ext_vector_type(4)));
+constexpr int SRHT_NB = 8;
+constexpr int SRHT_PF = 3;  // steps of 4 rows in flight per wavefront  // 16-column blocks per wavefront; blockIdx.z selects a 512-column group
 
-template <typename TC, int CPT>
-__global__ __launch_bounds__(256) void k_srht_passB2(const TC* __restrict__ T, int64_t N2, int64_t d,
-                                                     int L1, const int64_t* __restrict__ rows,
-                                                     const int* __restrict__ slot,
-                                                     const int* __restrict__ order,
-                                                     const int* __restrict__ bstart, int nneeded,
-                                                     int64_t m, double* __restrict__ partial) {
+template <typename TC>
+__global__ __launch_bounds__(256) void k_srht_passB_mfma(const TC* __restrict__ T, int64_t N2, int64_t d,
+                                                         int L1, const int64_t* __restrict__ rows,
+                                                         const int* __restrict__ slot,
+                                                         const int* __restrict__ order,
+                                                         const int* __restrict__ bstart, int nneeded,
+                                                         int64_t m, double* __restrict__ partial) {
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
   const int js = blockIdx.y, JS = gridDim.y;
   const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
-  const int tid = threadIdx.x;
-  const int64_t cbase = (int64_t)tid * CPT;
-  // vector loads need every thread's columns inside the row and 16-byte aligned rows
-  const bool vec = (CPT == 4) && (d % 4 == 0) && (cbase + CPT <= d);
-  const TC* base = T + (int64_t)sl * d;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int qi = lane & 15, kk = lane >> 4;
   const int64_t stride = (int64_t)nneeded * d;
-  for (int cb = b0; cb < b1; cb += SRHT_CH) {
-    const int nq = min(SRHT_CH, b1 - cb);
-    uint64_t khi[SRHT_CH];
+  const TC* base = T + (int64_t)sl * d;
+  int64_t colb[SRHT_NB];
+  bool colok[SRHT_NB];
 #pragma unroll
-    for (int q = 0; q < SRHT_CH; ++q) {
-      const uint64_t v = q < nq ? ((uint64_t)rows[order[cb + q]] >> L1) : 0ull;
-      khi[q] = __builtin_amdgcn_readfirstlane((unsigned)v) |
-               ((uint64_t)__builtin_amdgcn_readfirstlane((unsigned)(v >> 32)) << 32);
+  for (int b = 0; b < SRHT_NB; ++b) {
+    // a wavefront owns SRHT_NB consecutive 16-column blocks (whole cache lines per row)
+    colb[b] = (int64_t)blockIdx.z * (4 * SRHT_NB * 16) + (int64_t)(wv * SRHT_NB + b) * 16 + qi;
+    colok[b] = colb[b] < d;
+  }
+  for (int cb = b0; cb < b1; cb += 16) {
+    const int nq = min(16, b1 - cb);
+    const bool qok = qi < nq;
+    const uint64_t khi = qok ? ((uint64_t)rows[order[cb + qi]] >> L1) : 0ull;
+    lsq_d4 acc[SRHT_NB];
+#pragma unroll
+    for (int b = 0; b < SRHT_NB; ++b) acc[b] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+    // raw (storage-type) prefetch ring of SRHT_PF steps; values are converted right before use so
+    // that the loads in flight do not have to complete before the current matrix instructions
+    TC raw[SRHT_PF][SRHT_NB];
+#pragma unroll
+    for (int f = 0; f < SRHT_PF; ++f) {
+      const int64_t j = jh0 + 4 * f + kk;
+#pragma unroll
+      for (int b = 0; b < SRHT_NB; ++b)
+        raw[f][b] = (j < jh1 && colok[b]) ? __builtin_nontemporal_load(base + j * stride + colb[b]) : (TC)0;
     }
-    double acc[SRHT_CH][CPT];
+    for (int64_t jh = jh0; jh < jh1; jh += 4 * SRHT_PF) {
 #pragma unroll
-    for (int q = 0; q < SRHT_CH; ++q)
+      for (int f = 0; f < SRHT_PF; ++f) {
+        const int64_t j = jh + 4 * f + kk;
+        const double a = (qok && j < jh1) ? ((__popcll(khi & (uint64_t)j) & 1) ? -1.0 : 1.0) : 0.0;
+        double bv[SRHT_NB];
 #pragma unroll
-      for (int u = 0; u < CPT; ++u) acc[q][u] = 0.0;
-    int64_t jh = jh0;
-    for (; jh + 4 <= jh1; jh += 4) {
-      double v[4][CPT];
+        for (int b = 0; b < SRHT_NB; ++b) bv[b] = (double)raw[f][b];
+        const int64_t jn = j + 4 * SRHT_PF;
 #pragma unroll
-      for (int k = 0; k < 4; ++k) load_cpt<TC, CPT>(base + (jh + k) * stride, cbase, d, vec, v[k]);
+        for (int b = 0; b < SRHT_NB; ++b)
+          raw[f][b] = (jn < jh1 && colok[b]) ? __builtin_nontemporal_load(base + jn * stride + colb[b]) : (TC)0;
 #pragma unroll
-      for (int q = 0; q < SRHT_CH; ++q) {
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const double sg = (__popcll(khi[q] & (uint64_t)(jh + k)) & 1) ? -1.0 : 1.0;
-#pragma unroll
-          for (int u = 0; u < CPT; ++u) acc[q][u] = fma(sg, v[k][u], acc[q][u]);
-        }
-      }
-    }
-    for (; jh < jh1; ++jh) {
-      double v[CPT];
-      load_cpt<TC, CPT>(base + jh * stride, cbase, d, vec, v);
-#pragma unroll
-      for (int q = 0; q < SRHT_CH; ++q) {
-        const double sg = (__popcll(khi[q] & (uint64_t)jh) & 1) ? -1.0 : 1.0;
-#pragma unroll
-        for (int u = 0; u < CPT; ++u) acc[q][u] = fma(sg, v[u], acc[q][u]);
+        for (int b = 0; b < SRHT_NB; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[b], acc[b], 0, 0, 0);
       }
     }
     double* out = partial + (int64_t)js * m * d;
 #pragma unroll
-    for (int q = 0; q < SRHT_CH; ++q) {
-      if (q < nq) {
-        const int64_t r = order[cb + q];
+    for (int b = 0; b < SRHT_NB; ++b) {
+      if (!colok[b]) continue;
 #pragma unroll
-        for (int u = 0; u < CPT; ++u)
-          if (cbase + u < d) out[r * d + cbase + u] = acc[q][u];
+      for (int v = 0; v < 4; ++v) {
+        const int q = kk + 4 * v;
+        if (q < nq) out[(int64_t)order[cb + q] * d + colb[b]] = acc[b][v];
       }
     }
   }
@@ -375,20 +364,9 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                        slot, p.nneeded, T);
   }
   const int JS = srht_js(p.N2);
-  const int cpt = (int)((d + 255) / 256);
-  dim3 gb((unsigned)p.N1, (unsigned)JS);
-#define LSQ_PASSB(C)                                                                              \
-  hipLaunchKernelGGL((k_srht_passB2<TC, C>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot, order, \
-                     bstart, p.nneeded, p.m, partial)
-  if (cpt <= 1)
-    LSQ_PASSB(1);
-  else if (cpt <= 2)
-    LSQ_PASSB(2);
-  else if (cpt <= 3)
-    LSQ_PASSB(3);
-  else
-    LSQ_PASSB(4);
-#undef LSQ_PASSB
+  dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((d + 4 * SRHT_NB * 16 - 1) / (4 * SRHT_NB * 16)));
+  hipLaunchKernelGGL((k_srht_passB_mfma<TC>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot, order,
+                     bstart, p.nneeded, p.m, partial);
   hipLaunchKernelGGL(k_srht_final, dim3((unsigned)((p.m * d + 255) / 256)), dim3(256), 0, st, partial, JS,
                      p.m, d, 1.0 / sqrt((double)p.m), SA, ldsa);
 }
