@@ -69,7 +69,48 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
+    ap.add_argument("--sweep", choices=["c2"], default=None,
+                    help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
+                         "one JSON line per run")
     return ap.parse_args()
+
+
+def sweep_c2(a):
+    """Plain FP64 PCG at n = 2^20, d = 512, kappa = 1e4, sigma = 0.01 for every sketch and sketch size:
+    sketch ms, factor ms, iterations, fused-pass GB/s and the error against the exact minimiser."""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    n, d = 1 << 20, 512
+    P = make_planted(n, d, 1e4, sigma=0.01, seed=2001)
+    A = torch.from_numpy(P["A64"]).cuda()
+    y = torch.from_numpy(P["y64"]).cuda()
+    xs = torch.from_numpy(P["x_star"]).cuda()
+    ax = torch.linalg.norm(A @ xs)
+    ctx = lsq.Context()
+    kinds = [("srht", 1), ("sjlt", 1), ("sjlt", 2), ("sjlt", 4), ("sjlt", 8), ("gaussian", 1)]
+    for kind, s in kinds:
+        for m in (2 * d, 4 * d, 8 * d):
+            desc = lsq.sketch_desc(kind, m, seed=7, s=s)
+            x = torch.zeros(d, dtype=torch.float64, device="cuda")
+            ctx.pcg_solve(A, y, desc, x, tol=a.tol, max_iter=300)  # warm-up (workspace, code objects)
+            ctx.fused_pass_timing(reset=True)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, info = ctx.pcg_solve(A, y, desc, x, tol=a.tol, max_iter=300)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            _, fms, _ = ctx.fused_pass_timing()
+            e = float(torch.linalg.norm(A @ (x - xs)) / ax)
+            print(json.dumps({"sweep": "c2", "n": n, "d": d, "kappa": 1e4, "sketch": kind, "s": s, "m": m,
+                              "time_s": round(dt, 5), "sketch_ms": round(info.t_sketch_ms, 3),
+                              "factor_ms": round(info.t_factor_ms, 3), "iter_ms": round(info.t_iter_ms, 3),
+                              "iters": info.iters, "fused_ms": round(fms, 4),
+                              "fused_gbs": round(n * d * 8 / (fms * 1e-3) / 1e9, 1) if fms > 0 else None,
+                              "rel_a_norm_error": e}), flush=True)
+    ctx.close()
 
 
 def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
@@ -107,6 +148,9 @@ def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
 
 def main():
     a = parse()
+    if a.sweep == "c2":
+        sweep_c2(a)
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "
               "built: see the design notes on row-block sharding.", file=sys.stderr)
