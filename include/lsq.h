@@ -141,6 +141,8 @@ typedef struct {
   double t_sketch_ms, t_factor_ms, t_iter_ms, t_total_ms;
   double bytes_streamed; /* algorithmic bytes of A read by the iteration passes           */
   double mu;             /* step used by lsq_ihs_solve                                     */
+  int32_t status;        /* this problem's lsq_status (lsq_pcg_solve_batched; else LSQ_OK) */
+  int32_t pad_;
 } lsq_info;
 
 /* S A (m x d) into SA (device, row-major, leading dimension ldsa >= d).  sa_dtype must be LSQ_F64.
@@ -174,15 +176,26 @@ lsq_status lsq_pcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch
 lsq_status lsq_ihs_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
                          const lsq_ihs_opts* opts, double* x, double* err_trace, lsq_info* info);
 
-/* `count` independent problems solved together: SJLT sketch, QR and (mixed) PCG of every problem run
- * inside one persistent kernel, one workgroup per problem taken from a work queue ordered by
- * decreasing n*d, the launch captured in a HIP graph and replayed.  probs, descs and xs are host
- * arrays of length count (xs[i]: device pointer to x_i, d_i entries, in: x_0, out: solution);
- * infos (host, optional).  Limits: d_i <= 256, 4 d_i <= m_i <= 1024, n_i <= 2^24.  Every problem
- * must use LSQ_SJLT; opts is shared. */
+/* `count` independent problems solved together (Section 1.2 with the sparse embedding of
+ * Section 2, the SJLT): the sketch S_i A_i, the Householder QR S_i A_i = Q_i R_i, W_i = R_i^{-1}
+ * and PCG (inside FP64 iterative refinement when opts->mixed) of every problem run inside one
+ * persistent kernel, one workgroup per problem, problems taken from a work queue ordered by
+ * decreasing n_i d_i.  The launch is captured in a HIP graph that is replayed while the batch
+ * shape (count, workspace sizes, options) stays the same.
+ *   probs, descs, xs: host arrays of length count.  xs[i]: device pointer to x_i (d_i entries;
+ *     in: x_0, zeros are a valid start; out: the solution).
+ *   Rs (optional host array, entries may be NULL): device d_i x d_i row-major buffers that
+ *     receive R_i (diag > 0).
+ *   infos (optional host array of length count): per-problem iterations, refinements, estimate
+ *     and status; t_total_ms is the wall time of the whole batch; phase times are 0.
+ * Limits: descs[i].kind == LSQ_SJLT, 1 <= d_i <= 256, d_i <= m_i <= 1024, 1 <= s_i <= min(m_i, 32),
+ * d_i <= n_i <= 2^22; opts->stop_rule 0 only, no inner_f32, no x_ref (UNSUPPORTED otherwise).
+ * The call is synchronous.  It returns LSQ_OK when every problem met the stop rule, otherwise the
+ * status of the lowest-index problem that did not (every x_i is still written, and infos tell
+ * which problems failed). */
 lsq_status lsq_pcg_solve_batched(lsq_ctx* ctx, int32_t count, const lsq_problem* probs,
                                  const lsq_sketch_desc* descs, const lsq_pcg_opts* opts,
-                                 double* const* xs, lsq_info* infos);
+                                 double* const* xs, double* const* Rs, lsq_info* infos);
 
 /* Draw-level entry points (the specification above), for bit-exact checks.
  *   lsq_draw_srht: signs (device int8, N entries, may be NULL) and rows (device int64, m entries,
@@ -205,7 +218,8 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
 
 /* Process-wide tuning parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
  * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
- * default 8).  INVALID_ARG for an unknown key or an out-of-range value. */
+ * default 8); "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute
+ * unit, else 1..65536).  INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
 
 const char* lsq_status_string(lsq_status s);

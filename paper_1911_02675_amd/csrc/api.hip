@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <string>
 #include <vector>
@@ -49,6 +50,15 @@ struct lsq_ctx {
   double fused_total_ms = 0.0, fused_last_ms = 0.0;
   int64_t fused_count = 0;
   double last_rate = -1.0;  // contraction per PCG iteration seen in the previous loop (batch sizing)
+  // batched form: private stream (capture is not possible on the legacy default stream), the
+  // instantiated graph and the launch configuration it was captured for, pinned result buffer
+  hipStream_t bst = nullptr;
+  hipGraph_t bgraph = nullptr;
+  hipGraphExec_t bexec = nullptr;
+  std::vector<unsigned char> bkey;
+  void* bhost = nullptr;
+  size_t bhost_bytes = 0;
+  hipEvent_t bev[3] = {};
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -378,6 +388,15 @@ void lsq_destroy(lsq_ctx* c) {
   }
   for (int i = 0; i < 6; ++i)
     if (c->ev[i]) (void)hipEventDestroy(c->ev[i]);
+  for (int i = 0; i < 3; ++i)
+    if (c->bev[i]) (void)hipEventDestroy(c->bev[i]);
+  if (c->bexec) (void)hipGraphExecDestroy(c->bexec);
+  if (c->bgraph) (void)hipGraphDestroy(c->bgraph);
+  if (c->bst) {
+    (void)hipStreamSynchronize(c->bst);
+    (void)hipStreamDestroy(c->bst);
+  }
+  if (c->bhost) (void)hipHostFree(c->bhost);
   if (c->ds) (void)hipFree(c->ds);
   if (c->dflags) (void)hipFree(c->dflags);
   if (c->hds) (void)hipHostFree(c->hds);
@@ -568,14 +587,17 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     info->t_total_ms = ms;
     info->bytes_streamed = passes * a_bytes;
     info->mu = 0.0;
+    info->pad_ = 0;
   }
-  if (dev_status == LSQ_ERR_RANK) return fail(LSQ_ERR_RANK, "breakdown: p^T H p <= 0");
-  if (dev_status == LSQ_ERR_NONFINITE) return fail(LSQ_ERR_NONFINITE, "non-finite value in PCG");
-  if (o->stop_rule == 0) {
+  lsq_status ret = LSQ_OK;
+  if (dev_status == LSQ_ERR_RANK) ret = fail(LSQ_ERR_RANK, "breakdown: p^T H p <= 0");
+  else if (dev_status == LSQ_ERR_NONFINITE) ret = fail(LSQ_ERR_NONFINITE, "non-finite value in PCG");
+  else if (o->stop_rule == 0) {
     const bool ok = o->mixed ? (est <= o->tol) : (c->hds->done != 0);
-    if (!ok) return fail(LSQ_ERR_NOT_CONVERGED, "iteration budget spent before the stop rule held");
+    if (!ok) ret = fail(LSQ_ERR_NOT_CONVERGED, "iteration budget spent before the stop rule held");
   }
-  return LSQ_OK;
+  if (info) info->status = ret;
+  return ret;
 }
 
 lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
@@ -686,6 +708,8 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     info->t_total_ms = ms;
     info->bytes_streamed = (double)o->iters * p->n * d * (a_f32 ? 4.0 : 8.0);
     info->mu = mu;
+    info->status = LSQ_OK;
+    info->pad_ = 0;
   }
   return LSQ_OK;
 }
@@ -741,11 +765,169 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     g_fused_groups_per_cu = (int)value;
     return LSQ_OK;
   }
+  if (k == "batched_slots") {
+    if (value < 0 || value > 65536) return fail(LSQ_ERR_INVALID_ARG, "batched_slots in [0, 65536]");
+    g_batched_slots = (int)value;
+    return LSQ_OK;
+  }
   return fail(LSQ_ERR_INVALID_ARG, "unknown tuning key: " + k);
 }
 
 lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* probs,
-                                 const lsq_sketch_desc* descs, const lsq_pcg_opts* opts,
-                                 double* const* xs, lsq_info* infos);
+                                 const lsq_sketch_desc* descs, const lsq_pcg_opts* o,
+                                 double* const* xs, double* const* Rs, lsq_info* infos) {
+  if (!c || !probs || !descs || !o || !xs)
+    return fail(LSQ_ERR_INVALID_ARG, "null context, problems, descriptors, options or xs");
+  if (count < 1) return fail(LSQ_ERR_INVALID_ARG, "count < 1");
+  if (o->max_iter < 1) return fail(LSQ_ERR_INVALID_ARG, "max_iter < 1");
+  if (!(o->tol > 0.0)) return fail(LSQ_ERR_INVALID_ARG, "tol must be > 0");
+  if (o->mixed && o->max_refine < 1) return fail(LSQ_ERR_INVALID_ARG, "max_refine < 1");
+  if (o->stop_rule != 0 || o->inner_f32 || o->x_ref)
+    return fail(LSQ_ERR_UNSUPPORTED, "batched form: stop_rule 0 only, no inner_f32, no x_ref");
+  // validation and the queue order (largest n d first)
+  std::vector<int> order(count);
+  int64_t kmax = 1, mpmax = 16, dpmax = 16;
+  for (int i = 0; i < count; ++i) {
+    const lsq_problem& p = probs[i];
+    const lsq_sketch_desc& s = descs[i];
+    const std::string at = "problem " + std::to_string(i) + ": ";
+    lsq_status st = check_problem(c, &p);
+    if (st != LSQ_OK) return fail(st, at + g_err);
+    if (!xs[i]) return fail(LSQ_ERR_INVALID_ARG, at + "null x");
+    if (s.kind != LSQ_SJLT) return fail(LSQ_ERR_UNSUPPORTED, at + "the batched form uses the SJLT");
+    if (p.d > 256) return fail(LSQ_ERR_UNSUPPORTED, at + "batched form limited to d <= 256");
+    if (p.n < p.d || p.n > (int64_t(1) << 22))
+      return fail(LSQ_ERR_UNSUPPORTED, at + "batched form needs d <= n <= 2^22");
+    if (s.m < p.d || s.m > 1024) return fail(LSQ_ERR_UNSUPPORTED, at + "batched form needs d <= m <= 1024");
+    if (s.s < 1 || s.s > 32 || s.s > s.m) return fail(LSQ_ERR_INVALID_ARG, at + "need 1 <= s <= min(m, 32)");
+    order[i] = i;
+    kmax = std::max(kmax, (int64_t)s.s * p.n);
+    mpmax = std::max(mpmax, (s.m + 15) / 16 * 16);
+    dpmax = std::max(dpmax, (p.d + 15) / 16 * 16);
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return probs[a].n * probs[a].d > probs[b].n * probs[b].d;
+  });
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev));
+  const int slots = std::min<int64_t>(count, g_batched_slots > 0 ? g_batched_slots : std::max(cus, 1));
+  // workspace (per slot) and the problem table
+  BatchArgs a;
+  memset(&a, 0, sizeof(a));
+  a.count = count;
+  a.mixed = o->mixed ? 1 : 0;
+  a.max_iter = o->max_iter;
+  a.max_refine = o->mixed ? o->max_refine : 1;
+  a.tol = o->tol;
+  a.keys_stride = kmax;
+  a.sa_stride = mpmax * dpmax;
+  a.v_stride = mpmax * 16;
+  a.r_stride = dpmax * dpmax;
+  a.last_stride = 256;
+  BatchDesc* dtab;
+  CHK(wsT(c, "b_desc", (size_t)count, &dtab));
+  CHK(wsT(c, "b_out", (size_t)count, &a.out));
+  CHK(wsT(c, "b_queue", 1, &a.queue));
+  CHK(wsT(c, "b_keys", (size_t)slots * kmax, &a.keys));
+  CHK(wsT(c, "b_sorted", (size_t)slots * kmax, &a.sorted));
+  CHK(wsT(c, "b_SA", (size_t)slots * a.sa_stride, &a.SA));
+  CHK(wsT(c, "b_V", (size_t)slots * a.v_stride, &a.V));
+  CHK(wsT(c, "b_R", (size_t)slots * a.r_stride, &a.R));
+  CHK(wsT(c, "b_W", (size_t)slots * a.r_stride, &a.W));
+  CHK(wsT(c, "b_WT", (size_t)slots * a.r_stride, &a.WT));
+  CHK(wsT(c, "b_last", (size_t)slots * a.last_stride, &a.last));
+  a.descs = dtab;
+  std::vector<BatchDesc> table(count);
+  for (int q = 0; q < count; ++q) {
+    const int i = order[q];
+    const lsq_problem& p = probs[i];
+    const lsq_sketch_desc& s = descs[i];
+    BatchDesc& t = table[q];
+    memset(&t, 0, sizeof(t));
+    t.A = p.A;
+    t.y = (const double*)p.y;
+    t.x = xs[i];
+    t.R = Rs ? Rs[i] : nullptr;
+    t.n = p.n;
+    t.lda = p.lda;
+    t.d = (int32_t)p.d;
+    t.m = (int32_t)s.m;
+    t.s = s.s;
+    t.a_f32 = p.a_dtype == LSQ_F32;
+    t.seed = s.seed;
+    t.t = s.t;
+    t.idx = i;
+  }
+  if (!c->bst) {
+    HIPCHK(hipStreamCreateWithFlags(&c->bst, hipStreamNonBlocking));
+    for (int i = 0; i < 3; ++i) HIPCHK(hipEventCreate(&c->bev[i]));
+  }
+  const size_t out_bytes = sizeof(BatchOut) * (size_t)count;
+  if (c->bhost_bytes < out_bytes) {
+    if (c->bhost) HIPCHK(hipHostFree(c->bhost));
+    c->bhost = nullptr;
+    c->bhost_bytes = 0;
+    HIPCHK(hipHostMalloc(&c->bhost, out_bytes, hipHostMallocDefault));
+    c->bhost_bytes = out_bytes;
+  }
+  // the graph depends only on the launch arguments: capture again when they change
+  std::vector<unsigned char> key(sizeof(a) + sizeof(int));
+  memcpy(key.data(), &a, sizeof(a));
+  memcpy(key.data() + sizeof(a), &slots, sizeof(int));
+  if (!c->bexec || key != c->bkey) {
+    if (c->bexec) HIPCHK(hipGraphExecDestroy(c->bexec));
+    if (c->bgraph) HIPCHK(hipGraphDestroy(c->bgraph));
+    c->bexec = nullptr;
+    c->bgraph = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->bst, hipStreamCaptureModeThreadLocal));
+    batched_launch(c->bst, a, slots);
+    const hipError_t le = hipGetLastError();
+    hipGraph_t g = nullptr;
+    const hipError_t ce = hipStreamEndCapture(c->bst, &g);
+    if (le != hipSuccess || ce != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return fail(LSQ_ERR_HIP, std::string("graph capture failed: ") +
+                                   hipGetErrorString(le != hipSuccess ? le : ce));
+    }
+    c->bgraph = g;
+    HIPCHK(hipGraphInstantiate(&c->bexec, g, nullptr, nullptr, 0));
+    c->bkey = key;
+  }
+  // order after the caller's stream, upload the table, run, copy the results back
+  HIPCHK(hipEventRecord(c->bev[0], c->st));
+  HIPCHK(hipStreamWaitEvent(c->bst, c->bev[0], 0));
+  HIPCHK(hipMemcpyAsync(dtab, table.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, c->bst));
+  HIPCHK(hipEventRecord(c->bev[1], c->bst));
+  HIPCHK(hipGraphLaunch(c->bexec, c->bst));
+  HIPCHK(hipEventRecord(c->bev[2], c->bst));
+  HIPCHK(hipMemcpyAsync(c->bhost, a.out, out_bytes, hipMemcpyDeviceToHost, c->bst));
+  HIPCHK(hipStreamSynchronize(c->bst));
+  float ms = 0.0f;
+  HIPCHK(hipEventElapsedTime(&ms, c->bev[1], c->bev[2]));
+  const BatchOut* res = (const BatchOut*)c->bhost;
+  lsq_status ret = LSQ_OK;
+  int first_bad = -1;
+  for (int i = 0; i < count; ++i) {
+    const int st = res[i].status;
+    if (infos) {
+      lsq_info& f = infos[i];
+      memset(&f, 0, sizeof(f));
+      f.iters = res[i].iters;
+      f.refinements = res[i].refinements;
+      f.est_rel_err = res[i].est;
+      f.t_total_ms = ms;
+      f.bytes_streamed = (double)(res[i].iters + res[i].refinements + 1) * (double)probs[i].n *
+                         (double)probs[i].d * (probs[i].a_dtype == LSQ_F32 ? 4.0 : 8.0);
+      f.status = st < 0 ? LSQ_ERR_HIP : st;
+    }
+    if (st != LSQ_OK && first_bad < 0) {
+      first_bad = i;
+      ret = st < 0 ? LSQ_ERR_HIP : (lsq_status)st;
+    }
+  }
+  if (ret != LSQ_OK)
+    return fail(ret, "problem " + std::to_string(first_bad) + ": " + lsq_status_string(ret));
+  return LSQ_OK;
+}
 
 }  // extern "C"

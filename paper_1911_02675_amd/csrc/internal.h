@@ -79,6 +79,7 @@ void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* 
 // ---- iter.hip -----------------------------------------------------------------------------------
 int fused_nwg(int64_t n, int64_t d);
 extern int g_fused_groups_per_cu;   // tuning: fused-pass workgroups per CU
+extern int g_batched_slots;         // tuning: batched-kernel workgroups (0 = one per CU)
 // Partial sums are reduced in two fixed-order stages: nwg rows -> REDUCE_SPLIT rows -> 1.
 constexpr int REDUCE_SPLIT = 32;
 void reduce_stage1(hipStream_t st, const double* part, int nwg, int64_t d, double* part2,
@@ -113,5 +114,36 @@ void ihs_update(hipStream_t st, int64_t d, double* x, double* xprev, const doubl
                 double beta);
 // out = sqrt(a[0] / b) style scalar helpers evaluated on the device
 void error_from_resid(hipStream_t st, const double* scal, double denom, double* out);
+
+// ---- batched form (batched.hip) ----
+// One problem of a batch, in queue order (largest n*d first).
+struct BatchDesc {
+  const void* A;
+  const double* y;
+  double* x;        // in: x_0, out: solution (d entries)
+  double* R;        // optional copy of R (d x d row-major), may be null
+  int64_t n, lda;
+  int32_t d, m, s, a_f32;
+  uint64_t seed, t;
+  int32_t idx, pad;  // position in the caller's arrays
+};
+struct BatchOut {
+  int32_t status, iters, refinements, pad;
+  double est;
+};
+// Kernel arguments: the problem table, results, queue counter, solver options and the per-slot
+// workspace (slot = workgroup index; strides in elements).
+struct BatchArgs {
+  const BatchDesc* descs;
+  BatchOut* out;
+  int* queue;
+  int count, mixed, max_iter, max_refine;
+  double tol;
+  uint32_t *keys, *sorted;
+  double *SA, *V, *R, *W, *WT, *last;
+  int64_t keys_stride, sa_stride, v_stride, r_stride, last_stride;
+};
+// Resets the queue and the results, then launches the persistent kernel with `slots` workgroups.
+void batched_launch(hipStream_t st, const BatchArgs& a, int slots);
 
 }  // namespace lsq

@@ -48,7 +48,8 @@ class IhsOpts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("est_rel_err", C.c_double),
                 ("t_sketch_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_iter_ms", C.c_double),
-                ("t_total_ms", C.c_double), ("bytes_streamed", C.c_double), ("mu", C.c_double)]
+                ("t_total_ms", C.c_double), ("bytes_streamed", C.c_double), ("mu", C.c_double),
+                ("status", C.c_int32), ("pad_", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -83,7 +84,8 @@ def load():
         "lsq_ihs_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(IhsOpts), P, P,
                            C.POINTER(Info)], I32),
         "lsq_pcg_solve_batched": ([P, I32, C.POINTER(Problem), C.POINTER(SketchDesc),
-                                   C.POINTER(PcgOpts), C.POINTER(C.c_void_p), C.POINTER(Info)], I32),
+                                   C.POINTER(PcgOpts), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
+                                   C.POINTER(Info)], I32),
         "lsq_draw_srht": ([P, U64, U64, I64, I64, P, P], I32),
         "lsq_draw_sjlt": ([P, U64, U64, I64, I64, I32, P, P], I32),
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
@@ -210,15 +212,23 @@ class Context:
                                       _ptr(err_trace), C.byref(info)))
         return info
 
-    def pcg_solve_batched(self, As, ys, descs, xs, tol=1e-10, max_iter=200, mixed=1, max_refine=8):
+    def pcg_solve_batched(self, As, ys, descs, xs, tol=1e-10, max_iter=200, mixed=1, max_refine=8,
+                          Rs=None, raise_on_error=True):
+        """Solve len(As) independent problems in one persistent launch (SJLT descriptors).  Returns
+        (status, list of Info); xs (and Rs entries that are not None) are written on the device."""
         n = len(As)
         probs = (Problem * n)(*[problem(A, y) for A, y in zip(As, ys)])
         ds = (SketchDesc * n)(*descs)
         xp = (C.c_void_p * n)(*[x.data_ptr() for x in xs])
+        rp = None
+        if Rs is not None:
+            rp = (C.c_void_p * n)(*[None if R is None else R.data_ptr() for R in Rs])
         infos = (Info * n)()
         o = PcgOpts(tol, max_iter, 0, mixed, max_refine, 0, 8, None)
-        _check(self.lib.lsq_pcg_solve_batched(self.h, n, probs, ds, C.byref(o), xp, infos))
-        return list(infos)
+        st = self.lib.lsq_pcg_solve_batched(self.h, n, probs, ds, C.byref(o), xp, rp, infos)
+        if raise_on_error:
+            _check(st)
+        return st, list(infos)
 
     def draw_srht(self, seed, t, N, m, signs=None, rows=None):
         _check(self.lib.lsq_draw_srht(self.h, seed, t, N, m, _ptr(signs), _ptr(rows)))

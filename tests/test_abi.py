@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lsq.SketchDesc) == 40
     assert ctypes.sizeof(lsq.PcgOpts) == 40
     assert ctypes.sizeof(lsq.IhsOpts) == 40
-    assert ctypes.sizeof(lsq.Info) == 64
+    assert ctypes.sizeof(lsq.Info) == 72
 
 
 def test_null_arguments_rejected_without_device():
@@ -58,7 +58,10 @@ def test_null_arguments_rejected_without_device():
     assert lib.lsq_pcg_solve(None, None, None, None, None, None, None) == lsq.LSQ_ERR_INVALID_ARG
     assert lib.lsq_ihs_solve(None, None, None, None, None, None, None) == lsq.LSQ_ERR_INVALID_ARG
     assert lib.lsq_factor(None, None, 4, 4, 4, None, None) == lsq.LSQ_ERR_INVALID_ARG
+    assert lib.lsq_pcg_solve_batched(None, 1, None, None, None, None, None, None) == lsq.LSQ_ERR_INVALID_ARG
     assert b"null" in lib.lsq_last_error()
+    assert lib.lsq_tune(b"batched_slots", -1) == lsq.LSQ_ERR_INVALID_ARG
+    assert lib.lsq_tune(b"batched_slots", 0) == lsq.LSQ_OK
 
 
 def test_c_header_compiles_standalone(tmp_path):
@@ -66,7 +69,7 @@ def test_c_header_compiles_standalone(tmp_path):
     src = tmp_path / "t.c"
     src.write_text('#include "lsq.h"\nint main(void){ lsq_problem p; lsq_sketch_desc s; lsq_pcg_opts o;'
                    ' lsq_ihs_opts i; lsq_info f; (void)p;(void)s;(void)o;(void)i;(void)f;'
-                   ' return (int)sizeof(lsq_problem) - 48; }\n')
+                   ' return (int)sizeof(lsq_problem) - 48 + (int)sizeof(lsq_info) - 72; }\n')
     import subprocess
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                         str(src), "-o", str(tmp_path / "t")], capture_output=True, text=True)
