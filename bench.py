@@ -69,9 +69,14 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
-    ap.add_argument("--sweep", choices=["c2"], default=None,
+    ap.add_argument("--sweep", choices=["c2", "c4"], default=None,
                     help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
+                         "c4: 512 uneven problems, batched form vs a per-problem loop; "
                          "one JSON line per run")
+    ap.add_argument("--count", type=int, default=512, help="c4: number of problems")
+    ap.add_argument("--slots", default="0", help="c4: comma list of batched workgroup counts to time "
+                                                 "(0 = one per compute unit)")
+    ap.add_argument("--no-loop", action="store_true", help="c4: skip the per-problem loop")
     return ap.parse_args()
 
 
@@ -113,6 +118,155 @@ def sweep_c2(a):
     ctx.close()
 
 
+def gen_c4(count, seed=4001):
+    """The batched workload on the device: n_i ~ U{4096..65536} (even), d_i ~ U{16..256},
+    log10 kappa_i ~ U[2, 6], sigma = 0.01, geometric singular values, Haar factors.  Planted as in
+    synth.make_planted (rows in +- pairs, noise orthogonal to the range of the stored FP32 matrix),
+    so x*_i is exact; rows are stored at a stride of roundup(d_i, 4) floats (16-byte rows)."""
+    import math
+
+    import torch
+    rng = np.random.default_rng(seed)
+    ns = 2 * (rng.integers(4096, 65537, count) // 2)
+    ds = rng.integers(16, 257, count)
+    lk = rng.uniform(2.0, 6.0, count)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    out = []
+    for i in range(count):
+        n, d, kappa = int(ns[i]), int(ds[i]), 10.0 ** lk[i]
+        h = n // 2
+        Z = torch.randn(h, d, dtype=torch.float64, device="cuda", generator=g)
+        for _ in range(2):  # orthonormal columns (Cholesky QR, twice)
+            L = torch.linalg.cholesky(Z.T @ Z)
+            Z = torch.linalg.solve_triangular(L, Z.T.contiguous(), upper=False).T.contiguous()
+        V, Rv = torch.linalg.qr(torch.randn(d, d, dtype=torch.float64, device="cuda", generator=g))
+        V = V * torch.sign(torch.diagonal(Rv))[None, :]
+        sv = kappa ** (-torch.arange(d, dtype=torch.float64, device="cuda") / max(d - 1, 1))
+        B = ((Z * sv[None, :]) @ V.T / math.sqrt(2.0)).float()
+        D = torch.where(torch.rand(h, dtype=torch.float64, device="cuda", generator=g) < 0.5, -1.0, 1.0)
+        lda = (d + 3) // 4 * 4
+        buf = torch.zeros(n, lda, dtype=torch.float32, device="cuda")
+        buf[:h, :d] = B
+        buf[h:, :d] = B * D[:, None].float()
+        A = buf[:, :d]
+        xs = torch.randn(d, dtype=torch.float64, device="cuda", generator=g)
+        w = 0.01 * torch.randn(h, dtype=torch.float64, device="cuda", generator=g)
+        y = A.double() @ xs
+        y[:h] += w
+        y[h:] -= D * w
+        out.append(dict(n=n, d=d, kappa=kappa, A=A, buf=buf, y=y, xs=xs))
+        del Z, V, B, D
+    torch.cuda.synchronize()
+    return out
+
+
+def sweep_c4(a):
+    """The batched form (one persistent launch per sweep of all problems) against a loop of
+    single-problem solves, FP32 A with FP64 refinement to 1e-10, SJLT m = 4 d_i, s = 4."""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    t0 = time.time()
+    probs = gen_c4(a.count)
+    log(f"[c4] generated {a.count} problems in {time.time() - t0:.1f} s; "
+        f"sum n d = {sum(p['n'] * p['d'] for p in probs):.3e}")
+    X = torch.zeros(sum(p["d"] for p in probs), dtype=torch.float64, device="cuda")
+    xs, off = [], 0
+    for p in probs:
+        xs.append(X[off:off + p["d"]])
+        off += p["d"]
+    descs = [lsq.sketch_desc("sjlt", 4 * p["d"], seed=7000 + i, s=4) for i, p in enumerate(probs)]
+    As, ys = [p["A"] for p in probs], [p["y"] for p in probs]
+    ctx = lsq.Context()
+
+    def errors():
+        e = []
+        for p, x in zip(probs, xs):
+            A64 = p["A"].double()
+            e.append(float(torch.linalg.norm(A64 @ (x - p["xs"])) / torch.linalg.norm(A64 @ p["xs"])))
+        return e
+
+    def batch():
+        X.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st, infos = ctx.pcg_solve_batched(As, ys, descs, xs, tol=a.tol, max_iter=300, mixed=1,
+                                          max_refine=10, raise_on_error=False)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st, infos
+
+    results = []
+    for slots in [int(v) for v in a.slots.split(",")]:
+        lsq.tune("batched_slots", slots)
+        for _ in range(a.warmup):
+            batch()
+        times = []
+        for _ in range(a.steps):
+            dt, st, infos = batch()
+            times.append(dt)
+        e = errors()
+        dt = min(times)
+        kern_ms = infos[0].t_total_ms
+        # algorithmic HBM bytes of one sweep: every pass over A (PCG iterations and residual passes,
+        # the latter also read y), the sketch's s reads of A, and the solution writes
+        byt = 0.0
+        for p, inf in zip(probs, infos):
+            passes = inf.iters + inf.refinements + 1
+            byt += passes * p["n"] * p["d"] * 4.0 + (inf.refinements + 1) * p["n"] * 8.0
+            byt += 4 * p["n"] * p["d"] * 4.0
+        # schedule: per-problem durations from the device clock, per-workgroup bandwidth
+        dur = np.array([i.t_sketch_ms + i.t_factor_ms + i.t_iter_ms for i in infos])
+        pb = np.array([(i.iters + i.refinements + 1 + 4) * p["n"] * p["d"] * 4.0
+                       for p, i in zip(probs, infos)])
+        wg_gbs = pb / (dur * 1e-3) / 1e9
+        big = int(np.argmax(dur))
+        sched = {"max_problem_ms": round(float(dur[big]), 3),
+                 "max_problem_n_d": [probs[big]["n"], probs[big]["d"]],
+                 "last_start_ms": round(max(i.t_start_ms for i in infos), 3),
+                 "wg_gbs_p10_p50_p90": [round(float(v), 1) for v in np.percentile(wg_gbs, [10, 50, 90])],
+                 "phase_ms_sum": {"sketch": round(sum(i.t_sketch_ms for i in infos), 2),
+                                  "factor": round(sum(i.t_factor_ms for i in infos), 2),
+                                  "iterate": round(sum(i.t_iter_ms for i in infos), 2)}}
+        rec = {"sweep": "c4", "count": a.count, "slots": slots, "status": st, "schedule": sched,
+               "failed": sum(1 for i in infos if i.status != 0),
+               "batch_s": round(dt, 5), "kernel_ms": round(kern_ms, 3),
+               "solves_per_s": round(a.count / dt, 1),
+               "agg_gbs": round(byt / (kern_ms * 1e-3) / 1e9, 1),
+               "hbm_frac": round(byt / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+               "bytes": byt, "iters_mean": round(float(np.mean([i.iters for i in infos])), 2),
+               "iters_max": max(i.iters for i in infos),
+               "refinements_mean": round(float(np.mean([i.refinements for i in infos])), 2),
+               "max_rel_a_norm_error": max(e)}
+        log(f"[c4] slots {slots}: {dt * 1e3:.1f} ms per sweep ({a.count / dt:.0f} solves/s), kernel "
+            f"{kern_ms:.1f} ms, {rec['agg_gbs']} GB/s, max e_A {max(e):.2e}, failed {rec['failed']}; "
+            f"schedule {json.dumps(sched)}")
+        results.append(rec)
+    lsq.tune("batched_slots", 0)
+    best = min(results, key=lambda r: r["batch_s"])
+    loop = None
+    if not a.no_loop:
+        X.zero_()  # x_0 = 0 (the stop rule is relative to the error of x_0)
+        for i in range(min(4, a.count)):  # warm-up: code objects and workspace
+            ctx.pcg_solve(As[i], ys[i], descs[i], xs[i], tol=a.tol, max_iter=300, mixed=1, max_refine=10)
+        X.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for i in range(a.count):
+            ctx.pcg_solve(As[i], ys[i], descs[i], xs[i], tol=a.tol, max_iter=300, mixed=1, max_refine=10,
+                          raise_on_error=False)
+        torch.cuda.synchronize()
+        tl = time.perf_counter() - t
+        e = errors()
+        loop = {"loop_s": round(tl, 4), "loop_solves_per_s": round(a.count / tl, 1),
+                "loop_max_rel_a_norm_error": max(e)}
+        log(f"[c4] per-problem loop: {tl:.2f} s ({a.count / tl:.0f} solves/s), max e_A {max(e):.2e}")
+    ctx.close()
+    print(json.dumps({"sweep": "c4", "best": best, "all": results, "loop": loop,
+                      "speedup_vs_loop": round(loop["loop_s"] / best["batch_s"], 2) if loop else None}),
+          flush=True)
+
+
 def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
     """The CPU oracle as it stands, on a bounded sample of the same workload: its sketch of the first
     `rows` rows (scaled linearly to n), its Householder QR of the m x d sketch, and one of its PCG
@@ -150,6 +304,9 @@ def main():
     a = parse()
     if a.sweep == "c2":
         sweep_c2(a)
+        return
+    if a.sweep == "c4":
+        sweep_c4(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "

@@ -143,6 +143,7 @@ typedef struct {
   double mu;             /* step used by lsq_ihs_solve                                     */
   int32_t status;        /* this problem's lsq_status (lsq_pcg_solve_batched; else LSQ_OK) */
   int32_t pad_;
+  double t_start_ms;     /* lsq_pcg_solve_batched: start of this problem within the launch   */
 } lsq_info;
 
 /* S A (m x d) into SA (device, row-major, leading dimension ldsa >= d).  sa_dtype must be LSQ_F64.
@@ -166,7 +167,9 @@ lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, i
                           const double* v, double* w, double* scal);
 
 /* PCG with a fixed sketch (Section 1.2): x (device, d) holds x_0 on entry (zeros are a valid start)
- * and the solution on exit.  err_trace (device, optional) receives max_iter+1 values per inner solve
+ * and the solution on exit.  The stop rule measures the error relative to that of x_0 (for x_0 = 0,
+ * relative to ||A x*||): a warm start already near x* asks for a correspondingly smaller error and
+ * can end in LSQ_ERR_NOT_CONVERGED at the rounding floor.  err_trace (device, optional) receives max_iter+1 values per inner solve
  * (see lsq_pcg_opts.x_ref); info (host, optional). */
 lsq_status lsq_pcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
                          const lsq_pcg_opts* opts, double* x, double* err_trace, lsq_info* info);
@@ -186,8 +189,9 @@ lsq_status lsq_ihs_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch
  *     in: x_0, zeros are a valid start; out: the solution).
  *   Rs (optional host array, entries may be NULL): device d_i x d_i row-major buffers that
  *     receive R_i (diag > 0).
- *   infos (optional host array of length count): per-problem iterations, refinements, estimate
- *     and status; t_total_ms is the wall time of the whole batch; phase times are 0.
+ *   infos (optional host array of length count): per-problem iterations, refinements, estimate,
+ *     status and phase times (sketch, factor including W, iterations; from the device clock);
+ *     t_total_ms is the wall time of the whole batch and t_start_ms the problem's start within it.
  * Limits: descs[i].kind == LSQ_SJLT, 1 <= d_i <= 256, d_i <= m_i <= 1024, 1 <= s_i <= min(m_i, 32),
  * d_i <= n_i <= 2^22; opts->stop_rule 0 only, no inner_f32, no x_ref (UNSUPPORTED otherwise).
  * The call is synchronous.  It returns LSQ_OK when every problem met the stop rule, otherwise the

@@ -588,6 +588,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     info->bytes_streamed = passes * a_bytes;
     info->mu = 0.0;
     info->pad_ = 0;
+    info->t_start_ms = 0.0;
   }
   lsq_status ret = LSQ_OK;
   if (dev_status == LSQ_ERR_RANK) ret = fail(LSQ_ERR_RANK, "breakdown: p^T H p <= 0");
@@ -710,6 +711,7 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     info->mu = mu;
     info->status = LSQ_OK;
     info->pad_ = 0;
+    info->t_start_ms = 0.0;
   }
   return LSQ_OK;
 }
@@ -904,7 +906,12 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* p
   HIPCHK(hipStreamSynchronize(c->bst));
   float ms = 0.0f;
   HIPCHK(hipEventElapsedTime(&ms, c->bev[1], c->bev[2]));
+  int clk_khz = 0;
+  HIPCHK(hipDeviceGetAttribute(&clk_khz, hipDeviceAttributeWallClockRate, c->dev));
+  const double tick_ms = clk_khz > 0 ? 1.0 / clk_khz : 0.0;
   const BatchOut* res = (const BatchOut*)c->bhost;
+  uint64_t t0_min = ~0ull;
+  for (int i = 0; i < count; ++i) t0_min = std::min(t0_min, res[i].t_start);
   lsq_status ret = LSQ_OK;
   int first_bad = -1;
   for (int i = 0; i < count; ++i) {
@@ -915,7 +922,11 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* p
       f.iters = res[i].iters;
       f.refinements = res[i].refinements;
       f.est_rel_err = res[i].est;
+      f.t_sketch_ms = (double)(res[i].t_sketch - res[i].t_start) * tick_ms;
+      f.t_factor_ms = (double)(res[i].t_factor - res[i].t_sketch) * tick_ms;
+      f.t_iter_ms = (double)(res[i].t_end - res[i].t_factor) * tick_ms;
       f.t_total_ms = ms;
+      f.t_start_ms = (double)(res[i].t_start - t0_min) * tick_ms;
       f.bytes_streamed = (double)(res[i].iters + res[i].refinements + 1) * (double)probs[i].n *
                          (double)probs[i].d * (probs[i].a_dtype == LSQ_F32 ? 4.0 : 8.0);
       f.status = st < 0 ? LSQ_ERR_HIP : st;

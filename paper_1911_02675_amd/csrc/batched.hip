@@ -94,6 +94,40 @@ __device__ __forceinline__ lsq_b_d4 mfma16(double a, double b, lsq_b_d4 c) {
 }
 
 // ---------------------------------------------------------------------------------------------
+// Sums over aligned groups of G lanes, every lane of a group receiving the group's sum, without
+// LDS: DPP quad permutations (xor 1, xor 2) and mirrors (8- and 16-lane groups, whose halves are
+// already uniform), then the gfx950 permlane swaps across 16-lane rows (xor 16) and wave halves
+// (xor 32).  Every lane adds the same two operands, so all lanes of a group hold identical bits.
+// All 64 lanes must be active.
+// ---------------------------------------------------------------------------------------------
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double xor16_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+template <int G>
+__device__ __forceinline__ double grp_sum(double v) {
+  if (G >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_d<0x140>(v); // row_mirror
+  if (G >= 32) v = xor16_sum(v);
+  if (G >= 64) v = xor32_sum(v);
+  return v;
+}
+
+// ---------------------------------------------------------------------------------------------
 // Loads of VEC contiguous elements of a row of A.  The vector form needs 16-byte alignment of the
 // row start (A aligned, lda a multiple of VEC).  A chunk that straddles column d reads into the
 // row's padding, which exists for every row but the last; the last row is therefore read from a
@@ -300,7 +334,7 @@ LSQ_NOINLINE __device__ void b_sjlt_reduce(const TA LSQ_G* __restrict__ A, int64
                                            const uint32_t LSQ_G* __restrict__ sorted,
                                            double LSQ_G* __restrict__ SA) {
   constexpr int NG = BT / G;
-  constexpr int U = NV == 1 ? 4 : 2;
+  constexpr int U = NV >= 4 ? 1 : 4 / NV;
   const double scale = 1.0 / sqrt((double)s);
   const int tid = b_tid();
   const int gl = tid % G, g = tid / G;
@@ -584,55 +618,116 @@ __device__ __forceinline__ void b_fused(const TA LSQ_G* __restrict__ A, int64_t 
                                         double* scal, double* red) {
   constexpr int RPW = 64 / G;    // rows per wave per step
   constexpr int RS = BNW * RPW;  // rows per workgroup step
-  constexpr int U = NV == 1 ? 8 : (NV == 2 ? 4 : 2);
+  constexpr int U = NV >= 8 ? 1 : 8 / NV;  // rows in flight per lane group (U NV loads per lane)
+  (void)last;
   const int tid = b_tid(), lane = tid & 63, wv = tid >> 6;
   const int gl = lane % G, rw = lane / G;
   double pv[NV][VEC], acc[NV][VEC];
   int col[NV];
-  bool cok[NV];
+  bool em[NV][VEC];
 #pragma unroll
   for (int i = 0; i < NV; ++i) {
-    col[i] = (gl + G * i) * VEC;
-    cok[i] = col[i] < d;
+    const int c = (gl + G * i) * VEC;
+    col[i] = c < d ? c : 0;  // chunks past d read the row start and are masked
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
-      pv[i][e] = col[i] + e < d ? v[col[i] + e] : 0.0;
+      em[i][e] = c + e < d;
+      pv[i][e] = em[i][e] ? v[c + e] : 0.0;
       acc[i][e] = 0.0;
     }
   }
   double ss = 0.0;
-  const int64_t base = (int64_t)wv * RPW + rw;
-  const int64_t nlast = n - 1;
-  for (int64_t r0 = 0; r0 < n; r0 += (int64_t)U * RS) {
+  // rows [0, nm) are read with whole chunks; when d is not a multiple of VEC the last row's
+  // straddling chunk would run past the matrix, so that row is read element-wise at the end
+  const int nm = (VEC > 1 && d % VEC != 0) ? (int)n - 1 : (int)n;
+  const int row0 = wv * RPW + rw;
+  const int64_t kstep = (int64_t)RS * lda;
+  // one row of the lane group: masked chunk values -> q -> accumulators
+  auto row = [&](TA (&ak)[NV][VEC], double yk, bool ok) {
+    double q = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        ak[i][e] = em[i][e] ? ak[i][e] : (TA)0;
+        q = fma((double)ak[i][e], pv[i][e], q);
+      }
+    q = grp_sum<G>(q);
+    if (MODE == 1) q = yk - q;
+    q = ok ? q : 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[i][e] = fma(q, (double)ak[i][e], acc[i][e]);
+    if (gl == 0) ss = fma(q, q, ss);
+  };
+  // Whole blocks of U * RS rows, loads rotated through the registers: as soon as row k of a block
+  // is consumed its registers receive row k of the next block, so every lane keeps about U loads
+  // in flight while it computes (the last block re-reads itself instead of running past the end).
+  const int nblk = nm / (U * RS);
+  const int64_t bstep = (int64_t)U * RS * lda;
+  if (nblk > 0) {
     TA a[U][NV][VEC];
-    double yv[U];
+    double yk[U];
+    const TA LSQ_G* pr = A + (int64_t)row0 * lda;
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int64_t r = r0 + (int64_t)k * RS + base;
-      const bool rok = r < n;
-      const int64_t rr = rok ? r : 0;
 #pragma unroll
-      for (int i = 0; i < NV; ++i)
-        load_chunk<TA, VEC>(A, lda, rr, nlast, last, col[i], d, rok && cok[i], a[k][i]);
-      yv[k] = MODE == 1 ? y[rr] : 0.0;  // rr is a valid row; masked below
+      for (int i = 0; i < NV; ++i) RowLoad<TA, VEC>::get(pr + k * kstep + col[i], a[k][i]);
+      yk[k] = MODE == 1 ? y[row0 + k * RS] : 0.0;
     }
+    for (int b = 0; b < nblk; ++b) {
+      const bool more = b + 1 < nblk;
+      const TA LSQ_G* pn = more ? pr + bstep : pr;
+      const int yn = (more ? b + 1 : b) * U * RS + row0;
+#pragma unroll
+      for (int k = 0; k < U; ++k) {
+        row(a[k], yk[k], true);
+#pragma unroll
+        for (int i = 0; i < NV; ++i) RowLoad<TA, VEC>::get(pn + k * kstep + col[i], a[k][i]);
+        yk[k] = MODE == 1 ? y[yn + k * RS] : 0.0;
+      }
+      pr = pn;
+    }
+  }
+  // the remaining rows, U row steps at a time with masks (out-of-range rows read row 0)
+  for (int r0 = nblk * U * RS; r0 < nm; r0 += U * RS) {
+    TA a[U][NV][VEC];
+    double yk[U];
+    bool ok[U];
 #pragma unroll
     for (int k = 0; k < U; ++k) {
-      const int64_t r = r0 + (int64_t)k * RS + base;
-      double q = 0.0;
+      const int r = r0 + k * RS + row0;
+      ok[k] = r < nm;
+      const TA LSQ_G* pk = A + (int64_t)(ok[k] ? r : 0) * lda;
 #pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) q = fma((double)a[k][i][e], pv[i][e], q);
-      q = group_sum<G>(q);
-      if (MODE == 1) q = yv[k] - q;
-      q = r < n ? q : 0.0;
-#pragma unroll
-      for (int i = 0; i < NV; ++i)
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) acc[i][e] = fma(q, (double)a[k][i][e], acc[i][e]);
-      if (gl == 0) ss = fma(q, q, ss);
+      for (int i = 0; i < NV; ++i) RowLoad<TA, VEC>::get(pk + col[i], a[k][i]);
+      yk[k] = MODE == 1 ? y[ok[k] ? r : 0] : 0.0;
     }
+#pragma unroll
+    for (int k = 0; k < U; ++k) row(a[k], yk[k], ok[k]);
+  }
+  if (nm < n) {
+    // last row by the first lane group of wave 0, element loads
+    const bool act = wv == 0 && rw == 0;
+    const TA LSQ_G* pl = A + (n - 1) * lda;
+    TA a[NV][VEC];
+    double q = 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        a[i][e] = (act && em[i][e]) ? pl[col[i] + e] : (TA)0;
+        q = fma((double)a[i][e], pv[i][e], q);
+      }
+    q = grp_sum<G>(q);
+    if (MODE == 1) q = (act ? y[n - 1] : 0.0) - q;
+    q = act ? q : 0.0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[i][e] = fma(q, (double)a[i][e], acc[i][e]);
+    if (gl == 0) ss = fma(q, q, ss);
   }
   // lanes with equal gl hold the same columns: fold them, then one row of LDS per wave
 #pragma unroll
@@ -647,7 +742,7 @@ __device__ __forceinline__ void b_fused(const TA LSQ_G* __restrict__ A, int64_t 
     for (int i = 0; i < NV; ++i)
 #pragma unroll
       for (int e = 0; e < VEC; ++e)
-        if (col[i] + e < d) red[wv * B_VR + col[i] + e] = acc[i][e];
+        if (em[i][e]) red[wv * B_VR + (gl + G * i) * VEC + e] = acc[i][e];
   }
   if (lane == 0) red[wv * B_VR + B_DMAX + 1] = ss;
   __syncthreads();
@@ -820,18 +915,20 @@ struct Map {
 };
 
 __device__ __forceinline__ Map choose_map(int a_f32, const void* A, int64_t lda, int d) {
+  // few lanes per row (cheap row sums, all on the VALU) and up to 2 (FP32) or 4 (FP64) chunks per
+  // lane, which keeps the row data, the accumulators and v in registers
   const bool al = ((uintptr_t)A % 16) == 0;
   Map mp;
   if (a_f32 && al && lda % 4 == 0) {
     const int c = (d + 3) / 4;
     mp.vec = 4;
-    mp.nv = 1;
-    mp.g = c <= 4 ? 4 : (c <= 8 ? 8 : (c <= 16 ? 16 : (c <= 32 ? 32 : 64)));
+    mp.g = c <= 4 ? 4 : (c <= 8 ? 8 : (c <= 32 ? 16 : 32));
+    mp.nv = c <= 16 ? 1 : 2;
   } else if (!a_f32 && al && lda % 2 == 0) {
     const int c = (d + 1) / 2;
     mp.vec = 2;
-    mp.nv = c > 64 ? 2 : 1;
-    mp.g = c <= 8 ? 8 : (c <= 16 ? 16 : (c <= 32 ? 32 : 64));
+    mp.g = c <= 8 ? 8 : (c <= 64 ? 16 : 32);
+    mp.nv = c <= 16 ? 1 : (c <= 32 ? 2 : 4);
   } else {
     mp.vec = 1;
     mp.g = 64;
@@ -840,40 +937,41 @@ __device__ __forceinline__ Map choose_map(int a_f32, const void* A, int64_t lda,
   return mp;
 }
 
-#define LSQ_B_FOR_MAPS(TA, MACRO)   \
-  if constexpr (sizeof(TA) == 4) { \
-    if (mapv.vec == 4) {           \
-      if (mapv.g == 4)             \
-        MACRO(TA, 4, 4, 1)         \
-      else if (mapv.g == 8)        \
-        MACRO(TA, 4, 8, 1)         \
-      else if (mapv.g == 16)       \
-        MACRO(TA, 4, 16, 1)        \
-      else if (mapv.g == 32)       \
-        MACRO(TA, 4, 32, 1)        \
-      else                         \
-        MACRO(TA, 4, 64, 1)        \
-    } else {                       \
-      MACRO(TA, 1, 64, 4)          \
-    }                              \
-  } else {                         \
-    if (mapv.vec == 2) {           \
-      if (mapv.g == 8)             \
-        MACRO(TA, 2, 8, 1)         \
-      else if (mapv.g == 16)       \
-        MACRO(TA, 2, 16, 1)        \
-      else if (mapv.g == 32)       \
-        MACRO(TA, 2, 32, 1)        \
-      else if (mapv.nv == 1)       \
-        MACRO(TA, 2, 64, 1)        \
-      else                         \
-        MACRO(TA, 2, 64, 2)        \
-    } else {                       \
-      MACRO(TA, 1, 64, 4)          \
-    }                              \
+#define LSQ_B_FOR_MAPS(TA, MACRO)                  \
+  if constexpr (sizeof(TA) == 4) {                \
+    if (mapv.vec == 4) {                          \
+      if (mapv.g == 4)                            \
+        MACRO(TA, 4, 4, 1)                        \
+      else if (mapv.g == 8)                       \
+        MACRO(TA, 4, 8, 1)                        \
+      else if (mapv.g == 16 && mapv.nv == 1)      \
+        MACRO(TA, 4, 16, 1)                       \
+      else if (mapv.g == 16)                      \
+        MACRO(TA, 4, 16, 2)                       \
+      else                                        \
+        MACRO(TA, 4, 32, 2)                       \
+    } else {                                      \
+      MACRO(TA, 1, 64, 4)                         \
+    }                                             \
+  } else {                                        \
+    if (mapv.vec == 2) {                          \
+      if (mapv.g == 8)                            \
+        MACRO(TA, 2, 8, 1)                        \
+      else if (mapv.g == 16 && mapv.nv == 1)      \
+        MACRO(TA, 2, 16, 1)                       \
+      else if (mapv.g == 16 && mapv.nv == 2)      \
+        MACRO(TA, 2, 16, 2)                       \
+      else if (mapv.g == 16)                      \
+        MACRO(TA, 2, 16, 4)                       \
+      else                                        \
+        MACRO(TA, 2, 32, 4)                       \
+    } else {                                      \
+      MACRO(TA, 1, 64, 4)                         \
+    }                                             \
   }
 
 __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
+  const uint64_t t_start = wall_clock64();
   const BatchDesc pd = a.descs[q];
   const int d = pd.d, m = pd.m;
   const int dp = (d + 15) & ~15, mp = (m + 15) & ~15;
@@ -898,6 +996,7 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
   }
   __syncthreads();
   const Map mapv = choose_map(pd.a_f32, pd.A, pd.lda, d);
+  if (b_tid() == 0) out->t_start = t_start;
   // 1. sketch
   const int drew = b_sort(pd.n, m, pd.s, pd.seed, pd.t, keys, sorted);
 #define LSQ_B_RED(T_, V_, G_, N_) \
@@ -909,6 +1008,7 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
     LSQ_B_FOR_MAPS(double, LSQ_B_RED)
   }
 #undef LSQ_B_RED
+  if (b_tid() == 0) out->t_sketch = wall_clock64();
   // 2. factor
   b_qr(SA, m, d, mp, dp, V);
   const int full_rank = b_finish_r(SA, d, dp, R, (double LSQ_G*)pd.R);
@@ -919,12 +1019,14 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
       out->refinements = 0;
       out->pad = 0;
       out->est = 0.0;
+      out->t_factor = out->t_end = wall_clock64();
     }
     __syncthreads();
     return;
   }
   // 3. W = R^{-1};  4. iterate
   b_trinv(R, dp, W, WT);
+  if (b_tid() == 0) out->t_factor = wall_clock64();
   PcgArgs pa;
   pa.n = pd.n;
   pa.lda = pd.lda;
@@ -943,6 +1045,7 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
     LSQ_B_FOR_MAPS(double, LSQ_B_PCG)
   }
 #undef LSQ_B_PCG
+  if (b_tid() == 0) out->t_end = wall_clock64();
 }
 
 }  // namespace
@@ -970,6 +1073,7 @@ __global__ void k_batch_reset(int* queue, BatchOut* out, int count) {
     out[i].refinements = 0;
     out[i].pad = 0;
     out[i].est = 0.0;
+    out[i].t_start = out[i].t_sketch = out[i].t_factor = out[i].t_end = 0;
   }
 }
 

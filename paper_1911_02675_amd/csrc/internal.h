@@ -130,6 +130,7 @@ struct BatchDesc {
 struct BatchOut {
   int32_t status, iters, refinements, pad;
   double est;
+  uint64_t t_start, t_sketch, t_factor, t_end;  // device wall clock at the phase boundaries
 };
 // Kernel arguments: the problem table, results, queue counter, solver options and the per-slot
 // workspace (slot = workgroup index; strides in elements).

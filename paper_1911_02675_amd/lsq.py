@@ -49,7 +49,7 @@ class Info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("refinements", C.c_int32), ("est_rel_err", C.c_double),
                 ("t_sketch_ms", C.c_double), ("t_factor_ms", C.c_double), ("t_iter_ms", C.c_double),
                 ("t_total_ms", C.c_double), ("bytes_streamed", C.c_double), ("mu", C.c_double),
-                ("status", C.c_int32), ("pad_", C.c_int32)]
+                ("status", C.c_int32), ("pad_", C.c_int32), ("t_start_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

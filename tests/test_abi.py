@@ -47,7 +47,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(lsq.SketchDesc) == 40
     assert ctypes.sizeof(lsq.PcgOpts) == 40
     assert ctypes.sizeof(lsq.IhsOpts) == 40
-    assert ctypes.sizeof(lsq.Info) == 72
+    assert ctypes.sizeof(lsq.Info) == 80
 
 
 def test_null_arguments_rejected_without_device():
@@ -69,7 +69,7 @@ def test_c_header_compiles_standalone(tmp_path):
     src = tmp_path / "t.c"
     src.write_text('#include "lsq.h"\nint main(void){ lsq_problem p; lsq_sketch_desc s; lsq_pcg_opts o;'
                    ' lsq_ihs_opts i; lsq_info f; (void)p;(void)s;(void)o;(void)i;(void)f;'
-                   ' return (int)sizeof(lsq_problem) - 48 + (int)sizeof(lsq_info) - 72; }\n')
+                   ' return (int)sizeof(lsq_problem) - 48 + (int)sizeof(lsq_info) - 80; }\n')
     import subprocess
     r = subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                         str(src), "-o", str(tmp_path / "t")], capture_output=True, text=True)
