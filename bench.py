@@ -69,14 +69,17 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
-    ap.add_argument("--sweep", choices=["c2", "c4"], default=None,
+    ap.add_argument("--sweep", choices=["c2", "c4", "c5"], default=None,
                     help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
                          "c4: 512 uneven problems, batched form vs a per-problem loop; "
+                         "c5: refreshed IHS / Polyak-IHS statistics over 32 sketch seeds vs closed forms; "
                          "one JSON line per run")
     ap.add_argument("--count", type=int, default=512, help="c4: number of problems")
     ap.add_argument("--slots", default="0", help="c4: comma list of batched workgroup counts to time "
                                                  "(0 = one per compute unit)")
     ap.add_argument("--no-loop", action="store_true", help="c4: skip the per-problem loop")
+    ap.add_argument("--seeds", type=int, default=32, help="c5: sketch seeds per configuration")
+    ap.add_argument("--c5-kinds", default="srht,gaussian", help="c5: sketches to run")
     return ap.parse_args()
 
 
@@ -267,6 +270,79 @@ def sweep_c4(a):
           flush=True)
 
 
+def sweep_c5(a):
+    """Refreshed IHS (beta = 0) and Polyak-IHS (beta > 0) with a fresh sketch every iteration, the
+    library's step rule mu = theta_1 / theta_2, x_0 = 0, at n = 2^21, d = 256, kappa = 1e5, sigma = 0.01:
+    mean and relative standard error over the sketch seeds of delta_t / delta_0 (delta = ||A (x_t - x*)||^2),
+    time per iteration, and fixed-sketch PCG's iterations and time to the error refreshed IHS reached.
+    (The comparison with the closed forms is made by the tests, which may use the oracle.)"""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    n, d, T, kappa = 1 << 21, 256, 20, 1e5
+    t0 = time.time()
+    P = make_planted(n, d, kappa, sigma=0.01, seed=5001)
+    A = torch.from_numpy(P["A64"]).cuda()
+    y = torch.from_numpy(P["y64"]).cuda()
+    xs = torch.from_numpy(P["x_star"]).cuda()
+    del P
+    log(f"[c5] planted problem in {time.time() - t0:.1f} s")
+    ctx = lsq.Context()
+    trace = torch.zeros(T + 1, dtype=torch.float64, device="cuda")
+    for kind in [k for k in a.c5_kinds.split(",") if k]:
+        for m in (512, 1024):
+            ihs_mean_T = None
+            for beta in (0.0, 0.05, 0.1, 0.5):
+                ratios, it_ms, mu = [], [], None
+                for r in range(a.seeds):
+                    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+                    desc = lsq.sketch_desc(kind, m, seed=7000000 + 5000 + r, t=0)
+                    info = ctx.ihs_solve(A, y, desc, x, iters=T, beta=beta, refresh=1, mu_rule=0, x_ref=xs,
+                                         err_trace=trace)
+                    e = host_np(trace)
+                    ratios.append((e / e[0]) ** 2)
+                    it_ms.append((info.t_sketch_ms + info.t_factor_ms + info.t_iter_ms) / T)
+                    mu = info.mu
+                R = np.array(ratios)
+                mean = R.mean(axis=0)
+                se = R.std(axis=0, ddof=1) / np.sqrt(len(R)) / np.maximum(mean, 1e-300)
+                if beta == 0.0:
+                    ihs_mean_T = float(mean[-1])
+                rec = {"sweep": "c5", "kind": kind, "n": n, "d": d, "kappa": kappa, "m": m, "beta": beta,
+                       "mu": mu, "seeds": a.seeds, "T": T,
+                       "ratio_mean": [float(v) for v in mean], "ratio_rel_se": [float(v) for v in se],
+                       "ms_per_iter": float(np.median(it_ms))}
+                log(f"[c5] {kind} m={m} beta={beta}: mu {mu:.5f}, delta_T/delta_0 mean {mean[-1]:.3e} "
+                    f"(rel se {se[-1]:.3f}), {rec['ms_per_iter']:.2f} ms/iter")
+                print(json.dumps(rec), flush=True)
+            # fixed-sketch PCG: iterations (and time) to the error refreshed IHS reached in T steps
+            target = float(np.sqrt(ihs_mean_T))
+            x = torch.zeros(d, dtype=torch.float64, device="cuda")
+            ptrace = torch.zeros(201, dtype=torch.float64, device="cuda")
+            desc = lsq.sketch_desc(kind, m, seed=7000000 + 5000, t=0)
+            _, info = ctx.pcg_solve(A, y, desc, x, tol=1e-300, max_iter=200, stop_rule=1, x_ref=xs,
+                                    err_trace=ptrace)
+            pe = host_np(ptrace)
+            k = int(np.argmax(pe <= target)) if np.any(pe <= target) else None
+            per_it = info.t_iter_ms / max(info.iters, 1)
+            rec = {"sweep": "c5", "kind": kind, "m": m, "pcg_fixed_sketch": True,
+                   "target_rel_a_norm_error": target, "iters_to_target": k,
+                   "time_to_target_ms": (info.t_sketch_ms + info.t_factor_ms + k * per_it) if k else None,
+                   "ihs_time_ms": float(np.median(it_ms)) * T,
+                   "pcg_error_trace": [float(v) for v in pe[: (k or 40) + 1]]}
+            log(f"[c5] PCG fixed {kind} m={m}: {k} iterations to e_A {target:.2e} "
+                f"({rec['time_to_target_ms']} ms) vs refreshed IHS {rec['ihs_time_ms']:.1f} ms")
+            print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def host_np(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
 def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
     """The CPU oracle as it stands, on a bounded sample of the same workload: its sketch of the first
     `rows` rows (scaled linearly to n), its Householder QR of the m x d sketch, and one of its PCG
@@ -307,6 +383,9 @@ def main():
         return
     if a.sweep == "c4":
         sweep_c4(a)
+        return
+    if a.sweep == "c5":
+        sweep_c5(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "
