@@ -131,6 +131,16 @@ def gaussian_normals(seed, t, rows, cols):
     return box_muller(a, b, (q & 1) == 1)
 
 
+def round_bf16(x):
+    """Round to bfloat16 (8 significand bits) to nearest, ties to even, via single precision: the
+    value is first rounded to float32, then its bit pattern keeps the upper 16 bits after adding
+    0x7FFF plus the lowest kept bit.  Returns float64."""
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32)
+    bits = x32.view(np.uint32).astype(np.uint64)
+    bits = (bits + np.uint64(0x7FFF) + ((bits >> np.uint64(16)) & np.uint64(1))) & np.uint64(0xFFFF0000)
+    return bits.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
 def gaussian_matrix(seed, t, m, n):
     """Dense S (m x n) of the Gaussian embedding, entries N(0, 1/m)."""
     i = np.arange(m)[:, None]

@@ -109,6 +109,18 @@ def gaussian_sketch(A, m, seed, t=0, row_block=4096):
     return SA
 
 
+def gaussian_sketch_bf16(A, m, seed, t=0, row_block=4096):
+    """S A for the precision form of the Gaussian embedding: the standard normals are rounded to
+    bfloat16 before scaling by 1/sqrt(m) (the product with A in float64)."""
+    n, d = A.shape
+    SA = np.zeros((m, d))
+    for j0 in range(0, n, row_block):
+        j1 = min(n, j0 + row_block)
+        G = draws.round_bf16(draws.gaussian_normals(seed, t, np.arange(m)[:, None], np.arange(j0, j1)[None, :]))
+        SA += G @ A[j0:j1]
+    return SA / np.sqrt(m)
+
+
 def sketch(A, kind, m, seed, t=0, s=1):
     if kind == "srht":
         return srht_sketch(A, m, seed, t)

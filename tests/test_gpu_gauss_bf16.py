@@ -1,0 +1,82 @@
+"""GPU parity of the Gaussian precision form (BF16 matrix cores, A split into three BF16 terms,
+FP32 accumulation in short chains folded into FP64) against the oracle's BF16-rounded embedding.
+
+Bound per entry (i, c) of S A: the three-term split and the FP32 chains contribute at most
+c1 * 2^-24 * (|S_bf16| |A|)_ic; a normal whose single-precision Box-Muller value and the oracle's
+double-precision value round to different BF16 neighbours (probability about 1e-4 per entry) moves
+one term by one BF16 step, at most 2^-7 * max_j |S_ij A_jc| each; a few such flips are allowed."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_02675_amd import lsq
+    c = lsq.Context()
+    yield c
+    c.close()
+
+
+@pytest.mark.parametrize("n,d,m,dtype", [(5000, 33, 100, "f32"), (5000, 300, 300, "f64"), (70000, 64, 200, "f32"),
+                                         (3000, 1, 17, "f32"), (20001, 257, 129, "f32")])
+def test_gauss_bf16_sketch(ctx, n, d, m, dtype):
+    import torch
+
+    from oracle.draws import gaussian_normals, round_bf16
+    from oracle.sketch import gaussian_sketch_bf16
+    from paper_1911_02675_amd import lsq
+    say("gauss bf16", n, d, m, dtype)
+    rng = np.random.default_rng(n + d)
+    A = rng.standard_normal((n, d)) * rng.uniform(0.5, 2.0, d)[None, :]
+    if dtype == "f32":
+        A = A.astype(np.float32).astype(np.float64)
+    Ad = torch.from_numpy(A.astype(np.float32) if dtype == "f32" else A).cuda()
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    SA = torch.zeros((m, d), dtype=torch.float64, device="cuda")
+    seed = 31 + n
+    ctx.sketch(Ad, y, lsq.sketch_desc("gaussian", m, seed=seed, compute="bf16"), SA)
+    torch.cuda.synchronize()
+    got = SA.cpu().numpy()
+    ref = gaussian_sketch_bf16(A, m, seed)
+    Sb = round_bf16(gaussian_normals(seed, 0, np.arange(m)[:, None], np.arange(n)[None, :])) / np.sqrt(m)
+    absprod = np.abs(Sb) @ np.abs(A)
+    maxterm = np.max(np.abs(Sb)[:, :, None] * np.abs(A)[None, :, :], axis=1) if n * m * d <= 2e8 else None
+    err = np.abs(got - ref)
+    if maxterm is None:
+        maxterm = np.abs(Sb).max(axis=1)[:, None] * np.abs(A).max(axis=0)[None, :]
+    bound = 64 * 2.0 ** -24 * absprod + 4 * 2.0 ** -7 * maxterm
+    say(f"  max err / bound {np.max(err / bound):.3f}, max rel to |S||A| {np.max(err / absprod):.2e}")
+    assert np.all(err <= bound)
+
+
+def test_gauss_bf16_preconditioner_quality(ctx):
+    """The BF16 sketch is a working preconditioner at kappa = 1e6: PCG to 1e-10 in about the
+    iterations of the FP64 Gaussian sketch with the same draws."""
+    import torch
+
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    P = make_planted(1 << 15, 128, 1e6, sigma=0.01, seed=77, want64=False, want32=True)
+    A32, y, xs = P["A32"], P["y32"], P["x_star"]
+    Ad, yd = torch.from_numpy(A32).cuda(), torch.from_numpy(y).cuda()
+    its = {}
+    for comp in ("f64", "bf16"):
+        x = torch.zeros(128, dtype=torch.float64, device="cuda")
+        st, info = ctx.pcg_solve(Ad, yd, lsq.sketch_desc("gaussian", 512, seed=5, compute=comp), x, tol=1e-10,
+                                 mixed=1, max_refine=10, max_iter=300)
+        torch.cuda.synchronize()
+        e = a_norm_error(A32.astype(np.float64), x.cpu().numpy(), xs)
+        its[comp] = info.iters
+        say(f"  {comp}: iters {info.iters}, e_A {e:.2e}")
+        assert e <= 1e-10
+    assert its["bf16"] <= its["f64"] + 3

@@ -81,3 +81,35 @@ def test_gaussian_inverse_moments_monte_carlo():
     assert abs(np.mean(t2s) - t2) < 4 * se2
     # and the wrong normalisation (1/n instead of 1/m) would be far off
     assert abs(np.mean(t1s) * m / n - t1) > 20 * se1
+
+
+def test_round_bf16_pins():
+    from oracle.draws import round_bf16
+    # exact bfloat16 values are fixed points; halfway cases go to the even significand
+    exact = np.array([0.0, 1.0, -2.5, 1.0 + 2.0 ** -7, 3.0 * 2.0 ** -100, 65280.0])
+    assert np.array_equal(round_bf16(exact), exact)
+    assert round_bf16(1.0 + 2.0 ** -8) == 1.0                        # tie, even below
+    assert round_bf16(1.0 + 3 * 2.0 ** -8) == 1.0 + 2.0 ** -6        # tie, even above
+    assert round_bf16(1.0 + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert round_bf16(-(1.0 + 2.0 ** -8 + 2.0 ** -20)) == -(1.0 + 2.0 ** -7)
+    x = np.random.default_rng(3).standard_normal(100000) * 10.0 ** np.random.default_rng(4).uniform(-30, 30, 100000)
+    r = round_bf16(x)
+    assert np.all(np.abs(r - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-6))
+    # result has at most 8 significand bits
+    m_, e_ = np.frexp(r[r != 0])
+    assert np.all(m_ * 2 ** 8 == np.round(m_ * 2 ** 8))
+
+
+def test_gaussian_sketch_bf16_is_the_rounded_embedding():
+    from oracle.draws import gaussian_matrix, round_bf16
+    from oracle.sketch import gaussian_sketch, gaussian_sketch_bf16
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((300, 7))
+    m, seed = 20, 5
+    S = gaussian_matrix(seed, 0, m, 300) * np.sqrt(m)
+    Sb = round_bf16(S) / np.sqrt(m)
+    SA = gaussian_sketch_bf16(A, m, seed, row_block=128)
+    assert np.allclose(SA, Sb @ A, rtol=1e-13, atol=1e-13)
+    # within one bf16 rounding of the float64 sketch, entry by entry
+    bound = 2.0 ** -8 * (np.abs(S) / np.sqrt(m)) @ np.abs(A)
+    assert np.all(np.abs(SA - gaussian_sketch(A, m, seed)) <= bound + 1e-13)
