@@ -30,7 +30,7 @@ FUSED_PROFILE = os.path.join(ROOT, "profiles", "k_fused_f32_n4194304_d1024.md")
 FUSED_SOURCE = os.path.join(ROOT, "paper_1911_02675_amd", "csrc", "iter.hip")
 
 
-def counter_traffic(n, d, head):
+def counter_traffic(n, d, head, gpc=None):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
     record (scaled by the calibration recorded with it), or None when the record does not cover this
     workload or the kernel source has changed since the counters were taken."""
@@ -44,6 +44,8 @@ def counter_traffic(n, d, head):
     if not rec:
         return None
     if hashlib.sha256(open(FUSED_SOURCE, "rb").read()).hexdigest() != rec.get("source_sha256"):
+        return None
+    if gpc is not None and rec.get("fused_groups_per_cu") != gpc:
         return None
     return rec["traffic_bytes_per_launch"]
 
@@ -69,6 +71,9 @@ def parse():
     ap.add_argument("--forms", default="fp64,mixed")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 16)
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="before the solves, convert 2^28 FP32 values to FP64 once (1 GiB read, 2 GiB "
+                         "written): a kernel of known traffic for scaling rocprofv3 byte counters")
     ap.add_argument("--sweep", choices=["c2", "c4", "c5"], default=None,
                     help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
                          "c4: 512 uneven problems, batched form vs a per-problem loop; "
@@ -396,6 +401,7 @@ def main():
     from paper_1911_02675_amd import lsq
     from synth import make_planted
 
+    from paper_1911_02675_amd import autotune
     forms = [f for f in a.forms.split(",") if f]
     log(f"[bench] generating planted problem n={a.n} d={a.d} kappa={a.kappa:g}")
     t0 = time.time()
@@ -412,6 +418,11 @@ def main():
         A32 = torch.from_numpy(P["A32"]).to(dev)
         y32 = torch.from_numpy(P["y32"]).to(dev)
     torch.cuda.synchronize()
+    if a.calibration_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = src.double()
+        torch.cuda.synchronize()
+        del src, dst
     ctx = lsq.Context()
     ax = torch.linalg.norm(A64 @ xs)
 
@@ -427,7 +438,10 @@ def main():
         return x, info
 
     res = {}
+    tuned = {}
     for form in forms:
+        # launch parameters from the autotuner's table for this GPU (defaults when it has no entry)
+        tuned[form] = autotune.apply("f64" if form == "fp64" else "f32", a.d)
         for _ in range(a.warmup):
             solve(form)
         ctx.fused_pass_timing(reset=True)
@@ -477,7 +491,7 @@ def main():
         "config": {"workload": f"least squares n={a.n} d={a.d} kappa={a.kappa:g} sigma={a.sigma} "
                                f"{a.sketch} m={a.m} tol={a.tol:g}",
                    "n": a.n, "d": a.d, "m": a.m, "kappa": a.kappa, "sketch": a.sketch,
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU", "tuned": tuned},
         "rel_a_norm_error": h["err"],
         "fp64": ({"time_s": round(res["fp64"]["s"], 5), "rel_a_norm_error": res["fp64"]["err"],
                   "iters": res["fp64"]["info"]["iters"], "fused_gbs": round(res["fp64"]["fused_gbs"], 1),
@@ -494,7 +508,9 @@ def main():
                                   if "fp64" in res and "mixed" in res else None),
         "roofline": {"bound": "hbm", "achieved": round(h["fused_gbs"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(h["fused_gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": counter_traffic(a.n, a.d, head), "kernel": "k_fused (A^T(A p), one pass)",
+                     "traffic": counter_traffic(a.n, a.d, head,
+                                                tuned.get(head, {}).get("fused_groups_per_cu", 8)),
+                     "kernel": "k_fused (A^T(A p), one pass)",
                      "bytes_per_launch": h["bytes_per_pass"], "avg_launch_ms": round(h["fused_ms"], 4),
                      "launches": h["launches"]},
         "cpu_baseline": cpu,
