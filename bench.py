@@ -428,13 +428,18 @@ def main():
 
     def solve(form):
         x = torch.zeros(a.d, dtype=torch.float64, device=dev)
+        # not converged is reported, not raised: at kappa ~ 1e8 the FP64 conditioning floor can sit
+        # above the tolerance
         if form == "fp64":
             desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute="f64")
-            _, info = ctx.pcg_solve(A64, y64, desc, x, tol=a.tol, max_iter=200)
+            st, info = ctx.pcg_solve(A64, y64, desc, x, tol=a.tol, max_iter=200, raise_on_error=False)
         else:
             comp = "f32" if a.sketch == "srht" else "f64"
             desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute=comp)
-            _, info = ctx.pcg_solve(A32, y32, desc, x, tol=a.tol, max_iter=200, mixed=1, max_refine=8)
+            st, info = ctx.pcg_solve(A32, y32, desc, x, tol=a.tol, max_iter=200, mixed=1, max_refine=8,
+                                     raise_on_error=False)
+        if st not in (lsq.LSQ_OK, lsq.LSQ_ERR_NOT_CONVERGED):
+            raise lsq.LsqError(st, "solve failed")
         return x, info
 
     res = {}
@@ -462,7 +467,7 @@ def main():
         res[form] = dict(s=dt, err=e, info=infos[-1], fused_ms=fused_ms, launches=launches,
                          fused_gbs=bytes_per_pass / (fused_ms * 1e-3) / 1e9 if fused_ms > 0 else None,
                          bytes_per_pass=bytes_per_pass)
-        log(f"[bench] {form}: {dt * 1e3:.1f} ms/solve  e_A={e:.2e}  iters={info.iters} "
+        log(f"[bench] {form}: {dt * 1e3:.1f} ms/solve  e_A={e:.2e}  status={info.status}  iters={info.iters} "
             f"refine={info.refinements} sketch={info.t_sketch_ms:.1f} factor={info.t_factor_ms:.1f} "
             f"iter={info.t_iter_ms:.1f} ms  fused {fused_ms:.3f} ms/launch "
             f"({res[form]['fused_gbs']:.0f} GB/s)")
@@ -494,11 +499,13 @@ def main():
                    "parallelism": "single GPU", "tuned": tuned},
         "rel_a_norm_error": h["err"],
         "fp64": ({"time_s": round(res["fp64"]["s"], 5), "rel_a_norm_error": res["fp64"]["err"],
+                  "status": res["fp64"]["info"]["status"],
                   "iters": res["fp64"]["info"]["iters"], "fused_gbs": round(res["fp64"]["fused_gbs"], 1),
                   "phases_ms": {k: round(res["fp64"]["info"][k], 3) for k in
                                 ("t_sketch_ms", "t_factor_ms", "t_iter_ms")}}
                  if "fp64" in res else None),
         "mixed": ({"time_s": round(res["mixed"]["s"], 5), "rel_a_norm_error": res["mixed"]["err"],
+                   "status": res["mixed"]["info"]["status"],
                    "iters": res["mixed"]["info"]["iters"], "refinements": res["mixed"]["info"]["refinements"],
                    "fused_gbs": round(res["mixed"]["fused_gbs"], 1),
                    "phases_ms": {k: round(res["mixed"]["info"][k], 3) for k in
