@@ -5,10 +5,12 @@
 // H_N = H_{N2} (x) H_{N1}, so
 //     (H E A)[k] = sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo],
 //     T[j_hi, k_lo] = sum_{j_lo} H_{N1}[k_lo, j_lo] e_j A[j].
-// Pass A computes T block by block (a 128-byte column slice of N1 = 256 consecutive rows, or N rows
-// when N < 256), keeping only the k_lo that some selected row needs.  Pass B evaluates the high-bit
-// sum for the selected rows only, grouped by k_lo so that every needed T row is read once.  HBM
-// traffic is about |A| + 2 f |T| with f the fraction of k_lo values used; pass B does m N2 d adds.
+// Pass A computes T block by block (a column slice of N1 = 256 consecutive rows, or N rows when
+// N < 256), keeping only the k_lo that some selected row needs.  T is stored k_lo-major,
+// T[(slot(k_lo) N2 + j_hi) dT + col] with the row stride dT = d rounded up to 16 bytes, so that pass B
+// streams each bucket's N2 x dT block contiguously while it evaluates the high-bit sum for the
+// bucket's selected rows on the FP64 matrix cores.  HBM traffic is about |A| + 2 f |T| with f the
+// fraction of k_lo values used; pass B does m N2 d multiply-adds.
 //
 // SJLT: the hashed scatter is done as a stable counting sort of the (target, row) pairs followed by
 // a segmented reduction per target row, in increasing row order: no atomics touch S A, and the
@@ -97,15 +99,40 @@ void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1
                      nneeded_dev);
 }
 
-size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32) {
-  return (size_t)N2 * (size_t)nneeded * (size_t)d * (compute_f32 ? 4 : 8);
+// Row stride of T in elements: d rounded up to a 16-byte multiple of the compute type.
+static int64_t srht_dT(int64_t d, int compute_f32) {
+  const int64_t v = compute_f32 ? 4 : 2;
+  return (d + v - 1) / v * v;
 }
 
+size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32) {
+  return (size_t)N2 * (size_t)nneeded * (size_t)srht_dT(d, compute_f32) * (compute_f32 ? 4 : 8);
+}
+
+template <typename T, int W>
+struct SVec;
+template <>
+struct SVec<float, 4> {
+  typedef float __attribute__((ext_vector_type(4))) t;
+};
+template <>
+struct SVec<float, 2> {
+  typedef float __attribute__((ext_vector_type(2))) t;
+};
+template <>
+struct SVec<double, 2> {
+  typedef double __attribute__((ext_vector_type(2))) t;
+};
+template <>
+struct SVec<double, 4> {
+  typedef double __attribute__((ext_vector_type(4))) t;
+};
+
 // --------------------------------------------------------------------------------------------------
-// Pass A (N >= 256): blocks of SRHT_N1 = 256 rows, 128-byte column slices.  Layout 1: thread (c, g)
-// holds rows g + G i; butterflies over i transform the high row bits in registers.  One LDS
-// transpose to layout 2: thread (c, h) holds the G consecutive rows of each of its row groups;
-// butterflies over the low bits.  LDS traffic is one write and one read of the tile.
+// Pass A (N >= 256): blocks of SRHT_N1 = 256 rows.  Layout 1: thread (c, g) holds rows g + G i;
+// butterflies over i transform the high row bits in registers.  One LDS transpose to layout 2:
+// thread (c, h) holds the G consecutive rows of each of its row groups; butterflies over the low
+// bits.  LDS traffic is one write and one read of the tile.
 // --------------------------------------------------------------------------------------------------
 constexpr int SRHT_N1 = 256;
 
@@ -122,6 +149,90 @@ __device__ __forceinline__ void fwht_regs(T (&x)[V]) {
       }
 }
 
+// Vector form: 16 lanes per row, each holding VW = 16 / sizeof(TC) consecutive columns (256-byte row
+// segments of T), G = 16 row groups of 16 rows per thread.  Needs lda and d multiples of VW and A
+// aligned to VW elements.  Loads are never masked: lanes past the last column read a clamped column
+// (columns do not mix in the transform, and those lanes store nothing), and rows past n read row
+// n - 1 and are multiplied by a zero sign.  Grid (N2, slice groups): a workgroup walks the column
+// slices blockIdx.y, blockIdx.y + gridDim.y, ... of its block, loading the next slice while
+// transforming the current one.
+template <typename TA, typename TC>
+__global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A, int64_t n, int64_t d,
+                                                        int64_t lda, const int8_t* __restrict__ signs,
+                                                        const int* __restrict__ slot, int64_t N2,
+                                                        int64_t dT, TC* __restrict__ T) {
+  constexpr int VW = 16 / sizeof(TC);
+  typedef typename SVec<TA, VW>::t va;
+  typedef typename SVec<TC, VW>::t vc;
+  constexpr int LR = 16;          // lanes per row segment
+  constexpr int DC = LR * VW;     // columns per slice
+  constexpr int G = 256 / LR;     // row groups
+  constexpr int V = SRHT_N1 / G;  // rows per thread
+  constexpr int RS = LR + 1;      // padded LDS row stride (vectors)
+  static_assert(V == G, "layout 2 assumes one row group per thread");
+  __shared__ vc tile[SRHT_N1 * RS];
+  __shared__ int slot_s[SRHT_N1];
+  __shared__ int8_t sg_s[SRHT_N1];
+  const int64_t jhi = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int c = tid % LR, g = tid / LR, h = g;
+  const int64_t rbase = jhi * SRHT_N1;
+  const int nslices = (int)((d + DC - 1) / DC);
+  const bool full = rbase + SRHT_N1 <= n;
+  slot_s[tid] = slot[tid];
+  sg_s[tid] = rbase + tid < n ? signs[rbase + tid] : (int8_t)0;
+  __syncthreads();
+  int sidx = blockIdx.y;
+  if (sidx >= nslices) return;
+  const int64_t step = (int64_t)G * lda / VW;
+  auto load = [&](int s, vc(&x)[V]) {
+    int64_t col = (int64_t)s * DC + (int64_t)c * VW;
+    col = col < d ? col : d - VW;  // d is a multiple of VW
+    if (full) {
+      const va* p = (const va*)(A + (rbase + g) * lda + col);
+#pragma unroll
+      for (int i = 0; i < V; ++i) x[i] = __builtin_convertvector(__builtin_nontemporal_load(p + i * step), vc);
+    } else {
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const int64_t r = min(rbase + g + G * i, n - 1);
+        x[i] = __builtin_convertvector(__builtin_nontemporal_load((const va*)(A + r * lda + col)), vc);
+      }
+    }
+  };
+  vc x[V];
+  load(sidx, x);
+  for (; sidx < nslices; sidx += gridDim.y) {
+    const int64_t col = (int64_t)sidx * DC + (int64_t)c * VW;
+    const int nxt = sidx + gridDim.y;
+    vc xn[V];
+    if (nxt < nslices) load(nxt, xn);
+#pragma unroll
+    for (int i = 0; i < V; ++i) x[i] *= (TC)sg_s[g + G * i];
+    fwht_regs<V>(x);
+#pragma unroll
+    for (int i = 0; i < V; ++i) tile[(g + G * i) * RS + c] = x[i];
+    __syncthreads();
+    vc z[G];
+#pragma unroll
+    for (int j = 0; j < G; ++j) z[j] = tile[(G * h + j) * RS + c];
+    fwht_regs<G>(z);
+    if (col < d) {
+#pragma unroll
+      for (int j = 0; j < G; ++j) {
+        const int sl = slot_s[G * h + j];
+        if (sl >= 0) __builtin_nontemporal_store(z[j], (vc*)(T + ((int64_t)sl * N2 + jhi) * dT + col));
+      }
+    }
+    __syncthreads();
+    if (nxt < nslices) {
+#pragma unroll
+      for (int i = 0; i < V; ++i) x[i] = xn[i];
+    }
+  }
+}
+
+// Scalar form for any lda, d and alignment: 128-byte column slices, one column per lane.
 template <typename TA, typename TC, int V, int G>
 __device__ __forceinline__ void srht_load_slice(const TA* __restrict__ A, int64_t n, int64_t d,
                                                 int64_t lda, const int8_t* __restrict__ sg_s,
@@ -142,13 +253,11 @@ __device__ __forceinline__ void srht_load_slice(const TA* __restrict__ A, int64_
     if (sg_s[g + G * i] < 0) x[i] = -x[i];
 }
 
-// grid (N2, slice groups): a workgroup walks the column slices blockIdx.y, blockIdx.y + gridDim.y, ...
-// of its 256-row block, loading the next slice while transforming the current one.
 template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, int64_t n, int64_t d,
                                                      int64_t lda, const int8_t* __restrict__ signs,
-                                                     const int* __restrict__ slot, int nneeded,
-                                                     TC* __restrict__ T) {
+                                                     const int* __restrict__ slot, int64_t N2,
+                                                     int64_t dT, TC* __restrict__ T) {
   constexpr int DC = 128 / sizeof(TC);   // columns per slice
   constexpr int G = 256 / DC;            // row groups (low row bits)
   constexpr int V = SRHT_N1 / G;         // rows per thread
@@ -188,7 +297,7 @@ __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, i
       for (int j = 0; j < G; ++j) {
         const int r = G * (h + G * k) + j;
         const int sl = slot_s[r];
-        if (sl >= 0 && col < d) __builtin_nontemporal_store(z[j], T + (jhi * nneeded + sl) * d + col);
+        if (sl >= 0 && col < d) __builtin_nontemporal_store(z[j], T + ((int64_t)sl * N2 + jhi) * dT + col);
       }
     }
     __syncthreads();
@@ -200,13 +309,12 @@ __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, i
 }
 
 // --------------------------------------------------------------------------------------------------
-// Pass A: sign flip + zero padding + Walsh-Hadamard transform of N1 consecutive rows, in LDS.
+// Pass A for N < 256 (one block of N1 = N rows): sign flip, zero padding and the transform in LDS.
 // --------------------------------------------------------------------------------------------------
 template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_srht_passA(const TA* __restrict__ A, int64_t n, int64_t d,
-                                                    int64_t lda, int N1, int L1,
-                                                    const int8_t* __restrict__ signs,
-                                                    const int* __restrict__ slot, int nneeded,
+                                                    int64_t lda, int N1, const int8_t* __restrict__ signs,
+                                                    const int* __restrict__ slot, int64_t N2, int64_t dT,
                                                     TC* __restrict__ T) {
   constexpr int DC = 128 / sizeof(TC);
   __shared__ TC tile[SRHT_N1_MAX * DC];
@@ -234,34 +342,105 @@ __global__ __launch_bounds__(256) void k_srht_passA(const TA* __restrict__ A, in
     }
   }
   __syncthreads();
-  (void)L1;
   for (int idx = tid; idx < N1 * DC; idx += 256) {
     const int r = idx / DC, c = idx % DC;
     const int sl = slot[r];
     const int64_t col = c0 + c;
-    if (sl >= 0 && col < d) T[(jhi * nneeded + sl) * d + col] = tile[idx];
+    if (sl >= 0 && col < d) T[((int64_t)sl * N2 + jhi) * dT + col] = tile[idx];
   }
 }
 
-constexpr int SRHT_CH = 16;
-
-// Pass B on FP64 matrix cores.  For the (up to 16) selected rows of bucket k_lo and 4 consecutive
-// j_hi, the +-1 signs form the 16 x 4 A operand of v_mfma_f64_16x16x4 (lane l: row l % 16, j_hi offset
-// l / 16) and 4 rows of T the 4 x 16 B operand (lane l: T row offset l / 16, column l % 16); the
-// 16 x 16 result block of a wavefront's column block accumulates over the j_hi range of this
-// workgroup (lane l, register v: selected row l / 16 + 4 v, column l % 16).  Grid: (k_lo, j_hi split,
-// 512-column group).
+// --------------------------------------------------------------------------------------------------
+// Pass B on FP64 matrix cores.  Workgroup (bucket k_lo, j_hi range, 512-column group); each wavefront
+// owns NL * 16 * VW columns.  Per step of 4 consecutive j_hi: the +-1 signs form the 16 x 4 A operand
+// of v_mfma_f64_16x16x4 (lane l: selected row l % 16 of the tile, j_hi offset l / 16), and 16-byte
+// loads of the bucket's T rows (lane l: T row offset l / 16, VW columns) supply VW B operands each
+// (block (il, e) takes element e of load il: columns c0 + 16 VW il + VW (l % 16) + e).  Up to QT = 2
+// tiles of 16 selected rows share every load, so a bucket's T block is read once when it has at most
+// 32 selected rows.  The 16 x 16 result blocks (lane l, register v: tile row l / 16 + 4 v, column
+// l % 16 of the block) accumulate over the workgroup's j_hi range.
+// --------------------------------------------------------------------------------------------------
 typedef double lsq_d4 __attribute__((ext_vector_type(4)));
-constexpr int SRHT_NB = 8;
-constexpr int SRHT_PF = 3;  // steps of 4 rows in flight per wavefront  // 16-column blocks per wavefront; blockIdx.z selects a 512-column group
+constexpr int SRHT_WGC = 512;  // columns per workgroup
+
+template <typename TC, int NL, int QT>
+__device__ __forceinline__ void srht_passB_tiles(const TC* __restrict__ base, int64_t dT, int64_t jh0,
+                                                 int64_t jh1, int64_t c0, int64_t d,
+                                                 const uint64_t (&khi)[QT], const bool (&qok)[QT],
+                                                 int kk, int qi, double* __restrict__ out,
+                                                 const int* __restrict__ ord, int nq) {
+  constexpr int VW = 16 / sizeof(TC);
+  constexpr int SRHT_PF = sizeof(TC) == 4 ? 4 : 3;  // steps of 4 rows in flight per wavefront
+  typedef typename SVec<TC, VW>::t vc;
+  lsq_d4 acc[QT][NL * VW];
+#pragma unroll
+  for (int t = 0; t < QT; ++t)
+#pragma unroll
+    for (int b = 0; b < NL * VW; ++b) acc[t][b] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+  const vc* p = (const vc*)(base + c0) + qi;
+  bool colok[NL];
+#pragma unroll
+  for (int il = 0; il < NL; ++il) colok[il] = c0 + (int64_t)(il * 16 + qi) * VW < dT;
+  const int64_t rstep = dT / VW;
+  vc raw[SRHT_PF][NL];
+#pragma unroll
+  for (int f = 0; f < SRHT_PF; ++f) {
+    const int64_t j = jh0 + 4 * f + kk;
+#pragma unroll
+    for (int il = 0; il < NL; ++il)
+      raw[f][il] = (j < jh1 && colok[il]) ? __builtin_nontemporal_load(p + j * rstep + il * 16) : (vc)(TC)0;
+  }
+  for (int64_t jh = jh0; jh < jh1; jh += 4 * SRHT_PF) {
+#pragma unroll
+    for (int f = 0; f < SRHT_PF; ++f) {
+      const int64_t j = jh + 4 * f + kk;
+      double a[QT];
+#pragma unroll
+      for (int t = 0; t < QT; ++t)
+        a[t] = (qok[t] && j < jh1) ? ((__popcll(khi[t] & (uint64_t)j) & 1) ? -1.0 : 1.0) : 0.0;
+      vc cur[NL];
+#pragma unroll
+      for (int il = 0; il < NL; ++il) cur[il] = raw[f][il];
+      const int64_t jn = j + 4 * SRHT_PF;
+#pragma unroll
+      for (int il = 0; il < NL; ++il)
+        raw[f][il] = (jn < jh1 && colok[il]) ? __builtin_nontemporal_load(p + jn * rstep + il * 16) : (vc)(TC)0;
+#pragma unroll
+      for (int il = 0; il < NL; ++il)
+#pragma unroll
+        for (int e = 0; e < VW; ++e) {
+          const double bv = (double)cur[il][e];
+#pragma unroll
+          for (int t = 0; t < QT; ++t)
+            acc[t][il * VW + e] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], bv, acc[t][il * VW + e], 0, 0, 0);
+        }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < QT; ++t)
+#pragma unroll
+    for (int il = 0; il < NL; ++il)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+        const int64_t col = c0 + (int64_t)(il * 16 + qi) * VW + e;
+        if (col >= d) continue;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int q = 16 * t + kk + 4 * v;
+          if (q < nq) out[(int64_t)ord[q] * d + col] = acc[t][il * VW + e][v];
+        }
+      }
+}
 
 template <typename TC>
-__global__ __launch_bounds__(256) void k_srht_passB_mfma(const TC* __restrict__ T, int64_t N2, int64_t d,
-                                                         int L1, const int64_t* __restrict__ rows,
-                                                         const int* __restrict__ slot,
-                                                         const int* __restrict__ order,
-                                                         const int* __restrict__ bstart, int nneeded,
-                                                         int64_t m, double* __restrict__ partial) {
+__global__ __launch_bounds__(256, 2) void k_srht_passB(const TC* __restrict__ T, int64_t N2, int64_t d,
+                                                    int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                    const int* __restrict__ slot,
+                                                    const int* __restrict__ order,
+                                                    const int* __restrict__ bstart, int64_t m,
+                                                    double* __restrict__ partial) {
+  constexpr int VW = 16 / sizeof(TC);
+  constexpr int NL = SRHT_WGC / (4 * 16 * VW);
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
@@ -270,58 +449,20 @@ __global__ __launch_bounds__(256) void k_srht_passB_mfma(const TC* __restrict__ 
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qi = lane & 15, kk = lane >> 4;
-  const int64_t stride = (int64_t)nneeded * d;
-  const TC* base = T + (int64_t)sl * d;
-  int64_t colb[SRHT_NB];
-  bool colok[SRHT_NB];
-#pragma unroll
-  for (int b = 0; b < SRHT_NB; ++b) {
-    // a wavefront owns SRHT_NB consecutive 16-column blocks (whole cache lines per row)
-    colb[b] = (int64_t)blockIdx.z * (4 * SRHT_NB * 16) + (int64_t)(wv * SRHT_NB + b) * 16 + qi;
-    colok[b] = colb[b] < d;
-  }
-  for (int cb = b0; cb < b1; cb += 16) {
-    const int nq = min(16, b1 - cb);
-    const bool qok = qi < nq;
-    const uint64_t khi = qok ? ((uint64_t)rows[order[cb + qi]] >> L1) : 0ull;
-    lsq_d4 acc[SRHT_NB];
-#pragma unroll
-    for (int b = 0; b < SRHT_NB; ++b) acc[b] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
-    // raw (storage-type) prefetch ring of SRHT_PF steps; values are converted right before use so
-    // that the loads in flight do not have to complete before the current matrix instructions
-    TC raw[SRHT_PF][SRHT_NB];
-#pragma unroll
-    for (int f = 0; f < SRHT_PF; ++f) {
-      const int64_t j = jh0 + 4 * f + kk;
-#pragma unroll
-      for (int b = 0; b < SRHT_NB; ++b)
-        raw[f][b] = (j < jh1 && colok[b]) ? __builtin_nontemporal_load(base + j * stride + colb[b]) : (TC)0;
-    }
-    for (int64_t jh = jh0; jh < jh1; jh += 4 * SRHT_PF) {
-#pragma unroll
-      for (int f = 0; f < SRHT_PF; ++f) {
-        const int64_t j = jh + 4 * f + kk;
-        const double a = (qok && j < jh1) ? ((__popcll(khi & (uint64_t)j) & 1) ? -1.0 : 1.0) : 0.0;
-        double bv[SRHT_NB];
-#pragma unroll
-        for (int b = 0; b < SRHT_NB; ++b) bv[b] = (double)raw[f][b];
-        const int64_t jn = j + 4 * SRHT_PF;
-#pragma unroll
-        for (int b = 0; b < SRHT_NB; ++b)
-          raw[f][b] = (jn < jh1 && colok[b]) ? __builtin_nontemporal_load(base + jn * stride + colb[b]) : (TC)0;
-#pragma unroll
-        for (int b = 0; b < SRHT_NB; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv[b], acc[b], 0, 0, 0);
-      }
-    }
-    double* out = partial + (int64_t)js * m * d;
-#pragma unroll
-    for (int b = 0; b < SRHT_NB; ++b) {
-      if (!colok[b]) continue;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int q = kk + 4 * v;
-        if (q < nq) out[(int64_t)order[cb + q] * d + colb[b]] = acc[b][v];
-      }
+  const int64_t c0 = (int64_t)blockIdx.z * SRHT_WGC + (int64_t)wv * (NL * 16 * VW);
+  const TC* base = T + (int64_t)sl * N2 * dT;
+  double* out = partial + (int64_t)js * m * d;
+  for (int cb = b0; cb < b1; cb += 32) {
+    const int nq = min(32, b1 - cb);
+    if (nq <= 16) {
+      const bool qok[1] = {qi < nq};
+      const uint64_t khi[1] = {qok[0] ? ((uint64_t)rows[order[cb + qi]] >> L1) : 0ull};
+      srht_passB_tiles<TC, NL, 1>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, order + cb, nq);
+    } else {
+      const bool qok[2] = {true, 16 + qi < nq};
+      const uint64_t khi[2] = {(uint64_t)rows[order[cb + qi]] >> L1,
+                               qok[1] ? ((uint64_t)rows[order[cb + 16 + qi]] >> L1) : 0ull};
+      srht_passB_tiles<TC, NL, 2>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, order + cb, nq);
     }
   }
 }
@@ -335,7 +476,11 @@ __global__ void k_srht_final(const double* __restrict__ partial, int JS, int64_t
   SA[(idx / d) * ldsa + idx % d] = s * scale;
 }
 
-int srht_js(int64_t N2) { return N2 >= 256 ? 4 : 1; }
+// j_hi ranges of pass B: enough workgroups to fill the chip at large N2, one range for small N2.
+static int srht_js(int64_t N2) {
+  const int64_t js = N2 / 512;
+  return (int)(js < 1 ? 1 : (js > 8 ? 8 : js));
+}
 
 size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d) {
   return (size_t)srht_js(N2) * (size_t)m * (size_t)d * sizeof(double);
@@ -346,27 +491,39 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                          const SrhtPlan& p, const int8_t* signs, const int64_t* rows,
                          const int* slot, const int* order, const int* bstart, TC* T,
                          double* partial, double* SA, int64_t ldsa) {
-  constexpr int DC = 128 / sizeof(TC);
+  constexpr int VW = 16 / sizeof(TC);
+  const int64_t dT = srht_dT(d, sizeof(TC) == 4);
   int L1 = 0;
   while ((1ll << L1) < p.N1) ++L1;
-  const int64_t nslices = (d + DC - 1) / DC;
   if (p.N1 == SRHT_N1) {
-    // enough workgroups to fill the chip, each walking several column slices of its row block
-    int64_t sg = (4096 + p.N2 - 1) / p.N2;
-    if (sg > nslices) sg = nslices;
-    if (sg < 1) sg = 1;
-    dim3 ga((unsigned)p.N2, (unsigned)sg);
-    hipLaunchKernelGGL((k_srht_passA2<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, signs, slot,
-                       p.nneeded, T);
+    const bool vec = d % VW == 0 && lda % VW == 0 && ((uintptr_t)A % (VW * sizeof(TA))) == 0;
+    if (vec) {
+      // slice groups: about 2^17 (FP32 T) or 2^15 (FP64 T) workgroups in all, measured best on gfx950
+      constexpr int64_t DC = 16 * VW;
+      const int64_t nslices = (d + DC - 1) / DC;
+      const int64_t target = sizeof(TC) == 4 ? (1 << 17) : (1 << 15);
+      int64_t sg = (target + p.N2 - 1) / p.N2;
+      sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
+      hipLaunchKernelGGL((k_srht_passA_vec<TA, TC>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st, A,
+                         n, d, lda, signs, slot, p.N2, dT, T);
+    } else {
+      constexpr int64_t DC = 128 / sizeof(TC);
+      const int64_t nslices = (d + DC - 1) / DC;
+      int64_t sg = (4096 + p.N2 - 1) / p.N2;
+      sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
+      hipLaunchKernelGGL((k_srht_passA2<TA, TC>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st, A, n,
+                         d, lda, signs, slot, p.N2, dT, T);
+    }
   } else {
-    dim3 ga((unsigned)p.N2, (unsigned)nslices);
-    hipLaunchKernelGGL((k_srht_passA<TA, TC>), ga, dim3(256), 0, st, A, n, d, lda, (int)p.N1, L1, signs,
-                       slot, p.nneeded, T);
+    constexpr int64_t DC = 128 / sizeof(TC);
+    const int64_t nslices = (d + DC - 1) / DC;
+    hipLaunchKernelGGL((k_srht_passA<TA, TC>), dim3((unsigned)p.N2, (unsigned)nslices), dim3(256), 0, st, A,
+                       n, d, lda, (int)p.N1, signs, slot, p.N2, dT, T);
   }
   const int JS = srht_js(p.N2);
-  dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((d + 4 * SRHT_NB * 16 - 1) / (4 * SRHT_NB * 16)));
-  hipLaunchKernelGGL((k_srht_passB_mfma<TC>), gb, dim3(256), 0, st, T, p.N2, d, L1, rows, slot, order,
-                     bstart, p.nneeded, p.m, partial);
+  dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + SRHT_WGC - 1) / SRHT_WGC));
+  hipLaunchKernelGGL((k_srht_passB<TC>), gb, dim3(256), 0, st, T, p.N2, d, dT, L1, rows, slot, order, bstart,
+                     p.m, partial);
   hipLaunchKernelGGL(k_srht_final, dim3((unsigned)((p.m * d + 255) / 256)), dim3(256), 0, st, partial, JS,
                      p.m, d, 1.0 / sqrt((double)p.m), SA, ldsa);
 }
