@@ -95,3 +95,27 @@ def pcg_bound(C, T):
     lam = np.linalg.eigvalsh(C)
     q = (np.sqrt(lam[-1]) - np.sqrt(lam[0])) / (np.sqrt(lam[-1]) + np.sqrt(lam[0]))
     return 4.0 * q ** (2 * np.arange(T + 1))
+
+
+def fixed_sketch_params(d, m):
+    """Theorem 3.2 with rho = d/m (the edges (1 -+ sqrt(rho))^2 of the Marchenko-Pastur law that the
+    eigenvalues of C_S follow, Section 3.2): the fixed-sketch IHS step mu = (1 - rho)^2 / (1 + rho) with
+    delta_t / delta_0 <= (4 rho / (1 + rho)^2)^t, and the Polyak-IHS parameters mu = (1 - rho)^2,
+    beta = rho with asymptotic rate rho.  Returns (mu_ihs, rate_ihs, mu_polyak, beta_polyak)."""
+    rho = d / m
+    return (1.0 - rho) ** 2 / (1.0 + rho), 4.0 * rho / (1.0 + rho) ** 2, (1.0 - rho) ** 2, rho
+
+
+def mp_gamma(rho, mu, t, nodes=4000):
+    """Gamma_t^rho(mu) = E_{lambda ~ MP(rho, 1)} (1 - mu / lambda)^{2t} (Section 3.2) by Gauss-Chebyshev
+    quadrature of the second kind on [lambda_-, lambda_+] (the density is sqrt((l+ - l)(l - l-)) /
+    (2 pi rho l))."""
+    lm, lp = (1.0 - np.sqrt(rho)) ** 2, (1.0 + np.sqrt(rho)) ** 2
+    k = np.arange(1, nodes + 1)
+    z = np.cos(k * np.pi / (nodes + 1))
+    w = np.pi / (nodes + 1) * np.sin(k * np.pi / (nodes + 1)) ** 2  # int sqrt(1-z^2) f(z) dz
+    lam = 0.5 * (lp + lm) + 0.5 * (lp - lm) * z
+    half = 0.5 * (lp - lm)
+    # sqrt((l+ - l)(l - l-)) = half * sqrt(1 - z^2), dl = half dz
+    dens = half * half / (2.0 * np.pi * rho * lam)
+    return float(np.sum(w * dens * (1.0 - mu / lam) ** (2 * t)))
