@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before the solves, convert 2^28 FP32 values to FP64 once (1 GiB read, 2 GiB "
                          "written): a kernel of known traffic for scaling rocprofv3 byte counters")
-    ap.add_argument("--sweep", choices=["c2", "c4", "c5"], default=None,
+    ap.add_argument("--sweep", choices=["c2", "c4", "c5", "msize"], default=None,
                     help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
                          "c4: 512 uneven problems, batched form vs a per-problem loop; "
                          "c5: refreshed IHS / Polyak-IHS statistics over 32 sketch seeds vs closed forms; "
@@ -84,6 +84,9 @@ def parse():
                                                  "(0 = one per compute unit)")
     ap.add_argument("--no-loop", action="store_true", help="c4: skip the per-problem loop")
     ap.add_argument("--seeds", type=int, default=32, help="c5: sketch seeds per configuration")
+    ap.add_argument("--c5-methods", default="ihs,fcg,fixed,pcg",
+                    help="c5: comma list of ihs (refreshed IHS and Polyak-IHS), fcg (IPCG and GCC), fixed "
+                         "(fixed-sketch IHS and Polyak-IHS, Theorem 3.2 parameters), pcg (fixed sketch)")
     ap.add_argument("--c5-kinds", default="srht,gaussian", help="c5: sketches to run")
     return ap.parse_args()
 
@@ -277,7 +280,8 @@ def sweep_c4(a):
 
 def sweep_c5(a):
     """Refreshed IHS (beta = 0) and Polyak-IHS (beta > 0) with a fresh sketch every iteration, the
-    library's step rule mu = theta_1 / theta_2, x_0 = 0, at n = 2^21, d = 256, kappa = 1e5, sigma = 0.01:
+    library's step rule mu = theta_1 / theta_2, then flexible CG (IPCG, GCC) on the same sketches, x_0 = 0,
+    at n = 2^21, d = 256, kappa = 1e5, sigma = 0.01:
     mean and relative standard error over the sketch seeds of delta_t / delta_0 (delta = ||A (x_t - x*)||^2),
     time per iteration, and fixed-sketch PCG's iterations and time to the error refreshed IHS reached.
     (The comparison with the closed forms is made by the tests, which may use the oracle.)"""
@@ -298,7 +302,8 @@ def sweep_c5(a):
     for kind in [k for k in a.c5_kinds.split(",") if k]:
         for m in (512, 1024):
             ihs_mean_T = None
-            for beta in (0.0, 0.05, 0.1, 0.5):
+            methods = a.c5_methods.split(",")
+            for beta in ((0.0, 0.05, 0.1, 0.5) if "ihs" in methods else ()):
                 ratios, it_ms, mu = [], [], None
                 for r in range(a.seeds):
                     x = torch.zeros(d, dtype=torch.float64, device="cuda")
@@ -321,7 +326,59 @@ def sweep_c5(a):
                 log(f"[c5] {kind} m={m} beta={beta}: mu {mu:.5f}, delta_T/delta_0 mean {mean[-1]:.3e} "
                     f"(rel se {se[-1]:.3f}), {rec['ms_per_iter']:.2f} ms/iter")
                 print(json.dumps(rec), flush=True)
+            # flexible CG with the same refreshed sketches: IPCG (window 1) and GCC (every direction)
+            for name, window in ((("ipcg", 1), ("gcc", T)) if "fcg" in methods else ()):
+                ratios, it_ms = [], []
+                for r in range(a.seeds):
+                    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+                    desc = lsq.sketch_desc(kind, m, seed=7000000 + 5000 + r, t=0)
+                    info = ctx.fcg_solve(A, y, desc, x, iters=T, window=window, refresh=1, x_ref=xs,
+                                         err_trace=trace)
+                    e = host_np(trace)
+                    ratios.append((e / e[0]) ** 2)
+                    it_ms.append((info.t_sketch_ms + info.t_factor_ms + info.t_iter_ms) / T)
+                R = np.array(ratios)
+                mean = R.mean(axis=0)
+                se = R.std(axis=0, ddof=1) / np.sqrt(len(R)) / np.maximum(mean, 1e-300)
+                rec = {"sweep": "c5", "kind": kind, "n": n, "d": d, "kappa": kappa, "m": m, "method": name,
+                       "window": window, "seeds": a.seeds, "T": T,
+                       "ratio_mean": [float(v) for v in mean], "ratio_rel_se": [float(v) for v in se],
+                       "ms_per_iter": float(np.median(it_ms))}
+                if kind == "gaussian":
+                    # Corollary 4.2: E delta_t / E delta_0 <= (1 - theta_1^2 / theta_2)^t
+                    t1 = m / (m - d - 1.0)
+                    t2 = m * m * (m - 1.0) / ((m - d) * (m - d - 1.0) * (m - d - 3.0))
+                    rec["bound"] = [float((1.0 - t1 * t1 / t2) ** t) for t in range(T + 1)]
+                log(f"[c5] {name.upper()} {kind} m={m}: delta_T/delta_0 mean {mean[-1]:.3e} "
+                    f"(rel se {se[-1]:.3f}), {rec['ms_per_iter']:.2f} ms/iter")
+                print(json.dumps(rec), flush=True)
+            # fixed sketch (refresh = 0): IHS and Polyak-IHS with the Theorem 3.2 parameters (rho = d/m)
+            for name, rule in ((("fixed_ihs", 2), ("fixed_polyak", 3)) if "fixed" in methods else ()):
+                ratios, it_ms, mu = [], [], None
+                for r in range(a.seeds):
+                    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+                    desc = lsq.sketch_desc(kind, m, seed=7000000 + 5000 + r, t=0)
+                    info = ctx.ihs_solve(A, y, desc, x, iters=T, refresh=0, mu_rule=rule, x_ref=xs,
+                                         err_trace=trace)
+                    e = host_np(trace)
+                    ratios.append((e / e[0]) ** 2)
+                    it_ms.append(info.t_iter_ms / T)
+                    mu = info.mu
+                R = np.array(ratios)
+                mean = R.mean(axis=0)
+                se = R.std(axis=0, ddof=1) / np.sqrt(len(R)) / np.maximum(mean, 1e-300)
+                rho = d / m
+                rate = 4 * rho / (1 + rho) ** 2 if rule == 2 else rho
+                rec = {"sweep": "c5", "kind": kind, "n": n, "d": d, "kappa": kappa, "m": m, "method": name,
+                       "mu": mu, "beta": 0.0 if rule == 2 else rho, "seeds": a.seeds, "T": T,
+                       "ratio_mean": [float(v) for v in mean], "ratio_rel_se": [float(v) for v in se],
+                       "theorem_3_2_rate": rate, "ms_per_iter_excl_sketch": float(np.median(it_ms))}
+                log(f"[c5] {name} {kind} m={m}: mu {mu:.5f}, delta_T/delta_0 mean {mean[-1]:.3e} "
+                    f"(rate^T {rate ** T:.3e}), {rec['ms_per_iter_excl_sketch']:.3f} ms/iter after one sketch")
+                print(json.dumps(rec), flush=True)
             # fixed-sketch PCG: iterations (and time) to the error refreshed IHS reached in T steps
+            if "pcg" not in methods or ihs_mean_T is None:
+                continue
             target = float(np.sqrt(ihs_mean_T))
             x = torch.zeros(d, dtype=torch.float64, device="cuda")
             ptrace = torch.zeros(201, dtype=torch.float64, device="cuda")
@@ -339,6 +396,62 @@ def sweep_c5(a):
             log(f"[c5] PCG fixed {kind} m={m}: {k} iterations to e_A {target:.2e} "
                 f"({rec['time_to_target_ms']} ms) vs refreshed IHS {rec['ihs_time_ms']:.1f} ms")
             print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def sweep_msize(a):
+    """Sketch-size chooser (Section 6) on the benchmark workload: for each form, the measured sketch and
+    factor times at every candidate m, the predicted time-to-solve (measured costs + T(m) passes), the
+    chooser's pick, the paper's m*, and the measured time-to-solve of full solves at every candidate."""
+    import torch
+
+    from paper_1911_02675_amd import autotune, lsq, msize
+    from synth import make_planted
+    forms = [f for f in a.forms.split(",") if f]
+    t0 = time.time()
+    P = make_planted(a.n, a.d, a.kappa, sigma=a.sigma, seed=a.seed, want64=True, want32="mixed" in forms)
+    log(f"[msize] planted problem in {time.time() - t0:.1f} s")
+    A64 = torch.from_numpy(P["A64"]).cuda()
+    y64 = torch.from_numpy(P["y64"]).cuda()
+    A32 = torch.from_numpy(P["A32"]).cuda() if "mixed" in forms else None
+    y32 = torch.from_numpy(P["y32"]).cuda() if "mixed" in forms else None
+    del P
+    ctx = lsq.Context()
+    for form in forms:
+        autotune.apply("f64" if form == "fp64" else "f32", a.d)
+        A, y = (A64, y64) if form == "fp64" else (A32, y32)
+        comp = "f64" if form == "fp64" or a.sketch != "srht" else "f32"
+        meas, t_pass = msize.calibrate(ctx, A, y, a.sketch, compute=comp, s=a.s, seed=a.seed)
+        extra = 0.0 if form == "fp64" else 3.0  # refinement residual passes of the mixed form
+        pick, pred = msize.choose(meas, t_pass, a.d, a.tol, extra)
+        measured = {}
+        for m in sorted(meas):
+            best = None
+            for _ in range(a.steps + a.warmup):
+                x = torch.zeros(a.d, dtype=torch.float64, device="cuda")
+                desc = lsq.sketch_desc(a.sketch, m, seed=a.seed, s=a.s, compute=comp)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                st, info = ctx.pcg_solve(A, y, desc, x, tol=a.tol, max_iter=300, mixed=int(form != "fp64"),
+                                         max_refine=8, raise_on_error=False)
+                torch.cuda.synchronize()
+                dt = (time.perf_counter() - t1) * 1e3
+                best = (dt, info.iters, st) if best is None or dt < best[0] else best
+            measured[m] = best
+            log(f"[msize] {form} m={m}: sketch {meas[m][0]:.2f} factor {meas[m][1]:.2f} ms, T(m) "
+                f"{msize.pcg_iterations(m, a.d, a.tol)}, predicted {pred[m]:.1f} ms, measured {best[0]:.1f} ms "
+                f"({best[1]} iterations, status {best[2]})")
+        rec = {"sweep": "msize", "form": form, "n": a.n, "d": a.d, "kappa": a.kappa, "sketch": a.sketch,
+               "tol": a.tol, "t_pass_ms": t_pass, "chooser_m": pick,
+               "paper_m_star": msize.paper_m_star(a.sketch, a.n, a.d, a.tol),
+               "rows": [{"m": m, "sketch_ms": meas[m][0], "factor_ms": meas[m][1],
+                         "T_model": msize.pcg_iterations(m, a.d, a.tol), "predicted_ms": pred[m],
+                         "measured_ms": measured[m][0], "iters": measured[m][1], "status": measured[m][2]}
+                        for m in sorted(meas)]}
+        best_m = min(measured, key=lambda k: measured[k][0])
+        log(f"[msize] {form}: chooser picks m={pick} ({measured[pick][0]:.1f} ms measured); fastest measured "
+            f"m={best_m} ({measured[best_m][0]:.1f} ms); paper m* = {rec['paper_m_star']}")
+        print(json.dumps(rec), flush=True)
     ctx.close()
 
 
@@ -391,6 +504,9 @@ def main():
         return
     if a.sweep == "c5":
         sweep_c5(a)
+        return
+    if a.sweep == "msize":
+        sweep_msize(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "

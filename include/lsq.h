@@ -120,7 +120,10 @@ typedef struct {
  *   mu_rule: 0 = mu = theta_1 / theta_2 from the inverse moments (Theorem 4.1): the Gaussian closed
  *            form for LSQ_GAUSSIAN (needs m >= d + 4), the Haar/SRHT trace approximation for LSQ_SRHT
  *            rescaled to S S^T = (N/m) I, i.e. mu = (N/m) theta_1/theta_2; LSQ_SJLT has no closed form
- *            and needs mu_rule = 1.  1 = use `mu` as given.
+ *            and needs mu_rule = 1.  1 = use `mu` as given.  2 and 3 are the fixed-sketch parameters of
+ *            Theorem 3.2 with rho = d/m (meant for refresh = 0; need m > d): 2 = IHS step
+ *            mu = (1 - rho)^2 / (1 + rho) (the optimal step of Theorem 3.4) with `beta` as given;
+ *            3 = Polyak-IHS mu = (1 - rho)^2, beta = rho (the given `beta` is ignored).
  *   x_ref:   optional; when given err_trace[t] = ||A (x_t - x_ref)|| / ||A x_ref|| for t = 0..iters
  *            (one extra pass over A per iteration; use it for studies, not for timing). */
 typedef struct {
@@ -133,9 +136,27 @@ typedef struct {
   const double* x_ref;
 } lsq_ihs_opts;
 
+/* Flexible conjugate gradient options (Section 1.2, analysed with refreshed sketches in Section 4):
+ * with r_t = A^T (y - A x_t) and H_{S_t} = R_t^T R_t,
+ *   v_t = H_{S_t}^{-1} r_t,   p_t = v_t - sum_{j=t-k_t}^{t-1} (<v_t, H p_j> / <p_j, H p_j>) p_j,
+ *   x_{t+1} = x_t + (<p_t, r_t> / <p_t, H p_t>) p_t       (exact line search along p_t)
+ * with k_t = min(window, t).
+ *   window:  conjugation window k >= 0: 0 = IHS direction with an exact line search, 1 = IPCG,
+ *            >= iters = GCC (every earlier direction).  min(window, iters) <= 1024.
+ *   refresh: 1 = S_t drawn with refresh counter desc.t + t; 0 = S_t = S fixed (then every window
+ *            k >= 1 reproduces PCG).
+ *   x_ref:   optional; when given err_trace[t] = ||A (x_t - x_ref)|| / ||A x_ref|| for t = 0..iters. */
+typedef struct {
+  int32_t iters;
+  int32_t window;
+  int32_t refresh;
+  int32_t pad_;
+  const double* x_ref;
+} lsq_fcg_opts;
+
 /* Per-call report (host).  Times are HIP-event times on the context stream. */
 typedef struct {
-  int32_t iters;       /* PCG iterations (summed over inner solves) or IHS iterations  */
+  int32_t iters;       /* PCG iterations (summed over inner solves), IHS or FCG iterations */
   int32_t refinements; /* outer refinement steps (mixed form)                           */
   double est_rel_err;  /* final stop-rule estimate (or exact error when x_ref was given) */
   double t_sketch_ms, t_factor_ms, t_iter_ms, t_total_ms;
@@ -178,6 +199,15 @@ lsq_status lsq_pcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch
  * err_trace (device, optional, iters+1 values) needs opts->x_ref. */
 lsq_status lsq_ihs_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
                          const lsq_ihs_opts* opts, double* x, double* err_trace, lsq_info* info);
+
+/* FCG / GCC / IPCG (lsq_fcg_opts) for opts->iters iterations from x (device, in: x_0, out: x_iters).
+ * One pass over A per iteration (H p_t; the residual is updated as r_{t+1} = r_t - alpha_t H p_t) plus
+ * one for r_0, a sketch and a factorization per iteration when refresh = 1.  err_trace (device,
+ * optional, iters+1 values) needs opts->x_ref.  The workspace holds min(window, iters) directions and
+ * their images H p_j (2 d doubles each).  Errors: INVALID_ARG for iters < 0, window < 0, err_trace
+ * without x_ref; UNSUPPORTED for min(window, iters) > 1024; RANK from the factorization. */
+lsq_status lsq_fcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
+                         const lsq_fcg_opts* opts, double* x, double* err_trace, lsq_info* info);
 
 /* `count` independent problems solved together (Section 1.2 with the sparse embedding of
  * Section 2, the SJLT): the sketch S_i A_i, the Householder QR S_i A_i = Q_i R_i, W_i = R_i^{-1}

@@ -227,7 +227,9 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
   HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, sizeof(int), hipMemcpyDeviceToHost, c->st));
   HIPCHK(hipStreamSynchronize(c->st));
   if (c->hflags[0]) return fail(LSQ_ERR_RANK, "S A is numerically rank deficient (zero pivot in R)");
-  tri_inverse(c->st, R, d, W, WT);
+  double* tscr;
+  CHK(wsT(c, "trinv", trinv_scratch_len(d), &tscr));
+  tri_inverse(c->st, R, d, W, WT, tscr);
   HIPCHK(hipGetLastError());
   return LSQ_OK;
 }
@@ -626,9 +628,15 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     } else {
       return fail(LSQ_ERR_INVALID_ARG, "the SJLT has no closed-form step: use mu_rule = 1");
     }
+  } else if (o->mu_rule == 2 || o->mu_rule == 3) {
+    // Theorem 3.2 with rho = d/m: IHS step (1 - rho)^2 / (1 + rho); Polyak mu = (1 - rho)^2, beta = rho
+    if (m <= d) return fail(LSQ_ERR_INVALID_ARG, "the fixed-sketch rules need m > d");
+    const double rho = (double)d / (double)m;
+    mu = o->mu_rule == 2 ? (1.0 - rho) * (1.0 - rho) / (1.0 + rho) : (1.0 - rho) * (1.0 - rho);
   } else if (o->mu_rule != 1) {
-    return fail(LSQ_ERR_INVALID_ARG, "mu_rule must be 0 or 1");
+    return fail(LSQ_ERR_INVALID_ARG, "mu_rule must be 0, 1, 2 or 3");
   }
+  const double beta = o->mu_rule == 3 ? (double)d / (double)m : o->beta;
   const hipStream_t st = c->st;
   const int a_f32 = p->a_dtype == LSQ_F32;
   double *SA, *R, *W, *WT, *xprev, *diff, *errv;
@@ -682,7 +690,7 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
     int ndot;
     precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
-    ihs_update(st, d, x, xprev, b.rhat, mu, o->beta);
+    ihs_update(st, d, x, xprev, b.rhat, mu, beta);
     HIPCHK(hipEventRecord(c->ev[1], st));
     HIPCHK(hipEventSynchronize(c->ev[1]));
     float ms;
@@ -709,6 +717,115 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     info->t_total_ms = ms;
     info->bytes_streamed = (double)o->iters * p->n * d * (a_f32 ? 4.0 : 8.0);
     info->mu = mu;
+    info->status = LSQ_OK;
+    info->pad_ = 0;
+    info->t_start_ms = 0.0;
+  }
+  return LSQ_OK;
+}
+
+lsq_status lsq_fcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
+                         const lsq_fcg_opts* o, double* x, double* err_trace, lsq_info* info) {
+  CHK(check_problem(c, p));
+  CHK(check_sketch(p, s, true));
+  if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
+  if (o->iters < 0) return fail(LSQ_ERR_INVALID_ARG, "iters < 0");
+  if (o->window < 0) return fail(LSQ_ERR_INVALID_ARG, "window < 0");
+  if (err_trace && !o->x_ref) return fail(LSQ_ERR_INVALID_ARG, "err_trace needs x_ref");
+  const int ring = std::max(1, std::min(o->window, o->iters));
+  if (ring > FCG_MAX_WINDOW) return fail(LSQ_ERR_UNSUPPORTED, "min(window, iters) > 1024");
+  const int64_t d = p->d, m = s->m;
+  const hipStream_t st = c->st;
+  const int a_f32 = p->a_dtype == LSQ_F32;
+  double *SA, *R, *W, *WT, *diff, *P, *HP, *php;
+  CHK(wsT(c, "SA", (size_t)m * d, &SA));
+  CHK(wsT(c, "f_R", (size_t)d * d, &R));
+  CHK(wsT(c, "f_W", (size_t)d * d, &W));
+  CHK(wsT(c, "f_WT", (size_t)d * d, &WT));
+  CHK(wsT(c, "ihs_diff", d, &diff));
+  CHK(wsT(c, "fcg_P", (size_t)ring * d, &P));
+  CHK(wsT(c, "fcg_HP", (size_t)ring * d, &HP));
+  CHK(wsT(c, "fcg_php", ring, &php));
+  SolveBufs b;
+  CHK(solve_bufs(c, p->n, d, &b));
+  double ax2 = 0.0;
+  auto error_at = [&](int t) -> lsq_status {
+    // err_trace[t] = ||A (x - x_ref)|| / ||A x_ref||
+    vec_copy(st, diff, x, d);
+    vec_axpy(st, diff, o->x_ref, -1.0, d);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, diff, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    error_from_resid(st, b.red + d, ax2, err_trace + t);
+    HIPCHK(hipGetLastError());
+    return LSQ_OK;
+  };
+  if (err_trace) {
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, o->x_ref, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    HIPCHK(hipMemcpyAsync(c->hflags, b.red + d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    memcpy(&ax2, c->hflags, sizeof(double));
+    CHK(error_at(0));
+  }
+  double t_sketch = 0.0, t_factor = 0.0, t_iter = 0.0;
+  HIPCHK(hipEventRecord(c->ev[4], st));
+  {
+    // r_0 = A^T (y - A x_0)
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    vec_copy(st, b.r, b.red, d);
+  }
+  for (int t = 0; t < o->iters; ++t) {
+    if (t == 0 || o->refresh) {
+      float ms;
+      HIPCHK(hipEventRecord(c->ev[0], st));
+      CHK(do_sketch(c, p, s, s->t + (o->refresh ? (uint64_t)t : 0), SA, d));
+      HIPCHK(hipEventRecord(c->ev[1], st));
+      CHK(do_factor(c, SA, m, d, d, R, W, WT));
+      HIPCHK(hipEventRecord(c->ev[2], st));
+      HIPCHK(hipEventSynchronize(c->ev[2]));
+      hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+      t_sketch += ms;
+      hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+      t_factor += ms;
+    }
+    HIPCHK(hipEventRecord(c->ev[0], st));
+    int ndot;
+    precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);  // v_t
+    const int kt = std::min(o->window, t);
+    const int slot = t % ring;
+    double* pt = P + (size_t)slot * d;
+    fcg_orth(st, b.rhat, P, HP, php, d, t, kt, ring);
+    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 0, pt, nullptr, b.part, b.nwg, nullptr);
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    fcg_step(st, pt, b.red, d, x, b.r, HP + (size_t)slot * d, php + slot);
+    HIPCHK(hipEventRecord(c->ev[1], st));
+    HIPCHK(hipEventSynchronize(c->ev[1]));
+    float ms;
+    hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+    t_iter += ms;
+    if (err_trace) CHK(error_at(t + 1));
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(c->ev[5], st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (info) {
+    float ms;
+    info->iters = o->iters;
+    info->refinements = 0;
+    info->est_rel_err = 0.0;
+    if (err_trace) {
+      double e;
+      hipMemcpy(&e, err_trace + o->iters, sizeof(double), hipMemcpyDeviceToHost);
+      info->est_rel_err = e;
+    }
+    info->t_sketch_ms = t_sketch;
+    info->t_factor_ms = t_factor;
+    info->t_iter_ms = t_iter;
+    hipEventElapsedTime(&ms, c->ev[4], c->ev[5]);
+    info->t_total_ms = ms;
+    info->bytes_streamed = (double)(o->iters + 1) * p->n * d * (a_f32 ? 4.0 : 8.0);
+    info->mu = 0.0;
     info->status = LSQ_OK;
     info->pad_ = 0;
     info->t_start_ms = 0.0;

@@ -85,14 +85,46 @@ __device__ __forceinline__ T group_sum(T v) {
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<LSQ_WAVE>(v); }
 
-// Block-wide sum of K values per thread (NT threads); every thread receives the K totals.
+// Sums over aligned groups of G lanes, every lane of a group receiving the group's sum, without
+// LDS: DPP quad permutations (xor 1, xor 2) and mirrors (8- and 16-lane groups, whose halves are
+// already uniform), then the gfx950 permlane swaps across 16-lane rows (xor 16) and wave halves
+// (xor 32).  Every lane adds the same two operands, so all lanes of a group hold identical bits.
+// All 64 lanes must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double xor16_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double xor32_sum(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+template <int G>
+__device__ __forceinline__ double grp_sum(double v) {
+  if (G >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_d<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_d<0x140>(v); // row_mirror
+  if (G >= 32) v = xor16_sum(v);
+  if (G >= 64) v = xor32_sum(v);
+  return v;
+}
+
+// Block-wide sum of K values per thread (NT threads, all active); every thread receives the K totals.
 // scratch: at least (NT/64) * K + K doubles of shared memory.
 template <int NT, int K>
 __device__ __forceinline__ void block_sum(double (&v)[K], double* scratch) {
   constexpr int NW = NT / LSQ_WAVE;
   const int lane = threadIdx.x & (LSQ_WAVE - 1), wv = threadIdx.x / LSQ_WAVE;
 #pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  for (int k = 0; k < K; ++k) v[k] = grp_sum<LSQ_WAVE>(v[k]);
   if (lane == 0) {
 #pragma unroll
     for (int k = 0; k < K; ++k) scratch[wv * K + k] = v[k];

@@ -225,34 +225,133 @@ void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int6
   hipLaunchKernelGGL(k_qr_rankcheck, dim3(1), dim3(1024), 0, st, R, d, status);
 }
 
-// W = R^{-1}: one wavefront per column j solves R w = e_j from the bottom up; W and W^T written.
-__global__ __launch_bounds__(256) void k_trinv(const double* __restrict__ R, int64_t d,
-                                               double* __restrict__ W, double* __restrict__ WT) {
-  __shared__ double wcol[4][1024];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int64_t j = (int64_t)blockIdx.x * 4 + wv;
-  if (j >= d) return;
-  double* w = wcol[wv];
-  const double wj = 1.0 / R[j * d + j];
-  if (lane == 0) w[j] = wj;
-  for (int64_t i = j - 1; i >= 0; --i) {
+// --------------------------------------------------------------------------------------------------
+// W = R^{-1} by recursive doubling of inverted diagonal blocks (the blocked form of triangular
+// inversion).  R is padded to dp = 16 2^L >= d with the identity on the padding; the 16 x 16 diagonal
+// blocks are inverted by substitution; then level by level two neighbouring inverted blocks of size
+// h become one of size 2 h through W12 = -W11 (R12 W22), two FP64 matrix-core products per level that
+// skip the zero triangles of W11 and W22.  One wavefront computes one 16 x 16 output block, reading
+// its operands from L2.
+// --------------------------------------------------------------------------------------------------
+typedef double lsq_f_d4 __attribute__((ext_vector_type(4)));
+
+static int64_t trinv_padded(int64_t d) {
+  int64_t dp = 16;
+  while (dp < d) dp *= 2;
+  return dp;
+}
+
+size_t trinv_scratch_len(int64_t d) {
+  const int64_t dp = trinv_padded(d);
+  return (size_t)3 * dp * dp;
+}
+
+__global__ void k_trinv_pad(const double* __restrict__ R, int64_t d, int64_t dp, double* __restrict__ Rp,
+                            double* __restrict__ Wp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= dp * dp) return;
+  const int64_t i = idx / dp, j = idx % dp;
+  Rp[idx] = (i < d && j < d) ? R[i * d + j] : (i == j ? 1.0 : 0.0);
+  Wp[idx] = 0.0;
+}
+
+// One wavefront per 16 x 16 diagonal block; lane j < 16 solves R_bb w = e_j bottom-up.
+__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ Rp, int64_t dp,
+                                                   double* __restrict__ Wp) {
+  __shared__ double Rb[16][17];
+  const int64_t b0 = (int64_t)blockIdx.x * 16;
+  for (int e = threadIdx.x; e < 256; e += 64) Rb[e / 16][e % 16] = Rp[(b0 + e / 16) * dp + b0 + e % 16];
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j >= 16) return;
+  double w[16];
+#pragma unroll
+  for (int i = 15; i >= 0; --i) {
     double s = 0.0;
-    for (int64_t k = i + 1 + lane; k <= j; k += 64) s += R[i * d + k] * w[k];
-    s = wave_sum(s);
-    const double wi = -s / R[i * d + i];
-    if (lane == 0) w[i] = wi;
-    __builtin_amdgcn_wave_barrier();
+#pragma unroll
+    for (int k = i + 1; k < 16; ++k) s = fma(Rb[i][k], w[k], s);
+    w[i] = i > j ? 0.0 : (i == j ? 1.0 / Rb[i][i] : -s / Rb[i][i]);
   }
-  __builtin_amdgcn_wave_barrier();
-  for (int64_t i = lane; i < d; i += 64) {
-    const double v = i <= j ? w[i] : 0.0;
-    W[i * d + j] = v;
-    WT[j * d + i] = v;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) Wp[(b0 + i) * dp + b0 + j] = w[i];
+}
+
+// Level with block size h: pair p joins the blocks at rows r1 = 2 p h and c2 = r1 + h.
+// phase 0: T = R12 W22 -> Tp[r1.., c2..] (W22 upper: k <= j);  phase 1: W12 = -W11 T -> Wp[r1.., c2..]
+// (W11 upper: k >= i).  Grid (ceil((h/16)^2 / 4), pairs), 4 wavefronts per workgroup.
+__global__ __launch_bounds__(256) void k_trinv_level(const double* __restrict__ Rp, double* __restrict__ Wp,
+                                                     double* __restrict__ Tp, int64_t dp, int h, int phase) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nb = h / 16;
+  const int blk = blockIdx.x * 4 + wv;
+  if (blk >= nb * nb) return;  // whole wavefronts
+  const int bi = blk / nb, bj = blk % nb;
+  const int64_t r1 = 2 * (int64_t)blockIdx.y * h, c2 = r1 + h;
+  const int li = lane & 15, lk = lane >> 4;
+  lsq_f_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  const double *A, *B;
+  int k0, k1;
+  if (phase == 0) {
+    A = Rp + (r1 + 16 * bi + li) * dp + c2;  // R12 row, columns c2 + k
+    B = Wp + c2 * dp + c2 + 16 * bj + li;    // W22 rows c2 + k, one column
+    k0 = 0;
+    k1 = 16 * (bj + 1);
+  } else {
+    A = Wp + (r1 + 16 * bi + li) * dp + r1;  // W11 row, columns r1 + k
+    B = Tp + r1 * dp + c2 + 16 * bj + li;    // T rows r1 + k, one column
+    k0 = 16 * bi;
+    k1 = h;
+  }
+  for (int k = k0; k < k1; k += 16) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      a[u] = A[k + 4 * u + lk];
+      b[u] = B[(int64_t)(k + 4 * u + lk) * dp];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], acc, 0, 0, 0);
+  }
+  double* out = (phase == 0 ? Tp : Wp) + (r1 + 16 * bi) * dp + c2 + 16 * bj + li;
+  const double sg = phase == 0 ? 1.0 : -1.0;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) out[(int64_t)(lk + 4 * v) * dp] = sg * acc[v];
+}
+
+// W and W^T (d x d) from the padded inverse, through a 32 x 32 LDS tile.
+__global__ __launch_bounds__(256) void k_trinv_out(const double* __restrict__ Wp, int64_t dp, int64_t d,
+                                                   double* __restrict__ W, double* __restrict__ WT) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.x * 32, c0 = (int64_t)blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t r = r0 + k, c = c0 + tx;
+    const double v = (r < d && c < d) ? Wp[r * dp + c] : 0.0;
+    tile[k][tx] = v;
+    if (r < d && c < d) W[r * d + c] = v;
+  }
+  __syncthreads();
+  for (int k = ty; k < 32; k += 8) {
+    const int64_t c = c0 + k, r = r0 + tx;
+    if (r < d && c < d) WT[c * d + r] = tile[tx][k];
   }
 }
 
-void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT) {
-  hipLaunchKernelGGL(k_trinv, dim3((unsigned)((d + 3) / 4)), dim3(256), 0, st, R, d, W, WT);
+void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT, double* scratch) {
+  const int64_t dp = trinv_padded(d);
+  double* Rp = scratch;
+  double* Wp = Rp + dp * dp;
+  double* Tp = Wp + dp * dp;
+  hipLaunchKernelGGL(k_trinv_pad, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, R, d, dp, Rp, Wp);
+  hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)(dp / 16)), dim3(64), 0, st, Rp, dp, Wp);
+  for (int64_t h = 16; h < dp; h *= 2) {
+    const int64_t nb = h / 16;
+    dim3 g((unsigned)((nb * nb + 3) / 4), (unsigned)(dp / (2 * h)));
+    hipLaunchKernelGGL(k_trinv_level, g, dim3(256), 0, st, Rp, Wp, Tp, dp, (int)h, 0);
+    hipLaunchKernelGGL(k_trinv_level, g, dim3(256), 0, st, Rp, Wp, Tp, dp, (int)h, 1);
+  }
+  dim3 go((unsigned)((d + 31) / 32), (unsigned)((d + 31) / 32));
+  hipLaunchKernelGGL(k_trinv_out, go, dim3(256), 0, st, Wp, dp, d, W, WT);
 }
 
 }  // namespace lsq

@@ -73,8 +73,9 @@ void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a
 // scratch.  status: device int, set to LSQ_ERR_RANK on a zero pivot.
 void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* X,
                     double* R, int* status);
-// W = R^{-1} and WT = W^T (both d x d row-major).
-void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT);
+// W = R^{-1} and WT = W^T (both d x d row-major).  scratch: trinv_scratch_len(d) doubles.
+size_t trinv_scratch_len(int64_t d);
+void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT, double* scratch);
 
 // ---- iter.hip -----------------------------------------------------------------------------------
 int fused_nwg(int64_t n, int64_t d);
@@ -114,6 +115,14 @@ void ihs_update(hipStream_t st, int64_t d, double* x, double* xprev, const doubl
                 double beta);
 // out = sqrt(a[0] / b) style scalar helpers evaluated on the device
 void error_from_resid(hipStream_t st, const double* scal, double denom, double* out);
+
+// ---- fcg.hip ------------------------------------------------------------------------------------
+// Ring of K directions (P, HP: K x d; php: K) for the flexible CG window; see fcg.hip.
+constexpr int FCG_MAX_WINDOW = 1024;
+void fcg_orth(hipStream_t st, const double* v, double* P, const double* HP, const double* php, int64_t d,
+              int t, int kt, int K);
+void fcg_step(hipStream_t st, const double* p, const double* red, int64_t d, double* x, double* r,
+              double* hp_slot, double* php_slot);
 
 // ---- batched form (batched.hip) ----
 // One problem of a batch, in queue order (largest n*d first).

@@ -19,7 +19,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
-    "lsq_ihs_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
+    "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
     "lsq_fused_pass_timing", "lsq_tune", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
@@ -43,6 +43,11 @@ class PcgOpts(C.Structure):
 class IhsOpts(C.Structure):
     _fields_ = [("mu", C.c_double), ("beta", C.c_double), ("iters", C.c_int32), ("refresh", C.c_int32),
                 ("mu_rule", C.c_int32), ("pad_", C.c_int32), ("x_ref", C.c_void_p)]
+
+
+class FcgOpts(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("window", C.c_int32), ("refresh", C.c_int32), ("pad_", C.c_int32),
+                ("x_ref", C.c_void_p)]
 
 
 class Info(C.Structure):
@@ -82,6 +87,8 @@ def load():
         "lsq_pcg_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(PcgOpts), P, P,
                            C.POINTER(Info)], I32),
         "lsq_ihs_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(IhsOpts), P, P,
+                           C.POINTER(Info)], I32),
+        "lsq_fcg_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(FcgOpts), P, P,
                            C.POINTER(Info)], I32),
         "lsq_pcg_solve_batched": ([P, I32, C.POINTER(Problem), C.POINTER(SketchDesc),
                                    C.POINTER(PcgOpts), C.POINTER(C.c_void_p), C.POINTER(C.c_void_p),
@@ -209,6 +216,15 @@ class Context:
         o = IhsOpts(mu, beta, iters, refresh, mu_rule, 0, None if x_ref is None else x_ref.data_ptr())
         info = Info()
         _check(self.lib.lsq_ihs_solve(self.h, C.byref(p), C.byref(desc), C.byref(o), _ptr(x),
+                                      _ptr(err_trace), C.byref(info)))
+        return info
+
+    def fcg_solve(self, A, y, desc, x, iters=20, window=1, refresh=1, x_ref=None, err_trace=None):
+        """Flexible CG: window 0 = line-searched IHS, 1 = IPCG, >= iters = GCC."""
+        p = problem(A, y)
+        o = FcgOpts(iters, window, refresh, 0, None if x_ref is None else x_ref.data_ptr())
+        info = Info()
+        _check(self.lib.lsq_fcg_solve(self.h, C.byref(p), C.byref(desc), C.byref(o), _ptr(x),
                                       _ptr(err_trace), C.byref(info)))
         return info
 
