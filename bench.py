@@ -61,7 +61,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--d", type=int, default=1024)
-    ap.add_argument("--m", type=int, default=4096)
+    ap.add_argument("--m", default="auto",
+                    help="sketch size, or 'auto': the Section 6 cost model with this GPU's measured sketch, "
+                         "factor and pass times (paper_1911_02675_amd/msize.py), chosen per form before timing")
     ap.add_argument("--kappa", type=float, default=1e6)
     ap.add_argument("--sigma", type=float, default=0.01)
     ap.add_argument("--sketch", default="srht", choices=["srht", "sjlt", "gaussian"])
@@ -517,7 +519,7 @@ def main():
     from paper_1911_02675_amd import lsq
     from synth import make_planted
 
-    from paper_1911_02675_amd import autotune
+    from paper_1911_02675_amd import autotune, msize
     forms = [f for f in a.forms.split(",") if f]
     log(f"[bench] generating planted problem n={a.n} d={a.d} kappa={a.kappa:g}")
     t0 = time.time()
@@ -542,16 +544,18 @@ def main():
     ctx = lsq.Context()
     ax = torch.linalg.norm(A64 @ xs)
 
+    m_form, m_model = {}, {}
+
     def solve(form):
         x = torch.zeros(a.d, dtype=torch.float64, device=dev)
         # not converged is reported, not raised: at kappa ~ 1e8 the FP64 conditioning floor can sit
         # above the tolerance
         if form == "fp64":
-            desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute="f64")
+            desc = lsq.sketch_desc(a.sketch, m_form[form], seed=a.seed, s=a.s, compute="f64")
             st, info = ctx.pcg_solve(A64, y64, desc, x, tol=a.tol, max_iter=200, raise_on_error=False)
         else:
             comp = "f32" if a.sketch == "srht" else "f64"
-            desc = lsq.sketch_desc(a.sketch, a.m, seed=a.seed, s=a.s, compute=comp)
+            desc = lsq.sketch_desc(a.sketch, m_form[form], seed=a.seed, s=a.s, compute=comp)
             st, info = ctx.pcg_solve(A32, y32, desc, x, tol=a.tol, max_iter=200, mixed=1, max_refine=8,
                                      raise_on_error=False)
         if st not in (lsq.LSQ_OK, lsq.LSQ_ERR_NOT_CONVERGED):
@@ -563,6 +567,19 @@ def main():
     for form in forms:
         # launch parameters from the autotuner's table for this GPU (defaults when it has no entry)
         tuned[form] = autotune.apply("f64" if form == "fp64" else "f32", a.d)
+        if a.m == "auto":
+            # sketch size from the Section 6 cost model with costs measured here (outside the timed region)
+            comp = "f64" if form == "fp64" or a.sketch != "srht" else "f32"
+            meas, t_pass = msize.calibrate(ctx, A64 if form == "fp64" else A32, y64 if form == "fp64" else y32,
+                                           a.sketch, compute=comp, s=a.s, seed=a.seed)
+            m_form[form], _ = msize.choose(meas, t_pass, a.d, a.tol, 0.0 if form == "fp64" else 3.0)
+            m_model[form] = [{"m": m, "sketch_ms": round(ts, 3), "factor_ms": round(tf, 3), "T": T,
+                              "predicted_ms": round(pr, 2)}
+                             for m, ts, tf, T, pr in msize.table(meas, t_pass, a.d, a.tol,
+                                                                 0.0 if form == "fp64" else 3.0)]
+            log(f"[bench] {form}: sketch size m={m_form[form]} chosen by the cost model (pass {t_pass:.3f} ms)")
+        else:
+            m_form[form] = int(a.m)
         for _ in range(a.warmup):
             solve(form)
         ctx.fused_pass_timing(reset=True)
@@ -583,7 +600,7 @@ def main():
         res[form] = dict(s=dt, err=e, info=infos[-1], fused_ms=fused_ms, launches=launches,
                          fused_gbs=bytes_per_pass / (fused_ms * 1e-3) / 1e9 if fused_ms > 0 else None,
                          bytes_per_pass=bytes_per_pass)
-        log(f"[bench] {form}: {dt * 1e3:.1f} ms/solve  e_A={e:.2e}  status={info.status}  iters={info.iters} "
+        log(f"[bench] {form}: m={m_form[form]} {dt * 1e3:.1f} ms/solve  e_A={e:.2e}  status={info.status}  iters={info.iters} "
             f"refine={info.refinements} sketch={info.t_sketch_ms:.1f} factor={info.t_factor_ms:.1f} "
             f"iter={info.t_iter_ms:.1f} ms  fused {fused_ms:.3f} ms/launch "
             f"({res[form]['fused_gbs']:.0f} GB/s)")
@@ -594,7 +611,7 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(P["A64"], P["y64"], a.m, a.sketch, a.s, a.seed, h["info"]["iters"],
+        cpu = cpu_baseline(P["A64"], P["y64"], m_form[head], a.sketch, a.s, a.seed, h["info"]["iters"],
                            a.cpu_sample_rows)
     out = {
         "metric": "time-to-solve (s) + HBM GB/s, n=2^22 d=1024 to 1e-10; mixed vs FP64",
@@ -610,8 +627,10 @@ def main():
         "dtype": "f32 storage + f64" if head == "mixed" else "f64",
         "data": "synthetic (planted, exact minimiser known)",
         "config": {"workload": f"least squares n={a.n} d={a.d} kappa={a.kappa:g} sigma={a.sigma} "
-                               f"{a.sketch} m={a.m} tol={a.tol:g}",
-                   "n": a.n, "d": a.d, "m": a.m, "kappa": a.kappa, "sketch": a.sketch,
+                               f"{a.sketch} m={m_form[head]} tol={a.tol:g}",
+                   "n": a.n, "d": a.d, "m": m_form[head], "m_by_form": m_form,
+                   "m_rule": ("Section 6 cost model, measured costs" if a.m == "auto" else "fixed"),
+                   "m_model": m_model or None, "kappa": a.kappa, "sketch": a.sketch,
                    "parallelism": "single GPU", "tuned": tuned},
         "rel_a_norm_error": h["err"],
         "fp64": ({"time_s": round(res["fp64"]["s"], 5), "rel_a_norm_error": res["fp64"]["err"],
