@@ -173,9 +173,14 @@ typedef struct {
 lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc, void* SA,
                       int64_t ldsa, int32_t sa_dtype);
 
-/* Upper-triangular R (d x d, row-major, positive diagonal) with R^T R = (SA)^T (SA), by Householder QR
- * of SA (m x d, row-major, ld lds, m >= d), and W = R^{-1} (d x d, row-major).  Section 1.2 (the
- * paper names QR of S A or a Cholesky factor of H_S).  R or W may be NULL.  RANK on a zero pivot. */
+/* Upper-triangular R (d x d, row-major, positive diagonal) with R^T R = (SA)^T (SA) of SA (m x d,
+ * row-major, ld lds, m >= d), and W = R^{-1} (d x d, row-major).  Section 1.2 (the paper names QR of S A
+ * or a Cholesky factor of H_S = (SA)^T (SA)).  Default: CholeskyQR2, R = chol(Q1^T Q1) chol(X^T X) with
+ * Q1 = X chol(X^T X)^{-1}, backward stable like QR; when the first Cholesky breaks down or the spread of
+ * its diagonal exceeds 1e7 (kappa(SA) beyond about 1e7), Householder QR for m <= 8192 and shifted
+ * CholeskyQR3 above.  lsq_tune("factor", 1) selects Householder QR alone.  R or W may be NULL.  RANK
+ * when some |R_kk| <= 8 d eps max |R_jj|.  UNSUPPORTED for d > 1024 or m > 65536 (m > 8192 with
+ * Householder). */
 lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int64_t lds, double* R,
                       double* W);
 
@@ -253,7 +258,8 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
 /* Process-wide tuning parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
  * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
  * default 8); "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute
- * unit, else 1..65536).  INVALID_ARG for an unknown key or an out-of-range value. */
+ * unit, else 1..65536); "factor" (0 = CholeskyQR2 with its fallbacks, the default; 1 = Householder QR
+ * only, see lsq_factor).  INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
 
 const char* lsq_status_string(lsq_status s);

@@ -42,8 +42,9 @@ struct lsq_ctx {
   std::map<std::string, std::pair<void*, size_t>> bufs;
   DevState* ds = nullptr;   // device
   DevState* hds = nullptr;  // pinned host mirror
-  int* dflags = nullptr;    // device ints: [0] factor status, [1] SJLT draw error, [2] nneeded
-  int* hflags = nullptr;    // pinned host mirror (4 ints)
+  int* dflags = nullptr;    // device ints: [0] factor status, [1] SJLT draw error, [2] nneeded,
+                            // [4], [5] CholeskyQR breakdown / spread flags
+  int* hflags = nullptr;    // pinned host mirror (8 ints)
   hipEvent_t ev[6] = {};
   std::vector<EvPair> fused_ev;  // events around fused passes of the current call
   size_t fused_used = 0;
@@ -124,7 +125,9 @@ static lsq_status check_sketch(const lsq_problem* p, const lsq_sketch_desc* s, b
   if (!s) return fail(LSQ_ERR_INVALID_ARG, "null sketch descriptor");
   if (s->m < 1) return fail(LSQ_ERR_INVALID_ARG, "m < 1");
   if (need_factor && s->m < p->d) return fail(LSQ_ERR_INVALID_ARG, "m < d: S A cannot have full rank");
-  if (need_factor && s->m > 8192) return fail(LSQ_ERR_UNSUPPORTED, "m > 8192 is not implemented");
+  if (need_factor && s->m > FACTOR_M_MAX) return fail(LSQ_ERR_UNSUPPORTED, "m > 65536 is not implemented");
+  if (need_factor && g_factor_mode == 1 && s->m > QR_M_MAX)
+    return fail(LSQ_ERR_UNSUPPORTED, "Householder QR limited to m <= 8192");
   switch (s->kind) {
     case LSQ_SRHT:
       if (s->m > next_pow2(p->n)) return fail(LSQ_ERR_INVALID_ARG, "SRHT needs m <= N");
@@ -216,20 +219,48 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
   return LSQ_OK;
 }
 
-// Factor S A -> R, W = R^{-1}, W^T.
+namespace lsq {
+int g_factor_mode = 0;
+}  // namespace lsq
+
+// Factor S A -> R, W = R^{-1}, W^T.  CholeskyQR2 (Gram matrices on the matrix cores) when the first
+// Cholesky is usable, otherwise Householder QR (m <= 8192) or shifted CholeskyQR3 (larger m); the
+// Householder form alone with lsq_tune("factor", 1).
 static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, int64_t lds,
                             double* R, double* W, double* WT) {
-  double* X;
-  CHK(wsT(c, "qr_x", (size_t)m * d + (size_t)d * d, &X));
-  HIPCHK(hipMemsetAsync(c->dflags, 0, sizeof(int), c->st));
-  householder_qr(c->st, SA, m, d, lds, X, R, c->dflags);
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, sizeof(int), hipMemcpyDeviceToHost, c->st));
-  HIPCHK(hipStreamSynchronize(c->st));
-  if (c->hflags[0]) return fail(LSQ_ERR_RANK, "S A is numerically rank deficient (zero pivot in R)");
+  const hipStream_t st = c->st;
   double* tscr;
-  CHK(wsT(c, "trinv", trinv_scratch_len(d), &tscr));
-  tri_inverse(c->st, R, d, W, WT, tscr);
+  CHK(wsT(c, "trinv", trinv_scratch_len(cholqr_padded(d)), &tscr));
+  bool done = false;
+  if (g_factor_mode == 0) {
+    double* cs;
+    CHK(wsT(c, "cholqr", cholqr_scratch_len(m, d), &cs));
+    if (cholqr_factor(st, SA, m, d, lds, cs, R, c->dflags + 4, c->hflags + 4, tscr) == 0) {
+      done = true;
+    } else if (m > QR_M_MAX) {
+      // the shift regularises the first pass; a breakdown in the later passes means rank deficiency
+      cholqr3_shifted(st, SA, m, d, lds, cs, R, c->dflags + 4, tscr);
+      HIPCHK(hipMemcpyAsync(c->hflags + 4, c->dflags + 4, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (c->hflags[4]) return fail(LSQ_ERR_RANK, "S A is numerically rank deficient (Cholesky breakdown)");
+      done = true;
+    }
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipMemsetAsync(c->dflags, 0, sizeof(int), st));
+  if (done) {
+    qr_rank_check(st, R, d, c->dflags);
+  } else {
+    if (m > QR_M_MAX) return fail(LSQ_ERR_UNSUPPORTED, "Householder QR limited to m <= 8192");
+    double* X;
+    CHK(wsT(c, "qr_x", (size_t)m * d + (size_t)d * d, &X));
+    householder_qr(st, SA, m, d, lds, X, R, c->dflags);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->hflags, c->dflags, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (c->hflags[0]) return fail(LSQ_ERR_RANK, "S A is numerically rank deficient (zero pivot in R)");
+  tri_inverse(st, R, d, W, WT, tscr);
   HIPCHK(hipGetLastError());
   return LSQ_OK;
 }
@@ -365,15 +396,15 @@ lsq_status lsq_create(lsq_ctx** out, void* stream) {
   }
   bool ok = hipMalloc(&c->ds, sizeof(DevState)) == hipSuccess &&
             hipHostMalloc(&c->hds, sizeof(DevState), hipHostMallocDefault) == hipSuccess &&
-            hipMalloc(&c->dflags, 4 * sizeof(int)) == hipSuccess &&
-            hipHostMalloc(&c->hflags, 4 * sizeof(int), hipHostMallocDefault) == hipSuccess;
+            hipMalloc(&c->dflags, 8 * sizeof(int)) == hipSuccess &&
+            hipHostMalloc(&c->hflags, 8 * sizeof(int), hipHostMallocDefault) == hipSuccess;
   for (int i = 0; ok && i < 6; ++i) ok = hipEventCreate(&c->ev[i]) == hipSuccess;
   if (!ok) {
     lsq_destroy(c);
     return fail(LSQ_ERR_HIP, "context allocation failed");
   }
   hipMemset(c->ds, 0, sizeof(DevState));
-  hipMemset(c->dflags, 0, 4 * sizeof(int));
+  hipMemset(c->dflags, 0, 8 * sizeof(int));
   *out = c;
   return LSQ_OK;
 }
@@ -422,7 +453,7 @@ lsq_status lsq_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, int64_
                       double* W) {
   if (!c || !SA) return fail(LSQ_ERR_INVALID_ARG, "null context or SA");
   if (d < 1 || m < d || lds < d) return fail(LSQ_ERR_INVALID_ARG, "need m >= d >= 1 and lds >= d");
-  if (d > 1024 || m > 8192) return fail(LSQ_ERR_UNSUPPORTED, "factor limited to d <= 1024, m <= 8192");
+  if (d > 1024 || m > FACTOR_M_MAX) return fail(LSQ_ERR_UNSUPPORTED, "factor limited to d <= 1024, m <= 65536");
   double *Rb, *Wb, *WTb;
   CHK(wsT(c, "f_R", (size_t)d * d, &Rb));
   CHK(wsT(c, "f_W", (size_t)d * d, &Wb));
@@ -882,6 +913,11 @@ lsq_status lsq_tune(const char* key, int64_t value) {
   if (k == "fused_groups_per_cu") {
     if (value < 1 || value > 64) return fail(LSQ_ERR_INVALID_ARG, "fused_groups_per_cu in [1, 64]");
     g_fused_groups_per_cu = (int)value;
+    return LSQ_OK;
+  }
+  if (k == "factor") {
+    if (value < 0 || value > 1) return fail(LSQ_ERR_INVALID_ARG, "factor: 0 (CholeskyQR2) or 1 (Householder)");
+    g_factor_mode = (int)value;
     return LSQ_OK;
   }
   if (k == "batched_slots") {

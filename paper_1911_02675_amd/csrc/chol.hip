@@ -1,0 +1,471 @@
+// Factor step through the Gram matrix (the paper's alternative to QR of S A: a Cholesky factor of
+// H_S = (S A)^T (S A), Section 1.2 and Section 6), made backward stable by a second pass:
+// CholeskyQR2.  With X = S A (m x d):
+//     R1 = chol(X^T X),  Q1 = X R1^{-1},  R2 = chol(Q1^T Q1),  R = R2 R1,
+// and, when the first factorization breaks down, the shifted form with a third pass
+// (R1 = chol(X^T X + s I), s = 11 (m d + d (d + 1)) u ||X||_F^2).  Every product runs on the FP64
+// matrix cores (v_mfma_f64_16x16x4); the Cholesky is blocked by 64 columns (one workgroup factors the
+// diagonal block and inverts it, then the block row and the trailing matrix are updated in parallel).
+// All matrices are row-major and padded to dp = 64 ceil(d / 64) columns, with the identity on the
+// padding of every Gram matrix so that the padded factors are diag(R, I).
+#include "internal.h"
+
+namespace lsq {
+
+typedef double lsq_c_d4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ lsq_c_d4 mfma_d(double a, double b, lsq_c_d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int CQ_T = 64;   // tile edge
+constexpr int CQ_KS = 16;  // rows of X per LDS stage
+constexpr int CQ_LP = 65;  // padded LDS row (doubles)
+
+// --------------------------------------------------------------------------------------------------
+// Gram partials: part[s] = X[rows of split s]^T X[rows of split s] on the upper 64 x 64 tiles.
+// Grid (upper tile pairs, S).  Four wavefronts, each a 32 x 32 quarter of the tile (2 x 2 blocks of
+// 16 x 16).  Columns at or past d read as zero.
+// --------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ X, int64_t m, int64_t d,
+                                                   int64_t ldx, int64_t dp, double* __restrict__ part) {
+  __shared__ double As[CQ_KS][CQ_LP];
+  __shared__ double Bs[CQ_KS][CQ_LP];
+  const int nt = (int)(dp / CQ_T);
+  // tile pair p -> (bi, bj), bi <= bj, row-major over the upper triangle
+  int p = blockIdx.x, bi = 0;
+  while (p >= nt - bi) {
+    p -= nt - bi;
+    ++bi;
+  }
+  const int bj = bi + p;
+  const int S = gridDim.y, s = blockIdx.y;
+  const int64_t r0 = m * s / S, r1 = m * (s + 1) / S;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int lr = tid >> 4, lc = (tid & 15) * 4;  // loader: row lr of the stage, 4 columns from lc
+  const int64_t i0 = (int64_t)bi * CQ_T, j0 = (int64_t)bj * CQ_T;
+  lsq_c_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (lsq_c_d4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t k0 = r0; k0 < r1; k0 += CQ_KS) {
+    const int64_t r = k0 + lr;
+    const bool rok = r < r1;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t ca = i0 + lc + e, cb = j0 + lc + e;
+      As[lr][lc + e] = (rok && ca < d) ? X[r * ldx + ca] : 0.0;
+      Bs[lr][lc + e] = (rok && cb < d) ? X[r * ldx + cb] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < CQ_KS; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][32 * wi + 16 * a + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Bs[kk + (lane >> 4)][32 * wj + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* out = part + (int64_t)s * dp * dp;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t i = i0 + 32 * wi + 16 * a + (lane >> 4) + 4 * v;
+        const int64_t j = j0 + 32 * wj + 16 * b + (lane & 15);
+        out[i * dp + j] = acc[a][b][v];
+      }
+}
+
+// G = sum_s part[s] on the upper tiles (fixed order), plus the identity on the padding and an optional
+// shift on the diagonal.
+__global__ void k_gram_reduce(const double* __restrict__ part, int S, int64_t d, int64_t dp,
+                              const double* __restrict__ shift, double* __restrict__ G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= dp * dp) return;
+  const int64_t i = idx / dp, j = idx % dp;
+  if (i / CQ_T > j / CQ_T) return;  // lower tiles are never read
+  double v = 0.0;
+  for (int s = 0; s < S; ++s) v += part[(int64_t)s * dp * dp + idx];
+  if (i == j) v = i < d ? v + (shift ? *shift : 0.0) : 1.0;
+  G[idx] = v;
+}
+
+// G_ii += s for i < d.
+__global__ void k_gram_add_shift(double* __restrict__ G, int64_t d, int64_t dp, const double* __restrict__ shift) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d) G[i * dp + i] += *shift;
+}
+
+// s = 11 (m d + d (d + 1)) u tr(G) with tr(G) = ||X||_F^2 (one workgroup).
+__global__ __launch_bounds__(1024) void k_gram_shift(const double* __restrict__ G, int64_t m, int64_t d,
+                                                     int64_t dp, double* __restrict__ shift) {
+  __shared__ double sh[16];
+  double t = 0.0;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) t += G[i * dp + i];
+  t = grp_sum<64>(t);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < 16; ++w) s += sh[w];
+    *shift = 11.0 * ((double)m * (double)d + (double)d * (double)(d + 1)) * 1.1102230246251565e-16 * s;
+  }
+}
+
+// --------------------------------------------------------------------------------------------------
+// Blocked Cholesky G = R^T R (upper), 64-column blocks.
+// --------------------------------------------------------------------------------------------------
+// Diagonal block kb: factor in LDS (column by column), write R_kk, and its inverse into Dinv (64 x 64).
+// A pivot that is not positive sets *flag and is replaced by 1 so that the factorization completes.
+__global__ __launch_bounds__(256) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
+                                                   double* __restrict__ R, double* __restrict__ Dinv,
+                                                   int* __restrict__ flag) {
+  __shared__ double T[CQ_T][CQ_LP];
+  const int tid = threadIdx.x;
+  const int64_t o = (int64_t)kb * CQ_T;
+  for (int e = tid; e < CQ_T * CQ_T; e += 256) {
+    const int i = e / CQ_T, j = e % CQ_T;
+    T[i][j] = j >= i ? G[(o + i) * dp + o + j] : 0.0;
+  }
+  __syncthreads();
+  for (int k = 0; k < CQ_T; ++k) {
+    // row k: r_kk = sqrt(pivot), r_kj = t_kj / r_kk
+    const double piv = T[k][k];
+    const bool bad = !(piv > 0.0);
+    const double rkk = bad ? 1.0 : sqrt(piv);
+    __syncthreads();
+    if (tid == 0 && bad) *flag = 1;
+    if (tid >= k && tid < CQ_T) T[k][tid] = tid == k ? rkk : T[k][tid] / rkk;
+    __syncthreads();
+    // trailing: t_ij -= r_ki r_kj for k < i <= j
+    for (int e = tid; e < CQ_T * CQ_T; e += 256) {
+      const int i = e / CQ_T, j = e % CQ_T;
+      if (i > k && j >= i) T[i][j] = fma(-T[k][i], T[k][j], T[i][j]);
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < CQ_T * CQ_T; e += 256) {
+    const int i = e / CQ_T, j = e % CQ_T;
+    R[(o + i) * dp + o + j] = T[i][j];
+  }
+  // inverse of the 64 x 64 upper block, one column per thread: R w = e_j bottom-up
+  if (tid < CQ_T) {
+    const int j = tid;
+    double w[CQ_T];
+#pragma unroll
+    for (int i = CQ_T - 1; i >= 0; --i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = i + 1; k < CQ_T; ++k) s = fma(T[i][k], w[k], s);
+      w[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / T[i][i]);
+    }
+#pragma unroll
+    for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = w[i];
+  }
+}
+
+// Block row kb: R_kj = Dinv^T G_kj for column tiles right of the diagonal block.  One wavefront per
+// 16 x 16 output block; grid covers 4 row blocks x the 16-column blocks right of the diagonal.
+__global__ __launch_bounds__(256) void k_chol_row(const double* __restrict__ G, int64_t dp, int kb,
+                                                  const double* __restrict__ Dinv, double* __restrict__ R) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)(kb + 1) * CQ_T;
+  const int ncb = (int)((dp - c0) / 16);
+  const int blk = blockIdx.x * 4 + wv;
+  if (blk >= 4 * ncb) return;  // whole wavefronts
+  const int ib = blk / ncb, jb = blk % ncb;
+  const int64_t o = (int64_t)kb * CQ_T;
+  const int li = lane & 15, lk = lane >> 4;
+  lsq_c_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // (Dinv^T)[i][k] = Dinv[k][i], nonzero for k <= i
+  const int kend = 16 * (ib + 1);
+  for (int k = 0; k < kend; k += 4) {
+    const double a = Dinv[(k + lk) * CQ_T + 16 * ib + li];
+    const double b = G[(o + k + lk) * dp + c0 + 16 * jb + li];
+    acc = mfma_d(a, b, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) R[(o + 16 * ib + lk + 4 * v) * dp + c0 + 16 * jb + li] = acc[v];
+}
+
+// Trailing update: G_ij -= R_ki^T R_kj (K = 64) on the upper 16 x 16 blocks right of and below block kb.
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int64_t dp, int kb,
+                                                     const double* __restrict__ R) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t c0 = (int64_t)(kb + 1) * CQ_T;
+  const int nb = (int)((dp - c0) / 16);
+  int p = blockIdx.x * 4 + wv;
+  if (p >= nb * (nb + 1) / 2) return;  // whole wavefronts
+  int bi = 0;
+  while (p >= nb - bi) {
+    p -= nb - bi;
+    ++bi;
+  }
+  const int bj = bi + p;
+  const int64_t o = (int64_t)kb * CQ_T;
+  const int li = lane & 15, lk = lane >> 4;
+  lsq_c_d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k = 0; k < CQ_T; k += 4) {
+    const double a = R[(o + k + lk) * dp + c0 + 16 * bi + li];  // (R_k.)^T[i][k] = R[k][i]
+    const double b = R[(o + k + lk) * dp + c0 + 16 * bj + li];
+    acc = mfma_d(a, b, acc);
+  }
+  double* g = G + (c0 + 16 * bi) * dp + c0 + 16 * bj + li;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) g[(int64_t)(lk + 4 * v) * dp] -= acc[v];
+}
+
+// --------------------------------------------------------------------------------------------------
+// Q = X W with W upper triangular (dp x dp, identity on the padding): Q[r][j] = sum_{k <= j} X[r][k] W[k][j].
+// Tile 64 rows x 64 columns per workgroup, four wavefronts of 32 x 32, X and W staged through LDS.
+// --------------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_xw(const double* __restrict__ X, int64_t m, int64_t d, int64_t ldx,
+                                            const double* __restrict__ W, int64_t dp, double* __restrict__ Q) {
+  __shared__ double Xs[CQ_T][CQ_KS + 1];
+  __shared__ double Ws[CQ_KS][CQ_LP];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wi = wv >> 1, wj = wv & 1;
+  const int64_t r0 = (int64_t)blockIdx.x * CQ_T, j0 = (int64_t)blockIdx.y * CQ_T;
+  lsq_c_d4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (lsq_c_d4){0.0, 0.0, 0.0, 0.0};
+  const int64_t kend = j0 + CQ_T;  // W[k][j] = 0 for k > j
+  for (int64_t k0 = 0; k0 < kend; k0 += CQ_KS) {
+    // X tile: 64 rows x 16 columns (thread: row tid / 4, columns 4 (tid % 4) ..)
+    {
+      const int rr = tid >> 2, cc = (tid & 3) * 4;
+      const int64_t r = r0 + rr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t c = k0 + cc + e;
+        Xs[rr][cc + e] = (r < m && c < d) ? X[r * ldx + c] : 0.0;
+      }
+    }
+    // W tile: 16 rows x 64 columns
+    {
+      const int rr = tid >> 4, cc = (tid & 15) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) Ws[rr][cc + e] = W[(k0 + rr) * dp + j0 + cc + e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < CQ_KS; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) av[a] = Xs[32 * wi + 16 * a + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bv[b] = Ws[kk + (lane >> 4)][32 * wj + 16 * b + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d(av[a], bv[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = r0 + 32 * wi + 16 * a + (lane >> 4) + 4 * v;
+        const int64_t j = j0 + 32 * wj + 16 * b + (lane & 15);
+        if (r < m) Q[r * dp + j] = acc[a][b][v];
+      }
+}
+
+// C = A B for upper triangular A, B (dp x dp): C[i][j] = sum_{i <= k <= j} A[i][k] B[k][j], upper 16 x 16
+// blocks, one wavefront each; the strictly lower blocks of C are cleared.
+__global__ __launch_bounds__(256) void k_trtr(const double* __restrict__ A, const double* __restrict__ B,
+                                              int64_t dp, double* __restrict__ C) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int nb = (int)(dp / 16);
+  const int blk = blockIdx.x * 4 + wv;
+  if (blk >= nb * nb) return;  // whole wavefronts
+  const int bi = blk / nb, bj = blk % nb;
+  const int li = lane & 15, lk = lane >> 4;
+  double* c = C + (int64_t)(16 * bi) * dp + 16 * bj + li;
+  if (bi > bj) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) c[(int64_t)(lk + 4 * v) * dp] = 0.0;
+    return;
+  }
+  lsq_c_d4 acc = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 16 * bi; k < 16 * (bj + 1); k += 4) {
+    const double a = A[(int64_t)(16 * bi + li) * dp + k + lk];
+    const double b = B[(int64_t)(k + lk) * dp + 16 * bj + li];
+    acc = mfma_d(a, b, acc);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) c[(int64_t)(lk + 4 * v) * dp] = acc[v];
+}
+
+// R (d x d) from the padded factor; the lower triangle is zero.
+__global__ void k_chol_extract(const double* __restrict__ Rp, int64_t dp, int64_t d, double* __restrict__ R) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= d * d) return;
+  const int64_t i = idx / d, j = idx % d;
+  R[idx] = j >= i ? Rp[i * dp + j] : 0.0;
+}
+
+// max |R_jj| / min |R_jj| > lim sets *flag (the first factor is too inaccurate for two passes).
+__global__ __launch_bounds__(1024) void k_chol_diagratio(const double* __restrict__ Rp, int64_t dp, int64_t d,
+                                                         double lim, int* __restrict__ flag) {
+  __shared__ double smx[16], smn[16];
+  double mx = 0.0, mn = INFINITY;
+  for (int64_t i = threadIdx.x; i < d; i += 1024) {
+    const double v = fabs(Rp[i * dp + i]);
+    mx = fmax(mx, v);
+    mn = fmin(mn, v);
+  }
+  for (int off = 32; off >= 1; off >>= 1) {
+    mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mn = fmin(mn, __shfl_xor(mn, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    smx[threadIdx.x >> 6] = mx;
+    smn[threadIdx.x >> 6] = mn;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < 16; ++w) {
+      mx = fmax(mx, smx[w]);
+      mn = fmin(mn, smn[w]);
+    }
+    if (!(mx <= lim * mn)) *flag = 1;
+  }
+}
+
+// --------------------------------------------------------------------------------------------------
+// Host side.
+// --------------------------------------------------------------------------------------------------
+int64_t cholqr_padded(int64_t d) { return (d + CQ_T - 1) / CQ_T * CQ_T; }
+
+static int gram_splits(int64_t m, int64_t dp) {
+  const int64_t tiles = (dp / CQ_T) * (dp / CQ_T + 1) / 2;
+  int64_t s = (1024 + tiles - 1) / tiles;  // about 1024 workgroups
+  const int64_t smax = (m + 255) / 256;    // at least 256 rows per split
+  s = s > smax ? smax : s;
+  return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
+}
+
+size_t cholqr_scratch_len(int64_t m, int64_t d) {
+  const int64_t dp = cholqr_padded(d);
+  // part (S dp^2), G, Ra, Rb, Rc, W (dp^2 each), Dinv (64^2), Q and Q2 (m dp each), shift
+  return (size_t)gram_splits(m, dp) * dp * dp + 5 * (size_t)dp * dp + CQ_T * CQ_T + 2 * (size_t)m * dp + 8;
+}
+
+static void gram(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t ldx, int64_t dp, double* part,
+                 const double* shift, double* G) {
+  const int S = gram_splits(m, dp);
+  const int64_t nt = dp / CQ_T;
+  hipLaunchKernelGGL(k_gram_part, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)S), dim3(256), 0, st, X, m, d, ldx,
+                     dp, part);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, part, S, d, dp, shift,
+                     G);
+}
+
+static void cholesky(hipStream_t st, double* G, int64_t dp, double* R, double* Dinv, int* flag) {
+  hipMemsetAsync(R, 0, (size_t)dp * dp * sizeof(double), st);
+  const int nkb = (int)(dp / CQ_T);
+  for (int kb = 0; kb < nkb; ++kb) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, G, dp, kb, R, Dinv, flag);
+    const int64_t rest = dp - (int64_t)(kb + 1) * CQ_T;
+    if (rest <= 0) break;
+    const int64_t ncb = rest / 16;
+    hipLaunchKernelGGL(k_chol_row, dim3((unsigned)((4 * ncb + 3) / 4)), dim3(256), 0, st, G, dp, kb, Dinv, R);
+    const int64_t nup = ncb * (ncb + 1) / 2;
+    hipLaunchKernelGGL(k_chol_update, dim3((unsigned)((nup + 3) / 4)), dim3(256), 0, st, G, dp, kb, R);
+  }
+}
+
+// One CholeskyQR pass on X (m x d used columns, leading dimension ldx): Rout = chol(X^T X [+ shift I])
+// padded to dp with the identity.
+static void cq_pass(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t ldx, int64_t dp, double* part,
+                    double* G, const double* shift, double* Rout, double* Dinv, int* flag) {
+  gram(st, X, m, d, ldx, dp, part, shift, G);
+  cholesky(st, G, dp, Rout, Dinv, flag);
+}
+
+int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
+                  double* R, int* flags, int* hflags, double* trinv_scratch) {
+  const int64_t dp = cholqr_padded(d);
+  const int S = gram_splits(m, dp);
+  double* part = scratch;
+  double* G = part + (size_t)S * dp * dp;
+  double* Ra = G + dp * dp;
+  double* Rb = Ra + dp * dp;
+  double* Rc = Rb + dp * dp;
+  double* Wt = Rc + dp * dp;
+  double* Dinv = Wt + dp * dp;
+  double* Q = Dinv + CQ_T * CQ_T;
+  double* Q2 = Q + (size_t)m * dp;
+  double* shift = Q2 + (size_t)m * dp;
+  const dim3 gx((unsigned)((m + CQ_T - 1) / CQ_T), (unsigned)(dp / CQ_T));
+  // pass 1, then a check that it is usable for two passes
+  hipMemsetAsync(flags, 0, 2 * sizeof(int), st);
+  cq_pass(st, SA, m, d, lds, dp, part, G, nullptr, Ra, Dinv, flags);
+  hipLaunchKernelGGL(k_chol_diagratio, dim3(1), dim3(1024), 0, st, Ra, dp, d, 1e7, flags + 1);
+  hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
+  hipStreamSynchronize(st);
+  if (hflags[0] || hflags[1]) return 1;  // caller chooses the robust path
+  // Q1 = X R1^{-1}; pass 2 on Q1; R = R2 R1
+  tri_inverse_padded(st, Ra, dp, Wt, trinv_scratch);
+  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, SA, m, d, lds, Wt, dp, Q);
+  cq_pass(st, Q, m, d, dp, dp, part, G, nullptr, Rb, Dinv, flags);
+  hipLaunchKernelGGL(k_trtr, dim3((unsigned)((dp / 16) * (dp / 16) / 4 + 1)), dim3(256), 0, st, Rb, Ra, dp, Rc);
+  hipLaunchKernelGGL(k_chol_extract, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rc, dp, d, R);
+  return 0;
+}
+
+int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
+                    double* R, int* flags, double* trinv_scratch) {
+  const int64_t dp = cholqr_padded(d);
+  const int S = gram_splits(m, dp);
+  double* part = scratch;
+  double* G = part + (size_t)S * dp * dp;
+  double* Ra = G + dp * dp;
+  double* Rb = Ra + dp * dp;
+  double* Rc = Rb + dp * dp;
+  double* Wt = Rc + dp * dp;
+  double* Dinv = Wt + dp * dp;
+  double* Q = Dinv + CQ_T * CQ_T;
+  double* Q2 = Q + (size_t)m * dp;
+  double* shift = Q2 + (size_t)m * dp;
+  const dim3 gx((unsigned)((m + CQ_T - 1) / CQ_T), (unsigned)(dp / CQ_T));
+  const unsigned gt = (unsigned)((dp / 16) * (dp / 16) / 4 + 1);
+  hipMemsetAsync(flags, 0, sizeof(int), st);
+  // shift from ||X||_F^2 = tr(X^T X), then R1 = chol(X^T X + s I)
+  gram(st, SA, m, d, lds, dp, part, nullptr, G);
+  hipLaunchKernelGGL(k_gram_shift, dim3(1), dim3(1024), 0, st, G, m, d, dp, shift);
+  hipLaunchKernelGGL(k_gram_add_shift, dim3((unsigned)((d + 255) / 256)), dim3(256), 0, st, G, d, dp, shift);
+  cholesky(st, G, dp, Ra, Dinv, flags);
+  // Q1 = X R1^{-1}, R2 = chol(Q1^T Q1), R21 = R2 R1
+  tri_inverse_padded(st, Ra, dp, Wt, trinv_scratch);
+  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, SA, m, d, lds, Wt, dp, Q);
+  cq_pass(st, Q, m, d, dp, dp, part, G, nullptr, Rb, Dinv, flags);
+  hipLaunchKernelGGL(k_trtr, dim3(gt), dim3(256), 0, st, Rb, Ra, dp, Rc);
+  // Q2 = Q1 R2^{-1}, R3 = chol(Q2^T Q2), R = R3 R21
+  tri_inverse_padded(st, Rb, dp, Wt, trinv_scratch);
+  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, Q, m, d, dp, Wt, dp, Q2);
+  cq_pass(st, Q2, m, d, dp, dp, part, G, nullptr, Ra, Dinv, flags);
+  hipLaunchKernelGGL(k_trtr, dim3(gt), dim3(256), 0, st, Ra, Rc, dp, Rb);
+  hipLaunchKernelGGL(k_chol_extract, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rb, dp, d, R);
+  return 0;
+}
+
+}  // namespace lsq

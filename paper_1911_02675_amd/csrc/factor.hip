@@ -337,12 +337,13 @@ __global__ __launch_bounds__(256) void k_trinv_out(const double* __restrict__ Wp
   }
 }
 
-void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT, double* scratch) {
-  const int64_t dp = trinv_padded(d);
-  double* Rp = scratch;
-  double* Wp = Rp + dp * dp;
-  double* Tp = Wp + dp * dp;
-  hipLaunchKernelGGL(k_trinv_pad, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, R, d, dp, Rp, Wp);
+__global__ void k_trinv_copy(const double* __restrict__ Wp, int64_t dq, int64_t dp, double* __restrict__ W) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= dp * dp) return;
+  W[idx] = Wp[(idx / dp) * dq + idx % dp];
+}
+
+static void trinv_levels(hipStream_t st, double* Rp, double* Wp, double* Tp, int64_t dp) {
   hipLaunchKernelGGL(k_trinv_diag, dim3((unsigned)(dp / 16)), dim3(64), 0, st, Rp, dp, Wp);
   for (int64_t h = 16; h < dp; h *= 2) {
     const int64_t nb = h / 16;
@@ -350,6 +351,29 @@ void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* 
     hipLaunchKernelGGL(k_trinv_level, g, dim3(256), 0, st, Rp, Wp, Tp, dp, (int)h, 0);
     hipLaunchKernelGGL(k_trinv_level, g, dim3(256), 0, st, Rp, Wp, Tp, dp, (int)h, 1);
   }
+}
+
+void tri_inverse_padded(hipStream_t st, const double* R, int64_t n, double* W, double* scratch) {
+  const int64_t dq = trinv_padded(n);
+  double* Rp = scratch;
+  double* Wp = Rp + dq * dq;
+  double* Tp = Wp + dq * dq;
+  hipLaunchKernelGGL(k_trinv_pad, dim3((unsigned)((dq * dq + 255) / 256)), dim3(256), 0, st, R, n, dq, Rp, Wp);
+  trinv_levels(st, Rp, Wp, Tp, dq);
+  hipLaunchKernelGGL(k_trinv_copy, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, Wp, dq, n, W);
+}
+
+void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status) {
+  hipLaunchKernelGGL(k_qr_rankcheck, dim3(1), dim3(1024), 0, st, R, d, status);
+}
+
+void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT, double* scratch) {
+  const int64_t dp = trinv_padded(d);
+  double* Rp = scratch;
+  double* Wp = Rp + dp * dp;
+  double* Tp = Wp + dp * dp;
+  hipLaunchKernelGGL(k_trinv_pad, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, R, d, dp, Rp, Wp);
+  trinv_levels(st, Rp, Wp, Tp, dp);
   dim3 go((unsigned)((d + 31) / 32), (unsigned)((d + 31) / 32));
   hipLaunchKernelGGL(k_trinv_out, go, dim3(256), 0, st, Wp, dp, d, W, WT);
 }

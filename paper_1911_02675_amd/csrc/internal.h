@@ -76,6 +76,25 @@ void householder_qr(hipStream_t st, const double* SA, int64_t m, int64_t d, int6
 // W = R^{-1} and WT = W^T (both d x d row-major).  scratch: trinv_scratch_len(d) doubles.
 size_t trinv_scratch_len(int64_t d);
 void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* WT, double* scratch);
+// W = R^{-1} for an n x n upper R (row-major, ld n) into W (n x n); scratch: trinv_scratch_len(n) doubles.
+void tri_inverse_padded(hipStream_t st, const double* R, int64_t n, double* W, double* scratch);
+// status |= 1 when some |R_kk| <= 8 d eps max |R_jj|.
+void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status);
+
+// ---- chol.hip -----------------------------------------------------------------------------------
+// CholeskyQR2 of SA (m x d) -> R (d x d).  flags: 2 device ints, hflags: their pinned host mirror.
+// Returns 0 on success, 1 when the first Cholesky broke down or its diagonal spread exceeds 1e7 (then
+// R is not written and the caller uses a robust path).  trinv_scratch: trinv_scratch_len(padded d).
+int64_t cholqr_padded(int64_t d);
+size_t cholqr_scratch_len(int64_t m, int64_t d);
+int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
+                  double* R, int* flags, int* hflags, double* trinv_scratch);
+// Shifted CholeskyQR3 (any full-rank SA up to kappa ~ 1/u).  flags: 1 device int.
+int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
+                    double* R, int* flags, double* trinv_scratch);
+extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder
+constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
+constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 
 // ---- iter.hip -----------------------------------------------------------------------------------
 int fused_nwg(int64_t n, int64_t d);

@@ -18,7 +18,7 @@ relative A-norm error and delta is its square.
 """
 import math
 
-FACTOR_M_MAX = 8192  # largest m the factorization accepts
+FACTOR_M_MAX = 65536  # largest m the factorization accepts
 
 
 def lambert_w0(a):
@@ -83,11 +83,16 @@ def paper_m_star(kind, n, d, tol):
 
 
 def candidates(n, d, kind):
-    """Sketch sizes the chooser considers: 1.5d .. 8d, within the factorization's limit and m <= N."""
+    """Sketch sizes the chooser considers: 1.5d .. 16d, within the factorization's limit, m <= N for the
+    SRHT and m <= 16384 for the SJLT."""
     N = 1 << max(0, (n - 1).bit_length())
-    hi = min(FACTOR_M_MAX, N if kind == "srht" else FACTOR_M_MAX)
+    hi = FACTOR_M_MAX
+    if kind == "srht":
+        hi = min(hi, N)
+    if kind == "sjlt":
+        hi = min(hi, 16384)
     out = []
-    for f in (1.5, 2, 3, 4, 5, 6, 8):
+    for f in (1.5, 2, 3, 4, 5, 6, 8, 10, 12, 16):
         m = int(round(f * d / 64.0)) * 64 if d >= 64 else int(round(f * d))
         if d < m <= hi and m not in out:
             out.append(m)
