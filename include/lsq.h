@@ -187,6 +187,9 @@ lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int6
 /* One fused pass over A (Section 1.2: each PCG step multiplies by A and A^T):
  *   mode 0: w = A^T (A v), scal = ||A v||^2            (v = p,  H p and p^T H p)
  *   mode 1: w = A^T (y - A v), scal = ||y - A v||^2    (v = x,  b - H x and the residual norm)
+ *   mode 2: as mode 1 with a_j . v, y_j - a_j . v and the sum over rows in double-double arithmetic,
+ *           rounded to FP64 once (the refinement residual of the mixed form; not the paper's, which
+ *           does not discuss precision); f32_math must be 0
  * with FP64 arithmetic (FP32 A promoted exactly), or FP32 arithmetic when f32_math = 1 (FP32 A only).
  * w (device, d), scal (device, 1). */
 lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, int32_t f32_math,

@@ -118,4 +118,5 @@ def mp_gamma(rho, mu, t, nodes=4000):
     half = 0.5 * (lp - lm)
     # sqrt((l+ - l)(l - l-)) = half * sqrt(1 - z^2), dl = half dz
     dens = half * half / (2.0 * np.pi * rho * lam)
-    return float(np.sum(w * dens * (1.0 - mu / lam) ** (2 * t)))
+    with np.errstate(over="ignore"):  # steps far past 2 lambda_- give +inf, which is the right order
+        return float(np.sum(w * dens * (1.0 - mu / lam) ** (2 * t)))

@@ -469,9 +469,18 @@ lsq_status lsq_fused_pass(lsq_ctx* c, const lsq_problem* p, int32_t mode, int32_
                           const double* v, double* w, double* scal) {
   CHK(check_problem(c, p));
   if (!v || !w || !scal) return fail(LSQ_ERR_INVALID_ARG, "null v, w or scal");
-  if (mode != 0 && mode != 1) return fail(LSQ_ERR_INVALID_ARG, "mode must be 0 or 1");
-  if (f32_math && p->a_dtype != LSQ_F32)
-    return fail(LSQ_ERR_INVALID_ARG, "f32_math needs an FP32 matrix");
+  if (mode < 0 || mode > 2) return fail(LSQ_ERR_INVALID_ARG, "mode must be 0, 1 or 2");
+  if (f32_math && (p->a_dtype != LSQ_F32 || mode == 2))
+    return fail(LSQ_ERR_INVALID_ARG, "f32_math needs an FP32 matrix and mode 0 or 1");
+  if (mode == 2) {
+    double* part;
+    CHK(wsT(c, "resid_dd", resid_dd_part_len(p->d), &part));
+    if (!resid_dd(c->st, p->A, p->a_dtype == LSQ_F32, p->n, p->d, p->lda, v, p->y, part, w, scal))
+      return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->st));
+    return LSQ_OK;
+  }
   SolveBufs b;
   CHK(solve_bufs(c, p->n, p->d, &b));
   EvPair* e = fused_event(c);
@@ -574,9 +583,12 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     // iterative refinement: outer FP64 residual, inner PCG on the correction
     double rho_b = -1.0;
     const double floor_in = o->inner_f32 ? 1e-6 : 1e-13;
+    double* rpart;
+    CHK(wsT(c, "resid_dd", resid_dd_part_len(d), &rpart));
     for (int k = 0; k < o->max_refine; ++k) {
-      const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
-      reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
+      // outer residual in double-double (rounded once), so that it stays accurate near the solution
+      if (!resid_dd(st, p->A, a_f32, p->n, d, p->lda, x, p->y, rpart, b.r, nullptr))
+        return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
       passes += 1;
       int ndot;
       precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);

@@ -4,8 +4,9 @@
 //     R1 = chol(X^T X),  Q1 = X R1^{-1},  R2 = chol(Q1^T Q1),  R = R2 R1,
 // and, when the first factorization breaks down, the shifted form with a third pass
 // (R1 = chol(X^T X + s I), s = 11 (m d + d (d + 1)) u ||X||_F^2).  Every product runs on the FP64
-// matrix cores (v_mfma_f64_16x16x4); the Cholesky is blocked by 64 columns (one workgroup factors the
-// diagonal block and inverts it, then the block row and the trailing matrix are updated in parallel).
+// matrix cores (v_mfma_f64_16x16x4); the Cholesky is blocked by 64 columns (one wavefront factors the
+// diagonal block in registers and inverts it, then the block row and the trailing matrix are updated
+// in parallel).
 // All matrices are row-major and padded to dp = 64 ceil(d / 64) columns, with the identity on the
 // padding of every Gram matrix so that the padded factors are diag(R, I).
 #include "internal.h"
@@ -126,53 +127,54 @@ __global__ __launch_bounds__(1024) void k_gram_shift(const double* __restrict__ 
 // --------------------------------------------------------------------------------------------------
 // Blocked Cholesky G = R^T R (upper), 64-column blocks.
 // --------------------------------------------------------------------------------------------------
-// Diagonal block kb: factor in LDS (column by column), write R_kk, and its inverse into Dinv (64 x 64).
-// A pivot that is not positive sets *flag and is replaced by 1 so that the factorization completes.
-__global__ __launch_bounds__(256) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
-                                                   double* __restrict__ R, double* __restrict__ Dinv,
-                                                   int* __restrict__ flag) {
-  __shared__ double T[CQ_T][CQ_LP];
-  const int tid = threadIdx.x;
+// Diagonal block kb in one wavefront: lane j holds column j of the block in registers.  Step k takes
+// the pivot from lane k, scales row k (element k of every lane), publishes it through LDS, and every
+// lane j > k subtracts r_ki r_kj from its elements k < i <= j.  Then R_kk and its inverse (column j
+// by back substitution in lane j, rows of R_kk read from LDS) are written.  A pivot that is not
+// positive sets *flag and is replaced by 1 so that the factorization completes.
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+__global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
+                                                  double* __restrict__ R, double* __restrict__ Dinv,
+                                                  int* __restrict__ flag) {
+  __shared__ double Rs[CQ_T][CQ_LP];
+  const int j = threadIdx.x;
   const int64_t o = (int64_t)kb * CQ_T;
-  for (int e = tid; e < CQ_T * CQ_T; e += 256) {
-    const int i = e / CQ_T, j = e % CQ_T;
-    T[i][j] = j >= i ? G[(o + i) * dp + o + j] : 0.0;
-  }
-  __syncthreads();
+  double a[CQ_T];
+#pragma unroll
+  for (int i = 0; i < CQ_T; ++i) a[i] = i <= j ? G[(o + i) * dp + o + j] : 0.0;
+  bool bad = false;
+#pragma unroll
   for (int k = 0; k < CQ_T; ++k) {
-    // row k: r_kk = sqrt(pivot), r_kj = t_kj / r_kk
-    const double piv = T[k][k];
-    const bool bad = !(piv > 0.0);
-    const double rkk = bad ? 1.0 : sqrt(piv);
+    const double piv = readlane_d(a[k], k);
+    bad = bad || !(piv > 0.0);
+    const double rkk = piv > 0.0 ? sqrt(piv) : 1.0;
+    const double inv = 1.0 / rkk;
+    a[k] = j == k ? rkk : (j > k ? a[k] * inv : a[k]);
+    Rs[k][j] = j >= k ? a[k] : 0.0;
     __syncthreads();
-    if (tid == 0 && bad) *flag = 1;
-    if (tid >= k && tid < CQ_T) T[k][tid] = tid == k ? rkk : T[k][tid] / rkk;
-    __syncthreads();
-    // trailing: t_ij -= r_ki r_kj for k < i <= j
-    for (int e = tid; e < CQ_T * CQ_T; e += 256) {
-      const int i = e / CQ_T, j = e % CQ_T;
-      if (i > k && j >= i) T[i][j] = fma(-T[k][i], T[k][j], T[i][j]);
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < CQ_T * CQ_T; e += 256) {
-    const int i = e / CQ_T, j = e % CQ_T;
-    R[(o + i) * dp + o + j] = T[i][j];
-  }
-  // inverse of the 64 x 64 upper block, one column per thread: R w = e_j bottom-up
-  if (tid < CQ_T) {
-    const int j = tid;
-    double w[CQ_T];
 #pragma unroll
-    for (int i = CQ_T - 1; i >= 0; --i) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = i + 1; k < CQ_T; ++k) s = fma(T[i][k], w[k], s);
-      w[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / T[i][i]);
-    }
-#pragma unroll
-    for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = w[i];
+    for (int i = k + 1; i < CQ_T; ++i)
+      if (i <= j) a[i] = fma(-Rs[k][i], a[k], a[i]);
   }
+  if (j == 0 && bad) *flag = 1;
+#pragma unroll
+  for (int i = 0; i < CQ_T; ++i) R[(o + i) * dp + o + j] = i <= j ? a[i] : 0.0;
+  // inverse, column j: R w = e_j bottom-up
+  double w[CQ_T];
+#pragma unroll
+  for (int i = CQ_T - 1; i >= 0; --i) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = i + 1; k < CQ_T; ++k) s = fma(Rs[i][k], w[k], s);
+    w[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / Rs[i][i]);
+  }
+#pragma unroll
+  for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = w[i];
 }
 
 // Block row kb: R_kj = Dinv^T G_kj for column tiles right of the diagonal block.  One wavefront per
@@ -383,7 +385,7 @@ static void cholesky(hipStream_t st, double* G, int64_t dp, double* R, double* D
   hipMemsetAsync(R, 0, (size_t)dp * dp * sizeof(double), st);
   const int nkb = (int)(dp / CQ_T);
   for (int kb = 0; kb < nkb; ++kb) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, G, dp, kb, R, Dinv, flag);
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(64), 0, st, G, dp, kb, R, Dinv, flag);
     const int64_t rest = dp - (int64_t)(kb + 1) * CQ_T;
     if (rest <= 0) break;
     const int64_t ncb = rest / 16;

@@ -135,6 +135,13 @@ void ihs_update(hipStream_t st, int64_t d, double* x, double* xprev, const doubl
 // out = sqrt(a[0] / b) style scalar helpers evaluated on the device
 void error_from_resid(hipStream_t st, const double* scal, double denom, double* out);
 
+// ---- resid.hip ----------------------------------------------------------------------------------
+// r = A^T (y - A x) in double-double, rounded once; scal (optional) = ||y - A x||^2.  part:
+// resid_dd_part_len(d) doubles.  Returns false when d is beyond the kernel's chunk limit (d <= 1024).
+size_t resid_dd_part_len(int64_t d);
+bool resid_dd(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda, const double* x,
+              const double* y, double* part, double* r, double* scal);
+
 // ---- fcg.hip ------------------------------------------------------------------------------------
 // Ring of K directions (P, HP: K x d; php: K) for the flexible CG window; see fcg.hip.
 constexpr int FCG_MAX_WINDOW = 1024;

@@ -432,15 +432,32 @@ __device__ __forceinline__ void srht_passB_tiles(const TC* __restrict__ base, in
       }
 }
 
-template <typename TC>
+// Rows of one bucket are taken QMAX tiles (16 QMAX rows) at a time, each chunk in one sweep of the
+// bucket's T block; QMAX = 4 halves the columns per wavefront to keep the accumulators in registers.
+template <typename TC, int NL, int QT>
+__device__ __forceinline__ void srht_passB_chunk(const TC* __restrict__ base, int64_t dT, int64_t jh0, int64_t jh1,
+                                                 int64_t c0, int64_t d, const int64_t* __restrict__ rows,
+                                                 const int* __restrict__ ord, int nq, int L1, int kk, int qi,
+                                                 double* __restrict__ out) {
+  bool qok[QT];
+  uint64_t khi[QT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    qok[t] = 16 * t + qi < nq;
+    khi[t] = qok[t] ? ((uint64_t)rows[ord[16 * t + qi]] >> L1) : 0ull;
+  }
+  srht_passB_tiles<TC, NL, QT>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, ord, nq);
+}
+
+template <typename TC, int WGC, int QMAX>
 __global__ __launch_bounds__(256, 2) void k_srht_passB(const TC* __restrict__ T, int64_t N2, int64_t d,
-                                                    int64_t dT, int L1, const int64_t* __restrict__ rows,
-                                                    const int* __restrict__ slot,
-                                                    const int* __restrict__ order,
-                                                    const int* __restrict__ bstart, int64_t m,
-                                                    double* __restrict__ partial) {
+                                                       int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                       const int* __restrict__ slot,
+                                                       const int* __restrict__ order,
+                                                       const int* __restrict__ bstart, int64_t m,
+                                                       double* __restrict__ partial) {
   constexpr int VW = 16 / sizeof(TC);
-  constexpr int NL = SRHT_WGC / (4 * 16 * VW);
+  constexpr int NL = WGC / (4 * 16 * VW);
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
@@ -449,20 +466,291 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB(const TC* __restrict__ T,
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int qi = lane & 15, kk = lane >> 4;
-  const int64_t c0 = (int64_t)blockIdx.z * SRHT_WGC + (int64_t)wv * (NL * 16 * VW);
+  const int64_t c0 = (int64_t)blockIdx.z * WGC + (int64_t)wv * (NL * 16 * VW);
   const TC* base = T + (int64_t)sl * N2 * dT;
   double* out = partial + (int64_t)js * m * d;
-  for (int cb = b0; cb < b1; cb += 32) {
-    const int nq = min(32, b1 - cb);
+  for (int cb = b0; cb < b1; cb += 16 * QMAX) {
+    const int nq = min(16 * QMAX, b1 - cb);
+    const int* ord = order + cb;
     if (nq <= 16) {
-      const bool qok[1] = {qi < nq};
-      const uint64_t khi[1] = {qok[0] ? ((uint64_t)rows[order[cb + qi]] >> L1) : 0ull};
-      srht_passB_tiles<TC, NL, 1>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, order + cb, nq);
+      srht_passB_chunk<TC, NL, 1>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    } else if (QMAX == 2 || nq <= 32) {
+      srht_passB_chunk<TC, NL, 2>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    } else if (nq <= 48) {
+      srht_passB_chunk<TC, NL, (QMAX > 2 ? 3 : 2)>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
     } else {
-      const bool qok[2] = {true, 16 + qi < nq};
-      const uint64_t khi[2] = {(uint64_t)rows[order[cb + qi]] >> L1,
-                               qok[1] ? ((uint64_t)rows[order[cb + 16 + qi]] >> L1) : 0ull};
-      srht_passB_tiles<TC, NL, 2>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, order + cb, nq);
+      srht_passB_chunk<TC, NL, QMAX>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    }
+  }
+}
+
+// FP32 T on the FP32 matrix cores (v_mfma_f32_16x16x4, twice the FP64 rate): chains of 4 steps (16
+// terms) accumulate in FP32 and are then added into FP64 accumulators, so the summation error stays
+// within 16 u of the sum of |T| terms on top of the 8 u of the transform (u = 2^-24), below the
+// (log2 N + 2) 2u bound of an FP32 SRHT.  One load of VW floats per lane feeds VW blocks of 16
+// columns (16 VW columns per wavefront).  Output layout of the FP32 16 x 16 result: lane l, register v
+// holds row 4 (l / 16) + v, column l % 16.
+typedef float lsq_f4v __attribute__((ext_vector_type(4)));
+
+template <int QT, int VW>
+__device__ __forceinline__ void srht_passB_tiles_f32(const float* __restrict__ base, int64_t dT, int64_t jh0,
+                                                     int64_t jh1, int64_t c0, int64_t d,
+                                                     const uint64_t (&khi)[QT], const bool (&qok)[QT], int kk,
+                                                     int qi, double* __restrict__ out,
+                                                     const int* __restrict__ ord, int nq) {
+  constexpr int PF = 4;
+  typedef typename SVec<float, VW>::t vc;
+  lsq_f4v acc32[QT][VW];
+  lsq_d4 acc64[QT][VW];
+#pragma unroll
+  for (int t = 0; t < QT; ++t)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      acc32[t][e] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+      acc64[t][e] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+    }
+  const bool colok = c0 + (int64_t)qi * VW < dT;
+  const vc* p = (const vc*)(base + c0) + qi;
+  const int64_t rstep = dT / VW;
+  vc raw[PF];
+#pragma unroll
+  for (int f = 0; f < PF; ++f) {
+    const int64_t j = jh0 + 4 * f + kk;
+    raw[f] = (j < jh1 && colok) ? __builtin_nontemporal_load(p + j * rstep) : (vc)0.f;
+  }
+  for (int64_t jh = jh0; jh < jh1; jh += 4 * PF) {
+#pragma unroll
+    for (int f = 0; f < PF; ++f) {
+      const int64_t j = jh + 4 * f + kk;
+      float a[QT];
+#pragma unroll
+      for (int t = 0; t < QT; ++t)
+        a[t] = (qok[t] && j < jh1) ? ((__popcll(khi[t] & (uint64_t)j) & 1) ? -1.f : 1.f) : 0.f;
+      const vc cur = raw[f];
+      const int64_t jn = j + 4 * PF;
+      raw[f] = (jn < jh1 && colok) ? __builtin_nontemporal_load(p + jn * rstep) : (vc)0.f;
+#pragma unroll
+      for (int e = 0; e < VW; ++e)
+#pragma unroll
+        for (int t = 0; t < QT; ++t)
+          acc32[t][e] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], cur[e], acc32[t][e], 0, 0, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < QT; ++t)
+#pragma unroll
+      for (int e = 0; e < VW; ++e) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc64[t][e][v] += (double)acc32[t][e][v];
+        acc32[t][e] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+      }
+  }
+#pragma unroll
+  for (int t = 0; t < QT; ++t)
+#pragma unroll
+    for (int e = 0; e < VW; ++e) {
+      const int64_t col = c0 + (int64_t)qi * VW + e;
+      if (col >= d) continue;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int q = 16 * t + 4 * kk + v;
+        if (q < nq) out[(int64_t)ord[q] * d + col] = acc64[t][e][v];
+      }
+    }
+}
+
+template <int QT, int VW>
+__device__ __forceinline__ void srht_passB_chunk_f32(const float* __restrict__ base, int64_t dT, int64_t jh0,
+                                                     int64_t jh1, int64_t c0, int64_t d,
+                                                     const int64_t* __restrict__ rows, const int* __restrict__ ord,
+                                                     int nq, int L1, int kk, int qi, double* __restrict__ out) {
+  bool qok[QT];
+  uint64_t khi[QT];
+#pragma unroll
+  for (int t = 0; t < QT; ++t) {
+    qok[t] = 16 * t + qi < nq;
+    khi[t] = qok[t] ? ((uint64_t)rows[ord[16 * t + qi]] >> L1) : 0ull;
+  }
+  srht_passB_tiles_f32<QT, VW>(base, dT, jh0, jh1, c0, d, khi, qok, kk, qi, out, ord, nq);
+}
+
+template <int QMAX>
+__global__ __launch_bounds__(256, 2) void k_srht_passB_f32(const float* __restrict__ T, int64_t N2, int64_t d,
+                                                           int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                           const int* __restrict__ slot,
+                                                           const int* __restrict__ order,
+                                                           const int* __restrict__ bstart, int64_t m,
+                                                           double* __restrict__ partial) {
+  const int klo = blockIdx.x;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int qi = lane & 15, kk = lane >> 4;
+  constexpr int VW = QMAX > 2 ? 2 : 4;  // four row tiles: 32 columns per wavefront keep the sums in registers
+  const int64_t c0 = (int64_t)blockIdx.z * (64 * VW) + (int64_t)wv * (16 * VW);
+  const float* base = T + (int64_t)sl * N2 * dT;
+  double* out = partial + (int64_t)js * m * d;
+  for (int cb = b0; cb < b1; cb += 16 * QMAX) {
+    const int nq = min(16 * QMAX, b1 - cb);
+    const int* ord = order + cb;
+    if (nq <= 16) {
+      srht_passB_chunk_f32<1, VW>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    } else if (QMAX == 2 || nq <= 32) {
+      srht_passB_chunk_f32<2, VW>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    } else if (nq <= 48) {
+      srht_passB_chunk_f32<(QMAX > 2 ? 3 : 2), VW>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    } else {
+      srht_passB_chunk_f32<QMAX, VW>(base, dT, jh0, jh1, c0, d, rows, ord, nq, L1, kk, qi, out);
+    }
+  }
+}
+
+// Large buckets (FP32 T): the two low bits e of k_hi are folded into a 4-point Walsh-Hadamard transform
+// of each 4 consecutive T rows.  With j_hi = 4 j_a + j_b and k_hi = 4 k_a + e,
+//     sum_{j_hi} (-1)^{k_hi . j_hi} T[j_hi] = sum_{j_a} (-1)^{k_a . j_a} U_e[j_a],
+//     U_e[j_a] = sum_{j_b < 4} (-1)^{e . j_b} T[4 j_a + j_b],
+// so the bucket's rows are grouped by e into tiles of 16, and each FP32 matrix-core step (K = 4 values
+// of j_a) consumes 16 rows of T instead of 4.  The tile list (row, k_a, e) is built in LDS once per
+// workgroup; at most SRHT_WT tiles are carried per sweep of the bucket's T block.  Each lane loads the
+// 4 rows of its j_a (two columns each, 32 columns per wavefront) and forms U_0..U_3 with 8 adds.
+// The tile list is built in parallel: one thread per row of the bucket.
+// Summation: the 4-point transform adds 2 roundings (2 u) per term to the chains of 4 steps (16 terms)
+// that are folded into FP64, so the bound stays below the (log2 N + 2) 2u of an FP32 SRHT.
+constexpr int SRHT_WT = 6;        // tiles per sweep
+constexpr int SRHT_WROWS = 192;   // rows of a bucket per tile build (larger buckets loop)
+constexpr int SRHT_WMAXT = SRHT_WROWS / 16 + 4;  // at most this many tiles per build
+
+__global__ __launch_bounds__(256, 2) void k_srht_passB_f32w(const float* __restrict__ T, int64_t N2, int64_t d,
+                                                            int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                            const int* __restrict__ slot,
+                                                            const int* __restrict__ order,
+                                                            const int* __restrict__ bstart, int64_t m,
+                                                            double* __restrict__ partial) {
+  typedef typename SVec<float, 2>::t vc;
+  __shared__ int tq[SRHT_WMAXT][16];        // order[] positions of the tile's rows (-1: empty)
+  __shared__ unsigned long long tka[SRHT_WMAXT][16];
+  __shared__ int te[SRHT_WMAXT];
+  __shared__ int ntiles;
+  const int klo = blockIdx.x;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 4 (N2 / JS >= 512)
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int qi = lane & 15, kk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.z * 128 + (int64_t)wv * 32;
+  const float* base = T + (int64_t)sl * N2 * dT;
+  double* out = partial + (int64_t)js * m * d;
+  const bool colok = c0 + (int64_t)qi * 2 < dT;
+  const vc* p = (const vc*)(base + c0) + qi;
+  const int64_t rstep = dT / 2;
+  __shared__ int cnt[4], tbase[4];
+  for (int cb = b0; cb < b1; cb += SRHT_WROWS) {
+    const int ce = min(b1, cb + SRHT_WROWS);
+    // tiles of rows grouped by e: count the groups, place each row (the order of rows inside a tile
+    // does not change any output row), empty slots stay -1
+    __syncthreads();
+    for (int i = tid; i < SRHT_WMAXT * 16; i += 256) tq[i / 16][i % 16] = -1;
+    if (tid < 4) cnt[tid] = 0;
+    __syncthreads();
+    int e_me = 0, slot_me = 0;
+    uint64_t khi_me = 0;
+    if (tid < ce - cb) {
+      khi_me = (uint64_t)rows[order[cb + tid]] >> L1;
+      e_me = (int)(khi_me & 3);
+      slot_me = atomicAdd(&cnt[e_me], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nt = 0;
+      for (int e = 0; e < 4; ++e) {
+        tbase[e] = nt;
+        const int k = (cnt[e] + 15) / 16;
+        for (int t = 0; t < k; ++t) te[nt + t] = e;
+        nt += k;
+      }
+      ntiles = nt;
+    }
+    __syncthreads();
+    if (tid < ce - cb) {
+      const int t = tbase[e_me] + slot_me / 16;
+      tq[t][slot_me % 16] = cb + tid;
+      tka[t][slot_me % 16] = khi_me >> 2;
+    }
+    __syncthreads();
+    const int nt = ntiles;
+    for (int t0 = 0; t0 < nt; t0 += SRHT_WT) {
+      lsq_f4v acc32[SRHT_WT][2];
+      lsq_d4 acc64[SRHT_WT][2];
+      bool qok[SRHT_WT];
+      uint64_t ka[SRHT_WT];
+      int et[SRHT_WT];
+#pragma unroll
+      for (int t = 0; t < SRHT_WT; ++t) {
+        const bool tv = t0 + t < nt;
+        const int q = tv ? tq[t0 + t][qi] : -1;
+        qok[t] = q >= 0;
+        ka[t] = qok[t] ? tka[t0 + t][qi] : 0ull;
+        et[t] = tv ? te[t0 + t] : 0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          acc32[t][e] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+          acc64[t][e] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+        }
+      }
+      // j_a runs over [jh0/4, jh1/4); a step covers 4 consecutive j_a (lane group kk takes one)
+      const int64_t ja0 = jh0 >> 2, ja1 = jh1 >> 2;
+      for (int64_t jb = ja0; jb < ja1; jb += 16) {
+#pragma unroll
+        for (int f = 0; f < 4; ++f) {
+          const int64_t ja = jb + 4 * f + kk;
+          vc r[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b)
+            r[b] = (ja < ja1 && colok) ? __builtin_nontemporal_load(p + (4 * ja + b) * rstep) : (vc)0.f;
+          vc u[4];
+          const vc s01 = r[0] + r[1], d01 = r[0] - r[1], s23 = r[2] + r[3], d23 = r[2] - r[3];
+          u[0] = s01 + s23;
+          u[1] = d01 + d23;
+          u[2] = s01 - s23;
+          u[3] = d01 - d23;
+#pragma unroll
+          for (int t = 0; t < SRHT_WT; ++t) {
+            if (t0 + t >= nt) break;  // uniform
+            const float a = (qok[t] && ja < ja1) ? ((__popcll(ka[t] & (uint64_t)ja) & 1) ? -1.f : 1.f) : 0.f;
+            const int e = et[t];
+            const vc ue = e == 0 ? u[0] : (e == 1 ? u[1] : (e == 2 ? u[2] : u[3]));
+#pragma unroll
+            for (int c = 0; c < 2; ++c)
+              acc32[t][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, ue[c], acc32[t][c], 0, 0, 0);
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < SRHT_WT; ++t)
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[t][c][v] += (double)acc32[t][c][v];
+            acc32[t][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+          }
+      }
+#pragma unroll
+      for (int t = 0; t < SRHT_WT; ++t) {
+        if (t0 + t >= nt) break;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int64_t col = c0 + (int64_t)qi * 2 + c;
+          if (col >= d) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = tq[t0 + t][4 * kk + v];
+            if (q >= 0) out[(int64_t)order[q] * d + col] = acc64[t][c][v];
+          }
+        }
+      }
     }
   }
 }
@@ -521,9 +809,30 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                        n, d, lda, (int)p.N1, signs, slot, p.N2, dT, T);
   }
   const int JS = srht_js(p.N2);
-  dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + SRHT_WGC - 1) / SRHT_WGC));
-  hipLaunchKernelGGL((k_srht_passB<TC>), gb, dim3(256), 0, st, T, p.N2, d, dT, L1, rows, slot, order, bstart,
-                     p.m, partial);
+  // buckets of more than about 24 selected rows on average: 64-row chunks (one sweep of T per bucket)
+  const bool big = p.m > 24 * p.N1;
+  if constexpr (sizeof(TC) == 4) {
+    const int64_t wgc = big ? 128 : 256;  // 64 VW columns per workgroup
+    dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + wgc - 1) / wgc));
+    if (big && p.N2 >= 512)
+      hipLaunchKernelGGL(k_srht_passB_f32w, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
+                         order, bstart, p.m, partial);
+    else if (big)
+      hipLaunchKernelGGL(k_srht_passB_f32<4>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
+                         order, bstart, p.m, partial);
+    else
+      hipLaunchKernelGGL(k_srht_passB_f32<2>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
+                         order, bstart, p.m, partial);
+  } else if (big) {
+    constexpr int WGC = SRHT_WGC / 2;
+    dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + WGC - 1) / WGC));
+    hipLaunchKernelGGL((k_srht_passB<TC, WGC, 4>), gb, dim3(256), 0, st, T, p.N2, d, dT, L1, rows, slot, order,
+                       bstart, p.m, partial);
+  } else {
+    dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + SRHT_WGC - 1) / SRHT_WGC));
+    hipLaunchKernelGGL((k_srht_passB<TC, SRHT_WGC, 2>), gb, dim3(256), 0, st, T, p.N2, d, dT, L1, rows, slot, order,
+                       bstart, p.m, partial);
+  }
   hipLaunchKernelGGL(k_srht_final, dim3((unsigned)((p.m * d + 255) / 256)), dim3(256), 0, st, partial, JS,
                      p.m, d, 1.0 / sqrt((double)p.m), SA, ldsa);
 }

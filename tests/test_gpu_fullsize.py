@@ -41,9 +41,9 @@ def big():
     ctx.close()
 
 
-def _sketch(big, A, y, desc):
+def _sketch(big, A, y, desc, m=M):
     import torch
-    SA = torch.zeros((M, D), dtype=torch.float64, device="cuda")
+    SA = torch.zeros((m, D), dtype=torch.float64, device="cuda")
     big["ctx"].sketch(A, y, desc, SA)
     torch.cuda.synchronize()
     return SA.cpu().numpy()
@@ -53,17 +53,19 @@ COLS = np.arange(0, D, 16)  # 64 sampled columns
 ROWS = [0, 1, 2047, 4095]
 
 
-@pytest.mark.parametrize("compute", ["f64", "f32"])
-def test_fullsize_srht_rows(big, compute):
+@pytest.mark.parametrize("compute,m", [("f64", M), ("f32", M), ("f32", 6 * M)])
+def test_fullsize_srht_rows(big, compute, m):
+    """m = 4096 and the chooser's 24d (buckets of about 96 selected rows: the folded pass B)."""
     from oracle.draws import padded_length, srht_rows, srht_signs
     from oracle.sketch import hadamard_entry, srht_sketch_rows
     from paper_1911_02675_amd import lsq
     A = big["P"]["A64"] if compute == "f64" else big["P"]["A32"].astype(np.float64)
     Ad, yd = (big["A64"], big["y64"]) if compute == "f64" else (big["A32"], big["y32"])
-    got = _sketch(big, Ad, yd, lsq.sketch_desc("srht", M, seed=SEED, compute=compute))[np.ix_(ROWS, COLS)]
-    ref = srht_sketch_rows(A, M, SEED, 0, ROWS, cols=COLS)
+    rows = [0, 1, m // 2 - 1, m - 1]
+    got = _sketch(big, Ad, yd, lsq.sketch_desc("srht", m, seed=SEED, compute=compute), m)[np.ix_(rows, COLS)]
+    ref = srht_sketch_rows(A, m, SEED, 0, rows, cols=COLS)
     # any summation order of n signed terms: |error| <= (log2 N + 2) eps sum |a_j| / sqrt(m)
-    absum = np.abs(A[:, COLS]).sum(axis=0)[None, :] / np.sqrt(M)
+    absum = np.abs(A[:, COLS]).sum(axis=0)[None, :] / np.sqrt(m)
     eps = EPS64 if compute == "f64" else EPS32
     bound = (np.log2(padded_length(N_ROWS)) + 2) * eps * absum
     say(f"  SRHT {compute}: max err / bound {np.max(np.abs(got - ref) / bound):.3f}")
