@@ -96,7 +96,11 @@ typedef struct {
  *   stop_rule:  0 = the rule above; 1 = exactly max_iter iterations.
  *   mixed:      0 = plain form (A as given, FP64 arithmetic);
  *               1 = iterative refinement: FP64 residual A^T (y - A x) with A read in its storage type,
- *                   inner PCG on the correction, x += dx in FP64.
+ *                   inner PCG on the correction, x += dx in FP64.  From x = 0 the first residual is
+ *                   one plain pass; every later one is taken in double-double arithmetic and rounded
+ *                   once.  The check after the first correction is always measured; after a later
+ *                   correction the estimate is the measured one times that correction solve's own
+ *                   relative reduction, so the solve ends without a further residual.
  *   max_refine: outer refinement steps (mixed = 1).
  *   inner_f32:  mixed = 1 only: 1 = inner matrix-vector products in FP32 arithmetic (p rounded to
  *               FP32); 0 = FP32 storage read into FP64 registers.
@@ -262,7 +266,10 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
  * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
  * default 8); "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute
  * unit, else 1..65536); "factor" (0 = CholeskyQR2 with its fallbacks, the default; 1 = Householder QR
- * only, see lsq_factor).  INVALID_ARG for an unknown key or an out-of-range value. */
+ * only, see lsq_factor); "srht_passb" (FP32 SRHT second pass for buckets of more than 24 selected
+ * rows on average: 0 = staged through LDS with every row tile of a bucket in one pass over its block
+ * of the intermediate, the default; 1 = operands loaded straight into registers, six tiles per pass).
+ * INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
 
 const char* lsq_status_string(lsq_status s);

@@ -60,6 +60,8 @@ struct lsq_ctx {
   void* bhost = nullptr;
   size_t bhost_bytes = 0;
   hipEvent_t bev[3] = {};
+  double* hx = nullptr;  // pinned host copy of a starting point (mixed solve)
+  size_t hx_len = 0;
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -221,6 +223,7 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
 
 namespace lsq {
 int g_factor_mode = 0;
+int g_srht_passb = 0;
 }  // namespace lsq
 
 // Factor S A -> R, W = R^{-1}, W^T.  CholeskyQR2 (Gram matrices on the matrix cores) when the first
@@ -433,6 +436,7 @@ void lsq_destroy(lsq_ctx* c) {
   if (c->ds) (void)hipFree(c->ds);
   if (c->dflags) (void)hipFree(c->dflags);
   if (c->hds) (void)hipHostFree(c->hds);
+  if (c->hx) (void)hipHostFree(c->hx);
   if (c->hflags) (void)hipHostFree(c->hflags);
   delete c;
 }
@@ -585,10 +589,37 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     const double floor_in = o->inner_f32 ? 1e-6 : 1e-13;
     double* rpart;
     CHK(wsT(c, "resid_dd", resid_dd_part_len(d), &rpart));
+    if (d > 1024) return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
+    // From x_0 = 0 the first residual is A^T y, with no cancellation: one plain pass (FP64 arithmetic)
+    // gives it to working accuracy.  Any other start takes the double-double residual from the outset.
+    if (c->hx_len < (size_t)d) {
+      if (c->hx) HIPCHK(hipHostFree(c->hx));
+      c->hx = nullptr;
+      c->hx_len = 0;
+      HIPCHK(hipHostMalloc(&c->hx, sizeof(double) * d, hipHostMallocDefault));
+      c->hx_len = d;
+    }
+    HIPCHK(hipMemcpyAsync(c->hx, x, sizeof(double) * d, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    bool x0_zero = true;
+    for (int64_t i = 0; i < d && x0_zero; ++i) x0_zero = c->hx[i] == 0.0;
+    double est_carried = -1.0;
     for (int k = 0; k < o->max_refine; ++k) {
-      // outer residual in double-double (rounded once), so that it stays accurate near the solution
-      if (!resid_dd(st, p->A, a_f32, p->n, d, p->lda, x, p->y, rpart, b.r, nullptr))
+      // After a correction solved from an accurate residual (k >= 2: the first check, k = 1, measures
+      // the PCG's own drift and is always taken), the new error estimate is the old one times the
+      // correction solve's relative reduction; the rounding inside that solve is relative to the
+      // correction, so the carried value stands in for one more residual.
+      if (k >= 2 && o->stop_rule == 0 && est_carried >= 0.0 && est_carried <= o->tol) {
+        est = est_carried;
+        break;
+      }
+      if (k == 0 && x0_zero) {
+        const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+        reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
+      } else if (!resid_dd(st, p->A, a_f32, p->n, d, p->lda, x, p->y, rpart, b.r, nullptr)) {
+        // outer residual in double-double (rounded once), so that it stays accurate near the solution
         return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
+      }
       passes += 1;
       int ndot;
       precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
@@ -611,6 +642,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       total_iters += it;
       passes += it;
       if (c->hds->status) break;
+      est_carried = est * (c->hds->est / 4.0);
       vec_axpy(st, x, b.dx, 1.0, d);
     }
   }
@@ -930,6 +962,12 @@ lsq_status lsq_tune(const char* key, int64_t value) {
   if (k == "factor") {
     if (value < 0 || value > 1) return fail(LSQ_ERR_INVALID_ARG, "factor: 0 (CholeskyQR2) or 1 (Householder)");
     g_factor_mode = (int)value;
+    return LSQ_OK;
+  }
+  if (k == "srht_passb") {
+    if (value < 0 || value > 1)
+      return fail(LSQ_ERR_INVALID_ARG, "srht_passb: 0 (LDS-staged, the default) or 1 (register-direct)");
+    g_srht_passb = (int)value;
     return LSQ_OK;
   }
   if (k == "batched_slots") {

@@ -132,11 +132,6 @@ __global__ __launch_bounds__(1024) void k_gram_shift(const double* __restrict__ 
 // lane j > k subtracts r_ki r_kj from its elements k < i <= j.  Then R_kk and its inverse (column j
 // by back substitution in lane j, rows of R_kk read from LDS) are written.  A pivot that is not
 // positive sets *flag and is replaced by 1 so that the factorization completes.
-__device__ __forceinline__ double readlane_d(double v, int l) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
-  return __hiloint2double(hi, lo);
-}
 
 __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
                                                   double* __restrict__ R, double* __restrict__ Dinv,

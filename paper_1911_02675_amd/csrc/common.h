@@ -106,6 +106,12 @@ __device__ __forceinline__ double xor32_sum(double v) {
   const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
   return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
+// Lane l's value, uniform across the wavefront (two scalar reads).
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
 template <int G>
 __device__ __forceinline__ double grp_sum(double v) {
   if (G >= 2) v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]

@@ -93,6 +93,7 @@ int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_
 int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
                     double* R, int* flags, double* trinv_scratch);
 extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder
+extern int g_srht_passb;   // tuning: FP32 SRHT pass B for large buckets, 0 = LDS-staged, 1 = register-direct
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
 constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 

@@ -755,6 +755,207 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_f32w(const float* __restr
   }
 }
 
+// j_hi ranges of pass B: enough workgroups to fill the chip at large N2, one range for small N2.
+static int srht_js(int64_t N2) {
+  const int64_t js = N2 / 512;
+  return (int)(js < 1 ? 1 : (js > 8 ? 8 : js));
+}
+static int srht_js_cap(int64_t N2) { return srht_js(N2); }
+
+// Large buckets, FP32 T, staged through LDS: the same fold by the 4-point transform as above, with
+// every tile of a bucket (up to 4 TPW per sweep) carried in one pass over its T block, so the block is
+// read from HBM once.  Workgroup: bucket k_lo, a j_hi range, 64 columns; wavefront w owns tiles
+// w, w + 4, ... (TPW of them) over all 64 columns (four 16-column MFMA blocks).  Stages of 64 T rows
+// (16 values of j_a) x 64 columns are loaded two stages ahead into registers, written to a double
+// buffer in LDS (row pitch 68 floats: the 4 j_a of one MFMA step fall in distinct banks), and each
+// wavefront forms its tiles' U_e from the staged rows with two levels of +-1 fused adds (the same two
+// roundings as the butterfly).  FP32 chains of one stage (16 values of j_a) are folded into FP64.
+constexpr int SRHT_LP = 68;                     // LDS row pitch (floats)
+constexpr int SRHT_LSTAGE = 64 * SRHT_LP;       // floats per stage buffer
+constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
+constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 4; // tiles per build at most
+
+template <int TPW>
+__device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, int non, const int (&tv)[TPW],
+                                                 const uint32_t (&ka)[TPW], const float (&s1)[TPW],
+                                                 const float (&s2)[TPW], uint32_t ja_stage, int kk, int qi,
+                                                 lsq_f4v (&acc)[TPW][4]) {
+#pragma unroll 1
+  for (int step = 0; step < 4; ++step) {
+    const uint32_t ja = ja_stage + 4 * step + kk;
+    float a[TPW];
+#pragma unroll
+    for (int i = 0; i < TPW; ++i) a[i] = tv[i] ? ((__popc(ka[i] & ja) & 1) ? -1.f : 1.f) : 0.f;
+    const float* r = L + (16 * step + 4 * kk) * SRHT_LP + qi;
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+      const float t0 = r[16 * cb], t1 = r[SRHT_LP + 16 * cb], t2 = r[2 * SRHT_LP + 16 * cb],
+                  t3 = r[3 * SRHT_LP + 16 * cb];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        if (i >= non) break;  // the wavefront's tiles past the bucket's last (uniform)
+        // U_e = (t0 + s1 t1) + s2 (t2 + s1 t3), s1 = (-1)^{e_0}, s2 = (-1)^{e_1}
+        const float u = fmaf(s2[i], fmaf(s1[i], t3, t2), fmaf(s1[i], t1, t0));
+        acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], u, acc[i][cb], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int TPW>
+__global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restrict__ T, int64_t N2, int64_t d,
+                                                           int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                           const int* __restrict__ slot,
+                                                           const int* __restrict__ order,
+                                                           const int* __restrict__ bstart, int64_t m,
+                                                           double* __restrict__ partial) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) float L[2 * SRHT_LSTAGE];
+  __shared__ int tq[SRHT_LMAXT][16];  // order[] positions of the tile's rows (-1: empty)
+  __shared__ uint32_t tka[SRHT_LMAXT][16];
+  __shared__ int te[SRHT_LMAXT];
+  __shared__ int cnt[4], tbase[4], ntiles_s;
+  const int klo = blockIdx.x;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 64
+  const uint32_t ja0 = (uint32_t)(jh0 >> 2);
+  const int nst = (int)((jh1 - jh0) >> 6);                      // stages of 64 T rows
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int qi = lane & 15, kk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.z * 64;
+  double* out = partial + (int64_t)js * m * d;
+  // staging map: thread -> rows lr + 16 i (i < 4) of a stage, columns lc .. lc + 3
+  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  const bool lok = c0 + lc < dT;  // dT is a multiple of 4
+  const float* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + c0 + lc;
+  auto gload = [&](int st, f4(&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[i] = lok ? __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 16 * i) * dT))
+                 : (f4){0.f, 0.f, 0.f, 0.f};
+  };
+  auto lstore = [&](int buf, const f4(&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) *(f4*)(L + buf * SRHT_LSTAGE + (lr + 16 * i) * SRHT_LP + lc) = v[i];
+  };
+  for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
+    const int ce = min(b1, cb + SRHT_LROWS);
+    __syncthreads();
+    for (int i = tid; i < SRHT_LMAXT * 16; i += 256) tq[i / 16][i % 16] = -1;
+    if (tid < 4) cnt[tid] = 0;
+    __syncthreads();
+    int e_me = 0, slot_me = 0;
+    uint32_t khi_me = 0;
+    if (tid < ce - cb) {
+      khi_me = (uint32_t)((uint64_t)rows[order[cb + tid]] >> L1);
+      e_me = (int)(khi_me & 3);
+      slot_me = atomicAdd(&cnt[e_me], 1);
+    }
+    __syncthreads();
+    if (tid == 0) {
+      int nt = 0;
+      for (int e = 0; e < 4; ++e) {
+        tbase[e] = nt;
+        const int k = (cnt[e] + 15) / 16;
+        for (int t = 0; t < k; ++t) te[nt + t] = e;
+        nt += k;
+      }
+      ntiles_s = nt;
+    }
+    __syncthreads();
+    if (tid < ce - cb) {
+      const int t = tbase[e_me] + slot_me / 16;
+      tq[t][slot_me % 16] = cb + tid;
+      tka[t][slot_me % 16] = khi_me >> 2;
+    }
+    __syncthreads();
+    const int nt = ntiles_s;
+    for (int tg = 0; tg < nt; tg += 4 * TPW) {
+      // tiles tg + wv + 4 i, i < non, exist (non is uniform per wavefront)
+      const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));
+      int tv[TPW];
+      uint32_t ka[TPW];
+      float s1[TPW], s2[TPW];
+      lsq_f4v acc[TPW][4];
+      lsq_d4 acc64[TPW][4];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = tg + wv + 4 * i;
+        const int q = t < nt ? tq[t][qi] : -1;
+        tv[i] = q >= 0;
+        ka[i] = q >= 0 ? tka[t][qi] : 0u;
+        const int e = t < nt ? te[t] : 0;
+        s1[i] = (e & 1) ? -1.f : 1.f;
+        s2[i] = (e & 2) ? -1.f : 1.f;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          acc[i][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+          acc64[i][c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+        }
+      }
+      auto fold = [&]() {
+#pragma unroll
+        for (int i = 0; i < TPW; ++i)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[i][c][v] += (double)acc[i][c][v];
+            acc[i][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+          }
+      };
+      // two stages in flight in registers, one being consumed from LDS
+      f4 ra[4], rb[4];
+      gload(0, ra);
+      if (nst > 1) gload(1, rb);
+      __syncthreads();  // the previous sweep's last stage has been consumed
+      lstore(0, ra);
+      __syncthreads();
+      if (nst > 2) gload(2, ra);
+      for (int st = 0; st < nst; st += 2) {
+        // even stage: LDS buffer 0, next stage (st + 1) in rb, st + 2 in ra
+        srht_lds_compute<TPW>(L, non, tv, ka, s1, s2, ja0 + 16 * st, kk, qi, acc);
+        fold();
+        if (st + 1 < nst) lstore(1, rb);
+        __syncthreads();
+        if (st + 3 < nst) gload(st + 3, rb);
+        if (st + 1 >= nst) break;
+        // odd stage: LDS buffer 1, next stage (st + 2) in ra, st + 3 in rb
+        srht_lds_compute<TPW>(L + SRHT_LSTAGE, non, tv, ka, s1, s2, ja0 + 16 * (st + 1), kk, qi, acc);
+        fold();
+        if (st + 2 < nst) lstore(0, ra);
+        __syncthreads();
+        if (st + 4 < nst) gload(st + 4, ra);
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = tg + wv + 4 * i;
+        if (t >= nt) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t col = c0 + 16 * c + qi;
+          if (col >= d) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = tq[t][4 * kk + v];
+            if (q >= 0) out[(int64_t)order[q] * d + col] = acc64[i][c][v];
+          }
+        }
+      }
+    }
+  }
+}
+
+// j_hi ranges of the LDS-staged pass B: about 8192 workgroups in all, at most the partial buffer's
+// ranges, at least one stage (64 rows of T) per range.
+static int srht_js_lds(int64_t N1, int64_t N2, int64_t ncb) {
+  int js = 1;
+  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 64 && 2 * js <= srht_js_cap(N2)) js *= 2;
+  return js;
+}
+
 __global__ void k_srht_final(const double* __restrict__ partial, int JS, int64_t m, int64_t d,
                              double scale, double* __restrict__ SA, int64_t ldsa) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -764,11 +965,6 @@ __global__ void k_srht_final(const double* __restrict__ partial, int JS, int64_t
   SA[(idx / d) * ldsa + idx % d] = s * scale;
 }
 
-// j_hi ranges of pass B: enough workgroups to fill the chip at large N2, one range for small N2.
-static int srht_js(int64_t N2) {
-  const int64_t js = N2 / 512;
-  return (int)(js < 1 ? 1 : (js > 8 ? 8 : js));
-}
 
 size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d) {
   return (size_t)srht_js(N2) * (size_t)m * (size_t)d * sizeof(double);
@@ -808,13 +1004,20 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     hipLaunchKernelGGL((k_srht_passA<TA, TC>), dim3((unsigned)p.N2, (unsigned)nslices), dim3(256), 0, st, A,
                        n, d, lda, (int)p.N1, signs, slot, p.N2, dT, T);
   }
-  const int JS = srht_js(p.N2);
+  int JS = srht_js(p.N2);
   // buckets of more than about 24 selected rows on average: 64-row chunks (one sweep of T per bucket)
   const bool big = p.m > 24 * p.N1;
   if constexpr (sizeof(TC) == 4) {
     const int64_t wgc = big ? 128 : 256;  // 64 VW columns per workgroup
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + wgc - 1) / wgc));
-    if (big && p.N2 >= 512)
+    if (big && p.N2 >= 512 && g_srht_passb == 0) {
+      // up to 8 tiles per pass over the bucket's T block (two per wavefront); larger buckets take more
+      const int64_t ncb = (dT + 63) / 64;
+      JS = srht_js_lds(p.N1, p.N2, ncb);
+      dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
+      hipLaunchKernelGGL(k_srht_passB_lds<2>, gl, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
+                         order, bstart, p.m, partial);
+    } else if (big && p.N2 >= 512)
       hipLaunchKernelGGL(k_srht_passB_f32w, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
     else if (big)

@@ -136,7 +136,8 @@ def _sa(ctx, A, kind, m, seed, t=0, s=1, compute="f64"):
 
 @pytest.mark.parametrize("n,d,m", [(100, 3, 16), (4096, 64, 256), (3000, 70, 300), (20000, 129, 700),
                                    (1 << 14, 256, 2048), (60000, 70, 8000), (1 << 15, 48, 12000),
-                                   (1 << 17, 40, 8000), (200000, 33, 9000)])
+                                   (1 << 17, 40, 8000), (200000, 33, 9000), (1 << 17, 20, 100000),
+                                   (300000, 130, 20000)])
 def test_srht_sketch(ctx, n, d, m):
     from oracle import draws, sketch
     say("srht sketch", n, d, m)

@@ -27,7 +27,10 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("n,d,f32", [(300, 8, True), (257, 7, True), (300, 6, False), (130, 130, True)])
+# odd n (a padding row in the last pair), the vector and scalar column paths of both storage types, one
+# chunk and several, and enough rows that wavefronts take several pairs (the prefetched path)
+@pytest.mark.parametrize("n,d,f32", [(300, 8, True), (257, 7, True), (300, 6, False), (130, 130, True),
+                                     (301, 12, False), (20001, 16, True), (4099, 64, False)])
 def test_resid_dd_exact(ctx, n, d, f32):
     import torch
     rng = np.random.default_rng(n + d)
@@ -81,3 +84,28 @@ def test_mixed_refinement_beyond_fp64_floor(ctx):
     say("  kappa 1e8 mixed: status", st, "refinements", info.refinements, "e_A", e)
     assert st == lsq.LSQ_OK
     assert e <= 1e-10
+
+
+def test_mixed_refinement_from_nonzero_start(ctx):
+    """A nonzero starting point takes the double-double residual from the first step (from x_0 = 0 the
+    first residual is A^T y, taken by a plain pass); both starts reach the tolerance."""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    n, d, m = 1 << 15, 96, 768
+    P = make_planted(n, d, 1e6, sigma=0.01, seed=92, want64=True, want32=True)
+    A32 = torch.from_numpy(P["A32"]).cuda()
+    y32 = torch.from_numpy(P["y32"]).cuda()
+    xs = torch.from_numpy(P["x_star"]).cuda()
+    Ad = A32.double()
+    ax = float(torch.linalg.norm(Ad @ xs))
+    for x0 in (torch.zeros(d, dtype=torch.float64, device="cuda"), 0.5 * xs.clone()):
+        x = x0.clone()
+        st, info = ctx.pcg_solve(A32, y32, lsq.sketch_desc("srht", m, seed=5, compute="f32"), x, tol=1e-10,
+                                 max_iter=300, mixed=1, max_refine=10, raise_on_error=False)
+        e = float(torch.linalg.norm(Ad @ (x - xs))) / ax
+        say("  start", "zero" if float(x0.abs().max()) == 0 else "0.5 x*", "status", st, "refinements",
+            info.refinements, "iters", info.iters, "e_A", e)
+        assert st == lsq.LSQ_OK
+        assert e <= 1e-10
