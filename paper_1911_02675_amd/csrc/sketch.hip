@@ -158,9 +158,9 @@ __device__ __forceinline__ void fwht_regs(T (&x)[V]) {
 // transforming the current one.
 template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A, int64_t n, int64_t d,
-                                                        int64_t lda, const int8_t* __restrict__ signs,
-                                                        const int* __restrict__ slot, int64_t N2,
-                                                        int64_t dT, TC* __restrict__ T) {
+                                                            int64_t lda, const int8_t* __restrict__ signs,
+                                                            const int* __restrict__ slot, int64_t N2,
+                                                            int64_t dT, TC* __restrict__ T) {
   constexpr int VW = 16 / sizeof(TC);
   typedef typename SVec<TA, VW>::t va;
   typedef typename SVec<TC, VW>::t vc;
@@ -775,6 +775,52 @@ constexpr int SRHT_LSTAGE = 64 * SRHT_LP;       // floats per stage buffer
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
 constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 4; // tiles per build at most
 
+// Row tiles of one chunk [cb, ce) of a bucket's selected rows (ce - cb <= SRHT_LROWS), grouped by
+// e = k_hi & 3 in tiles of 16 (the order of rows inside a tile does not change any output row; empty
+// slots stay -1): one thread per row places itself with an LDS counter per group.  All threads of the
+// workgroup call it; returns the tile count.
+struct SrhtTiles {
+  int tq[SRHT_LMAXT][16];        // order[] positions of the tile's rows (-1: empty)
+  uint32_t tka[SRHT_LMAXT][16];  // k_a = k_hi >> 2 of each row
+  int te[SRHT_LMAXT];            // e of the tile
+  int cnt[4], tbase[4], nt;
+};
+
+__device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, const int64_t* __restrict__ rows,
+                                               const int* __restrict__ order, int L1) {
+  const int tid = threadIdx.x;
+  __syncthreads();  // the previous chunk's tiles are no longer read
+  for (int i = tid; i < SRHT_LMAXT * 16; i += blockDim.x) S.tq[i / 16][i % 16] = -1;
+  if (tid < 4) S.cnt[tid] = 0;
+  __syncthreads();
+  int e_me = 0, slot_me = 0;
+  uint32_t khi_me = 0;
+  if (tid < ce - cb) {
+    khi_me = (uint32_t)((uint64_t)rows[order[cb + tid]] >> L1);
+    e_me = (int)(khi_me & 3);
+    slot_me = atomicAdd(&S.cnt[e_me], 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int nt = 0;
+    for (int e = 0; e < 4; ++e) {
+      S.tbase[e] = nt;
+      const int k = (S.cnt[e] + 15) / 16;
+      for (int t = 0; t < k; ++t) S.te[nt + t] = e;
+      nt += k;
+    }
+    S.nt = nt;
+  }
+  __syncthreads();
+  if (tid < ce - cb) {
+    const int t = S.tbase[e_me] + slot_me / 16;
+    S.tq[t][slot_me % 16] = cb + tid;
+    S.tka[t][slot_me % 16] = khi_me >> 2;
+  }
+  __syncthreads();
+  return S.nt;
+}
+
 template <int TPW>
 __device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, int non, const int (&tv)[TPW],
                                                  const uint32_t (&ka)[TPW], const float (&s1)[TPW],
@@ -811,10 +857,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
                                                            double* __restrict__ partial) {
   typedef float f4 __attribute__((ext_vector_type(4)));
   __shared__ __attribute__((aligned(16))) float L[2 * SRHT_LSTAGE];
-  __shared__ int tq[SRHT_LMAXT][16];  // order[] positions of the tile's rows (-1: empty)
-  __shared__ uint32_t tka[SRHT_LMAXT][16];
-  __shared__ int te[SRHT_LMAXT];
-  __shared__ int cnt[4], tbase[4], ntiles_s;
+  __shared__ SrhtTiles S;
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
@@ -842,37 +885,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
     for (int i = 0; i < 4; ++i) *(f4*)(L + buf * SRHT_LSTAGE + (lr + 16 * i) * SRHT_LP + lc) = v[i];
   };
   for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
-    const int ce = min(b1, cb + SRHT_LROWS);
-    __syncthreads();
-    for (int i = tid; i < SRHT_LMAXT * 16; i += 256) tq[i / 16][i % 16] = -1;
-    if (tid < 4) cnt[tid] = 0;
-    __syncthreads();
-    int e_me = 0, slot_me = 0;
-    uint32_t khi_me = 0;
-    if (tid < ce - cb) {
-      khi_me = (uint32_t)((uint64_t)rows[order[cb + tid]] >> L1);
-      e_me = (int)(khi_me & 3);
-      slot_me = atomicAdd(&cnt[e_me], 1);
-    }
-    __syncthreads();
-    if (tid == 0) {
-      int nt = 0;
-      for (int e = 0; e < 4; ++e) {
-        tbase[e] = nt;
-        const int k = (cnt[e] + 15) / 16;
-        for (int t = 0; t < k; ++t) te[nt + t] = e;
-        nt += k;
-      }
-      ntiles_s = nt;
-    }
-    __syncthreads();
-    if (tid < ce - cb) {
-      const int t = tbase[e_me] + slot_me / 16;
-      tq[t][slot_me % 16] = cb + tid;
-      tka[t][slot_me % 16] = khi_me >> 2;
-    }
-    __syncthreads();
-    const int nt = ntiles_s;
+    const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
     for (int tg = 0; tg < nt; tg += 4 * TPW) {
       // tiles tg + wv + 4 i, i < non, exist (non is uniform per wavefront)
       const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));
@@ -884,10 +897,10 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
         const int t = tg + wv + 4 * i;
-        const int q = t < nt ? tq[t][qi] : -1;
+        const int q = t < nt ? S.tq[t][qi] : -1;
         tv[i] = q >= 0;
-        ka[i] = q >= 0 ? tka[t][qi] : 0u;
-        const int e = t < nt ? te[t] : 0;
+        ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
+        const int e = t < nt ? S.te[t] : 0;
         s1[i] = (e & 1) ? -1.f : 1.f;
         s2[i] = (e & 2) ? -1.f : 1.f;
 #pragma unroll
@@ -939,8 +952,130 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
           if (col >= d) continue;
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
-            const int q = tq[t][4 * kk + v];
+            const int q = S.tq[t][4 * kk + v];
             if (q >= 0) out[(int64_t)order[q] * d + col] = acc64[i][c][v];
+          }
+        }
+      }
+    }
+  }
+}
+
+// The same for FP64 T (no FP32 chains to fold: the tiles accumulate in FP64 directly, so a wavefront
+// carries up to TPW = 4 tiles).  Stages of 32 T rows (8 values of j_a, two MFMA steps) x 64 columns,
+// row pitch 68 doubles (the four j_a of a step fall in the two bank halves, two lane groups each).
+// v_mfma_f64_16x16x4: A and B operands as in the FP32 form; result lane l, register v holds tile row
+// l / 16 + 4 v, column l % 16 of its block.
+constexpr int SRHT_LP64 = 68;                    // LDS row pitch (doubles)
+constexpr int SRHT_LSTAGE64 = 32 * SRHT_LP64;    // doubles per stage buffer
+
+template <int TPW>
+__global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __restrict__ T, int64_t N2, int64_t d,
+                                                             int64_t dT, int L1, const int64_t* __restrict__ rows,
+                                                             const int* __restrict__ slot,
+                                                             const int* __restrict__ order,
+                                                             const int* __restrict__ bstart, int64_t m,
+                                                             double* __restrict__ partial) {
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ __attribute__((aligned(16))) double L[2 * SRHT_LSTAGE64];
+  __shared__ SrhtTiles S;
+  const int klo = blockIdx.x;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 64
+  const uint32_t ja0 = (uint32_t)(jh0 >> 2);
+  const int nst = (int)((jh1 - jh0) >> 5);                      // stages of 32 T rows
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int qi = lane & 15, kk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.z * 64;
+  double* out = partial + (int64_t)js * m * d;
+  // staging map: thread -> rows lr + 8 i (i < 4) of a stage, columns lc, lc + 1
+  const int lr = tid >> 5, lc = (tid & 31) * 2;
+  const bool lok = c0 + lc < dT;  // dT is even
+  const double* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + c0 + lc;
+  auto gload = [&](int st, d2(&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      v[i] = lok ? __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 8 * i) * dT))
+                 : (d2){0.0, 0.0};
+  };
+  auto lstore = [&](int buf, const d2(&v)[4]) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) *(d2*)(L + buf * SRHT_LSTAGE64 + (lr + 8 * i) * SRHT_LP64 + lc) = v[i];
+  };
+  for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
+    const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
+    for (int tg = 0; tg < nt; tg += 4 * TPW) {
+      const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));  // uniform per wavefront
+      int tv[TPW];
+      uint32_t ka[TPW];
+      double s1[TPW], s2[TPW];
+      lsq_d4 acc[TPW][4];
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = tg + wv + 4 * i;
+        const int q = t < nt ? S.tq[t][qi] : -1;
+        tv[i] = q >= 0;
+        ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
+        const int e = t < nt ? S.te[t] : 0;
+        s1[i] = (e & 1) ? -1.0 : 1.0;
+        s2[i] = (e & 2) ? -1.0 : 1.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[i][c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+      }
+      auto compute = [&](const double* Lb, uint32_t ja_stage) {
+#pragma unroll 1
+        for (int step = 0; step < 2; ++step) {
+          const uint32_t ja = ja_stage + 4 * step + kk;
+          double a[TPW];
+#pragma unroll
+          for (int i = 0; i < TPW; ++i) a[i] = tv[i] ? ((__popc(ka[i] & ja) & 1) ? -1.0 : 1.0) : 0.0;
+          const double* r = Lb + (16 * step + 4 * kk) * SRHT_LP64 + qi;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const double t0 = r[16 * c], t1 = r[SRHT_LP64 + 16 * c], t2 = r[2 * SRHT_LP64 + 16 * c],
+                         t3 = r[3 * SRHT_LP64 + 16 * c];
+#pragma unroll
+            for (int i = 0; i < TPW; ++i) {
+              if (i >= non) break;
+              const double u = fma(s2[i], fma(s1[i], t3, t2), fma(s1[i], t1, t0));
+              acc[i][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], u, acc[i][c], 0, 0, 0);
+            }
+          }
+        }
+      };
+      d2 ra[4], rb[4];
+      gload(0, ra);
+      if (nst > 1) gload(1, rb);
+      __syncthreads();  // the previous sweep's last stage has been consumed
+      lstore(0, ra);
+      __syncthreads();
+      if (nst > 2) gload(2, ra);
+      for (int st = 0; st < nst; st += 2) {
+        compute(L, ja0 + 8 * st);
+        if (st + 1 < nst) lstore(1, rb);
+        __syncthreads();
+        if (st + 3 < nst) gload(st + 3, rb);
+        if (st + 1 >= nst) break;
+        compute(L + SRHT_LSTAGE64, ja0 + 8 * (st + 1));
+        if (st + 2 < nst) lstore(0, ra);
+        __syncthreads();
+        if (st + 4 < nst) gload(st + 4, ra);
+      }
+#pragma unroll
+      for (int i = 0; i < TPW; ++i) {
+        const int t = tg + wv + 4 * i;
+        if (t >= nt) continue;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int64_t col = c0 + 16 * c + qi;
+          if (col >= d) continue;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int q = S.tq[t][kk + 4 * v];
+            if (q >= 0) out[(int64_t)order[q] * d + col] = acc[i][c][v];
           }
         }
       }
@@ -1026,6 +1161,23 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     else
       hipLaunchKernelGGL(k_srht_passB_f32<2>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
+  } else if (big && p.N2 >= 512 && g_srht_passb == 0) {
+    // tiles per wavefront from the expected bucket: e-groups of about m / (4 N1) rows, two standard
+    // deviations over, in tiles of 16, over 4 wavefronts; larger buckets take more passes over T
+    const int64_t ncb = (dT + 63) / 64;
+    JS = srht_js_lds(p.N1, p.N2, ncb);
+    dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
+    const double g = (double)p.m / (4.0 * (double)p.N1);
+    const int tiles = 4 * (int)ceil((g + 2.0 * sqrt(g)) / 16.0);
+    if (tiles <= 8)
+      hipLaunchKernelGGL(k_srht_passB_lds64<2>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+                         slot, order, bstart, p.m, partial);
+    else if (tiles <= 12)
+      hipLaunchKernelGGL(k_srht_passB_lds64<3>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+                         slot, order, bstart, p.m, partial);
+    else
+      hipLaunchKernelGGL(k_srht_passB_lds64<4>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+                         slot, order, bstart, p.m, partial);
   } else if (big) {
     constexpr int WGC = SRHT_WGC / 2;
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + WGC - 1) / WGC));

@@ -53,7 +53,7 @@ COLS = np.arange(0, D, 16)  # 64 sampled columns
 ROWS = [0, 1, 2047, 4095]
 
 
-@pytest.mark.parametrize("compute,m", [("f64", M), ("f32", M), ("f32", 6 * M)])
+@pytest.mark.parametrize("compute,m", [("f64", M), ("f32", M), ("f32", 6 * M), ("f64", 6 * M)])
 def test_fullsize_srht_rows(big, compute, m):
     """m = 4096 and the chooser's 24d (buckets of about 96 selected rows: the folded pass B)."""
     from oracle.draws import padded_length, srht_rows, srht_signs
