@@ -775,6 +775,16 @@ constexpr int SRHT_LSTAGE = 64 * SRHT_LP;       // floats per stage buffer
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
 constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 4; // tiles per build at most
 
+// Workgroup barrier for data exchanged through LDS only: this wavefront's LDS accesses complete
+// (lgkmcnt), then s_barrier; loads from global memory stay in flight (__syncthreads also drains them).
+// The empty asm statements keep the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Row tiles of one chunk [cb, ce) of a bucket's selected rows (ce - cb <= SRHT_LROWS), grouped by
 // e = k_hi & 3 in tiles of 16 (the order of rows inside a tile does not change any output row; empty
 // slots stay -1): one thread per row places itself with an LDS counter per group.  All threads of the
@@ -871,14 +881,13 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
   const int64_t c0 = (int64_t)blockIdx.z * 64;
   double* out = partial + (int64_t)js * m * d;
   // staging map: thread -> rows lr + 16 i (i < 4) of a stage, columns lc .. lc + 3
+  // (columns past dT read the row's last 4 columns instead: those lanes' LDS words are never output)
   const int lr = tid >> 4, lc = (tid & 15) * 4;
-  const bool lok = c0 + lc < dT;  // dT is a multiple of 4
-  const float* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + c0 + lc;
+  const float* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 4);
   auto gload = [&](int st, f4(&v)[4]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      v[i] = lok ? __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 16 * i) * dT))
-                 : (f4){0.f, 0.f, 0.f, 0.f};
+      v[i] = __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 16 * i) * dT));
   };
   auto lstore = [&](int buf, const f4(&v)[4]) {
 #pragma unroll
@@ -921,26 +930,27 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
       };
       // two stages in flight in registers, one being consumed from LDS
       f4 ra[4], rb[4];
+      // nst is even.  Loads are issued without conditions (stages past the last reload the last one,
+      // never used) so that the compiler's wait counts stay exact and two stages stay in flight.
       gload(0, ra);
-      if (nst > 1) gload(1, rb);
-      __syncthreads();  // the previous sweep's last stage has been consumed
+      gload(1, rb);
+      lds_barrier();  // the previous sweep's last stage has been consumed
       lstore(0, ra);
-      __syncthreads();
-      if (nst > 2) gload(2, ra);
+      lds_barrier();
+      gload(min(2, nst - 1), ra);
       for (int st = 0; st < nst; st += 2) {
         // even stage: LDS buffer 0, next stage (st + 1) in rb, st + 2 in ra
         srht_lds_compute<TPW>(L, non, tv, ka, s1, s2, ja0 + 16 * st, kk, qi, acc);
         fold();
-        if (st + 1 < nst) lstore(1, rb);
-        __syncthreads();
-        if (st + 3 < nst) gload(st + 3, rb);
-        if (st + 1 >= nst) break;
+        lstore(1, rb);
+        lds_barrier();
+        gload(min(st + 3, nst - 1), rb);
         // odd stage: LDS buffer 1, next stage (st + 2) in ra, st + 3 in rb
         srht_lds_compute<TPW>(L + SRHT_LSTAGE, non, tv, ka, s1, s2, ja0 + 16 * (st + 1), kk, qi, acc);
         fold();
-        if (st + 2 < nst) lstore(0, ra);
-        __syncthreads();
-        if (st + 4 < nst) gload(st + 4, ra);
+        lstore(0, ra);
+        lds_barrier();
+        gload(min(st + 4, nst - 1), ra);
       }
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
@@ -962,7 +972,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
 }
 
 // The same for FP64 T (no FP32 chains to fold: the tiles accumulate in FP64 directly, so a wavefront
-// carries up to TPW = 4 tiles).  Stages of 32 T rows (8 values of j_a, two MFMA steps) x 64 columns,
+// carries up to TPW = 3 tiles).  Stages of 32 T rows (8 values of j_a, two MFMA steps) x 64 columns,
 // row pitch 68 doubles (the four j_a of a step fall in the two bank halves, two lane groups each).
 // v_mfma_f64_16x16x4: A and B operands as in the FP32 form; result lane l, register v holds tile row
 // l / 16 + 4 v, column l % 16 of its block.
@@ -993,13 +1003,10 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
   double* out = partial + (int64_t)js * m * d;
   // staging map: thread -> rows lr + 8 i (i < 4) of a stage, columns lc, lc + 1
   const int lr = tid >> 5, lc = (tid & 31) * 2;
-  const bool lok = c0 + lc < dT;  // dT is even
-  const double* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + c0 + lc;
+  const double* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 2);
   auto gload = [&](int st, d2(&v)[4]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      v[i] = lok ? __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 8 * i) * dT))
-                 : (d2){0.0, 0.0};
+    for (int i = 0; i < 4; ++i) v[i] = __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 8 * i) * dT));
   };
   auto lstore = [&](int buf, const d2(&v)[4]) {
 #pragma unroll
@@ -1047,22 +1054,21 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
         }
       };
       d2 ra[4], rb[4];
-      gload(0, ra);
-      if (nst > 1) gload(1, rb);
-      __syncthreads();  // the previous sweep's last stage has been consumed
+      gload(0, ra);  // as in the FP32 form: nst even, unconditional loads
+      gload(1, rb);
+      lds_barrier();
       lstore(0, ra);
-      __syncthreads();
-      if (nst > 2) gload(2, ra);
+      lds_barrier();
+      gload(min(2, nst - 1), ra);
       for (int st = 0; st < nst; st += 2) {
         compute(L, ja0 + 8 * st);
-        if (st + 1 < nst) lstore(1, rb);
-        __syncthreads();
-        if (st + 3 < nst) gload(st + 3, rb);
-        if (st + 1 >= nst) break;
+        lstore(1, rb);
+        lds_barrier();
+        gload(min(st + 3, nst - 1), rb);
         compute(L + SRHT_LSTAGE64, ja0 + 8 * (st + 1));
-        if (st + 2 < nst) lstore(0, ra);
-        __syncthreads();
-        if (st + 4 < nst) gload(st + 4, ra);
+        lstore(0, ra);
+        lds_barrier();
+        gload(min(st + 4, nst - 1), ra);
       }
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
@@ -1087,7 +1093,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
 // ranges, at least one stage (64 rows of T) per range.
 static int srht_js_lds(int64_t N1, int64_t N2, int64_t ncb) {
   int js = 1;
-  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 64 && 2 * js <= srht_js_cap(N2)) js *= 2;
+  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 128 && 2 * js <= srht_js_cap(N2)) js *= 2;
   return js;
 }
 
@@ -1163,7 +1169,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                          order, bstart, p.m, partial);
   } else if (big && p.N2 >= 512 && g_srht_passb == 0) {
     // tiles per wavefront from the expected bucket: e-groups of about m / (4 N1) rows, two standard
-    // deviations over, in tiles of 16, over 4 wavefronts; larger buckets take more passes over T
+    // deviations over, in tiles of 16, over 4 wavefronts (at most 3 each); larger buckets take more
+    // passes over T
     const int64_t ncb = (dT + 63) / 64;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
@@ -1172,11 +1179,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     if (tiles <= 8)
       hipLaunchKernelGGL(k_srht_passB_lds64<2>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
-    else if (tiles <= 12)
-      hipLaunchKernelGGL(k_srht_passB_lds64<3>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
-                         slot, order, bstart, p.m, partial);
     else
-      hipLaunchKernelGGL(k_srht_passB_lds64<4>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+      hipLaunchKernelGGL(k_srht_passB_lds64<3>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
   } else if (big) {
     constexpr int WGC = SRHT_WGC / 2;
