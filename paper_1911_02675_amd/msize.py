@@ -83,7 +83,7 @@ def paper_m_star(kind, n, d, tol):
 
 
 def candidates(n, d, kind):
-    """Sketch sizes the chooser considers: 1.5d .. 32d, within the factorization's limit, m <= N for the
+    """Sketch sizes the chooser considers: 1.5d .. 64d, within the factorization's limit, m <= N for the
     SRHT and m <= 16384 for the SJLT."""
     N = 1 << max(0, (n - 1).bit_length())
     hi = FACTOR_M_MAX
@@ -92,7 +92,7 @@ def candidates(n, d, kind):
     if kind == "sjlt":
         hi = min(hi, 16384)
     out = []
-    for f in (1.5, 2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32):
+    for f in (1.5, 2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 40, 48, 64):
         m = int(round(f * d / 64.0)) * 64 if d >= 64 else int(round(f * d))
         if d < m <= hi and m not in out:
             out.append(m)

@@ -73,8 +73,9 @@ def test_choose_matches_brute_force():
 
 
 def test_candidates_respect_limits():
-    assert all(1024 < m <= 32768 for m in msize.candidates(1 << 22, 1024, "srht"))
-    assert max(msize.candidates(1 << 22, 1024, "srht")) == 32768
+    assert all(1024 < m <= 65536 for m in msize.candidates(1 << 22, 1024, "srht"))
+    assert max(msize.candidates(1 << 22, 1024, "srht")) == 65536  # the factorization's limit
+    assert max(msize.candidates(1 << 22, 2048, "srht")) == 65536
     assert max(msize.candidates(1 << 22, 1024, "sjlt")) == 16384
     assert all(m <= 4096 for m in msize.candidates(4096, 1024, "srht"))  # m <= N for the SRHT
     assert msize.candidates(1 << 22, 1024, "srht")[0] == 1536
