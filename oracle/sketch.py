@@ -121,7 +121,25 @@ def gaussian_sketch_bf16(A, m, seed, t=0, row_block=4096):
     return SA / np.sqrt(m)
 
 
+def haar_matrix(n, m, seed, t=0):
+    """S (m x n) of the Haar embedding (Section 2): orthonormal rows, S S^T = I_m, spanning a uniformly
+    distributed m-dimensional subspace.  S = Q^T for the QR factorization G = Q R with a positive
+    diagonal of R, where G (n x m) holds the Gaussian embedding's standard normals, G[j, i] = g(i, j);
+    Q is then Haar distributed (the positive-diagonal convention makes the factorization unique).
+    Rows are not rescaled: the inverse moments of C_S for this S are the Haar ones of Section 2."""
+    G = draws.gaussian_normals(seed, t, np.arange(m)[None, :], np.arange(n)[:, None])
+    Q, R = np.linalg.qr(G)
+    return (Q * np.sign(np.diag(R))[None, :]).T
+
+
+def haar_sketch(A, m, seed, t=0):
+    """S A for the Haar embedding (dense S; small n only)."""
+    return haar_matrix(A.shape[0], m, seed, t) @ A
+
+
 def sketch(A, kind, m, seed, t=0, s=1):
+    if kind == "haar":
+        return haar_sketch(A, m, seed, t)
     if kind == "srht":
         return srht_sketch(A, m, seed, t)
     if kind == "sjlt":

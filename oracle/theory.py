@@ -24,6 +24,15 @@ def theta_haar(n, d, m):
     return t1, t2
 
 
+def theta1_haar_exact(n, d, m):
+    """theta_1 = d^{-1} tr E[C_S^{-1}] for a Haar embedding with orthonormal rows, exactly: C_S = U^T P U
+    with P a uniformly random rank-m projection is a d x d matrix-variate beta B(m/2, (n-m)/2), whose
+    inverse has mean (n - d - 1)/(m - d - 1) I (m > d + 1).  Section 2's (n - d)/(m - d) is its limit."""
+    if m <= d + 1:
+        raise ValueError("needs m > d + 1")
+    return (n - d - 1) / (m - d - 1)
+
+
 def srht_thetas_scaled(N, d, m):
     """theta's of the SRHT as scaled here (S = m^{-1/2} R H E, so S S^T = (N/m) I): the Haar values
     for an m x N embedding with orthonormal rows, times (m/N) and (m/N)^2."""
