@@ -5,7 +5,9 @@
  *   Problem (Section 1):  x* = argmin_x 1/2 <x, H x> - <b, x>,  H = A^T A, A in R^{n x d}, n >= d.
  *   For least squares the caller passes y in R^n and b = A^T y, i.e. x* = argmin ||A x - y||_2.
  *   Embeddings (Section 2): Gaussian (entries N(0, 1/m)), SRHT (S = R H E with zero padding to a power
- *   of two), SJLT (s nonzeros +-1/sqrt(s) per column).
+ *   of two), SJLT (s nonzeros +-1/sqrt(s) per column), Haar (orthonormal rows, S S^T = I_m, spanning a
+ *   uniformly distributed subspace: S = Q^T for the positive-diagonal QR g^T = Q R of the Gaussian
+ *   embedding's unscaled draws g, formed as R^{-T} (g A) without Q).
  *   Preconditioner (Section 1.2): H_S = (S A)^T (S A) = R^T R, R from a QR of S A.
  *   Solvers: PCG with a fixed sketch (Section 1.2), IHS and Polyak-IHS (Section 1.1) with a fixed or a
  *   refreshed sketch (Sections 3 and 4).
@@ -54,7 +56,7 @@ typedef enum {
 } lsq_status;
 
 typedef enum { LSQ_F64 = 0, LSQ_F32 = 1, LSQ_BF16 = 2 } lsq_dtype;
-typedef enum { LSQ_GAUSSIAN = 0, LSQ_SRHT = 1, LSQ_SJLT = 2 } lsq_sketch_kind;
+typedef enum { LSQ_GAUSSIAN = 0, LSQ_SRHT = 1, LSQ_SJLT = 2, LSQ_HAAR = 3 } lsq_sketch_kind;
 
 typedef struct lsq_ctx lsq_ctx; /* opaque: stream, workspace, device state, tuning table */
 
@@ -123,8 +125,9 @@ typedef struct {
  *   refresh: 1 = S_t drawn with refresh counter desc.t + t (Section 4); 0 = S_t = S fixed (Section 3).
  *   mu_rule: 0 = mu = theta_1 / theta_2 from the inverse moments (Theorem 4.1): the Gaussian closed
  *            form for LSQ_GAUSSIAN (needs m >= d + 4), the Haar/SRHT trace approximation for LSQ_SRHT
- *            rescaled to S S^T = (N/m) I, i.e. mu = (N/m) theta_1/theta_2; LSQ_SJLT has no closed form
- *            and needs mu_rule = 1.  1 = use `mu` as given.  2 and 3 are the fixed-sketch parameters of
+ *            rescaled to S S^T = (N/m) I, i.e. mu = (N/m) theta_1/theta_2; for LSQ_HAAR the same trace
+ *            approximation with n, unscaled (S S^T = I); LSQ_SJLT has no closed form and needs
+ *            mu_rule = 1.  1 = use `mu` as given.  2 and 3 are the fixed-sketch parameters of
  *            Theorem 3.2 with rho = d/m (meant for refresh = 0; need m > d): 2 = IHS step
  *            mu = (1 - rho)^2 / (1 + rho) (the optimal step of Theorem 3.4) with `beta` as given;
  *            3 = Polyak-IHS mu = (1 - rho)^2, beta = rho (the given `beta` is ignored).
@@ -172,8 +175,11 @@ typedef struct {
 } lsq_info;
 
 /* S A (m x d) into SA (device, row-major, leading dimension ldsa >= d).  sa_dtype must be LSQ_F64.
- * Section 2.  Errors: INVALID_ARG for m < 1, m > N (SRHT), s outside [1, min(m, 32)] (SJLT),
- * lda < d, null pointers; UNSUPPORTED for d > 1024. */
+ * Section 2.  Errors: INVALID_ARG for m < 1, m > N (SRHT), m > n (Haar), s outside [1, min(m, 32)]
+ * (SJLT), a compute other than LSQ_F64 for Haar, lda < d, null pointers; UNSUPPORTED for d > 1024 or,
+ * for Haar, m > min(1024, n/4) (the m x m Gram of the draws is factored once on the device, which keeps
+ * the rows orthonormal to rounding while the n x m draws are well conditioned; the workspace holds the
+ * draws in FP32); RANK if that Gram is not positive definite. */
 lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc, void* SA,
                       int64_t ldsa, int32_t sa_dtype);
 

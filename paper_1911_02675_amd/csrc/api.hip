@@ -147,6 +147,14 @@ static lsq_status check_sketch(const lsq_problem* p, const lsq_sketch_desc* s, b
       if (s->compute != LSQ_F64 && s->compute != LSQ_BF16 && s->compute != LSQ_F32)
         return fail(LSQ_ERR_INVALID_ARG, "Gaussian compute must be LSQ_F64, LSQ_F32 or LSQ_BF16");
       break;
+    case LSQ_HAAR:
+      if (s->compute != LSQ_F64) return fail(LSQ_ERR_INVALID_ARG, "Haar compute must be LSQ_F64");
+      if (s->m > p->n) return fail(LSQ_ERR_INVALID_ARG, "Haar needs m <= n");
+      // one Cholesky of the draws' Gram keeps the rows orthonormal to about u kappa(g)^2, and
+      // kappa(g) <= (1 + sqrt(m/n)) / (1 - sqrt(m/n)) <= 3 for m <= n/4
+      if (s->m > 1024 || 4 * s->m > p->n)
+        return fail(LSQ_ERR_UNSUPPORTED, "Haar embedding limited to m <= min(1024, n/4)");
+      break;
     default:
       return fail(LSQ_ERR_INVALID_ARG, "unknown sketch kind");
   }
@@ -211,6 +219,32 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     HIPCHK(hipMemcpyAsync(c->hflags + 1, c->dflags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (c->hflags[1]) return fail(LSQ_ERR_INVALID_ARG, "SJLT draw limit exhausted (s too close to m)");
+  } else if (s->kind == LSQ_HAAR) {
+    // S = Q^T for the positive-diagonal QR g^T = Q R_g of the unscaled Gaussian draws g (m x n), without
+    // forming Q: S A = R_g^{-T} (g A), R_g^T R_g = g g^T.  With the Gaussian sketch G_s = g / sqrt(m):
+    // Y = G_s A and Z = G_s g^T (the Gaussian sketch of the drawn n x m matrix g^T), so g A = sqrt(m) Y
+    // and g g^T = sqrt(m) Z.
+    const int64_t m = s->m, n = p->n, d = p->d, mp = cholqr_padded(m);
+    float* Gt;
+    double *Y, *Z, *W, *scr, *tscr, *part;
+    CHK(wsT(c, "haar_gt", (size_t)n * m, &Gt));
+    CHK(wsT(c, "haar_y", (size_t)m * d, &Y));
+    CHK(wsT(c, "haar_z", (size_t)m * m, &Z));
+    CHK(wsT(c, "haar_w", (size_t)mp * mp, &W));
+    CHK(wsT(c, "haar_scr", spd_inverse_scratch_len(m), &scr));
+    CHK(wsT(c, "haar_tscr", trinv_scratch_len(mp), &tscr));
+    const size_t pb = std::max(gauss_partial_bytes(m, d, n, 0), gauss_partial_bytes(m, m, n, 0));
+    CHK(wsT(c, "gauss_part", pb / sizeof(double) + 1, &part));
+    launch_gauss_draw_t(st, s->seed, t, n, m, Gt);
+    gauss_apply(st, s->seed, t, p->A, a_f32, n, d, p->lda, m, 0, part, Y, d);
+    gauss_apply(st, s->seed, t, Gt, 1, n, m, m, m, 0, part, Z, m);
+    HIPCHK(hipMemsetAsync(c->dflags + 6, 0, sizeof(int), st));
+    const double rm = sqrt((double)m);
+    spd_chol_inverse(st, Z, m, rm, scr, W, c->dflags + 6, tscr);
+    haar_apply(st, W, mp, Y, m, d, rm, SA, ldsa);
+    HIPCHK(hipMemcpyAsync(c->hflags + 6, c->dflags + 6, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (c->hflags[6]) return fail(LSQ_ERR_RANK, "Haar embedding: the Gram of the Gaussian draws is not positive definite");
   } else {
     double* part;
     const int bf16 = s->compute == LSQ_BF16;
@@ -700,6 +734,13 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       const double t1 = (N - dd) / (md - dd);
       const double t2 = (N - dd) * (dd * dd + md * N - 2.0 * dd * md) / ((md - dd) * (md - dd) * (md - dd));
       mu = (N / md) * t1 / t2;
+    } else if (s->kind == LSQ_HAAR) {
+      // Section 2's Haar theta's (orthonormal rows, no rescaling)
+      if (m <= d) return fail(LSQ_ERR_INVALID_ARG, "Haar step rule needs m > d");
+      const double nn = (double)p->n, md = (double)m, dd = (double)d;
+      const double t1 = (nn - dd) / (md - dd);
+      const double t2 = (nn - dd) * (dd * dd + md * nn - 2.0 * dd * md) / ((md - dd) * (md - dd) * (md - dd));
+      mu = t1 / t2;
     } else {
       return fail(LSQ_ERR_INVALID_ARG, "the SJLT has no closed-form step: use mu_rule = 1");
     }

@@ -429,6 +429,56 @@ int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_
   return 0;
 }
 
+// ---- Haar embedding ------------------------------------------------------------------------------
+// G (dp x dp) = scale Z on the leading md x md block (Z row-major, ld md), the identity on the padding.
+__global__ __launch_bounds__(256) void k_pad_spd(const double* __restrict__ Z, int64_t md, int64_t dp, double scale,
+                                                 double* __restrict__ G) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= dp * dp) return;
+  const int64_t i = idx / dp, j = idx % dp;
+  G[idx] = (i < md && j < md) ? scale * Z[i * md + j] : (i == j ? 1.0 : 0.0);
+}
+
+size_t spd_inverse_scratch_len(int64_t md) {
+  const int64_t dp = cholqr_padded(md);
+  return 2 * (size_t)dp * dp + CQ_T * CQ_T;
+}
+
+void spd_chol_inverse(hipStream_t st, const double* Z, int64_t md, double scale, double* scratch, double* W,
+                      int* flag, double* trinv_scratch) {
+  const int64_t dp = cholqr_padded(md);
+  double* G = scratch;
+  double* R = G + dp * dp;
+  double* Dinv = R + dp * dp;
+  hipLaunchKernelGGL(k_pad_spd, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, Z, md, dp, scale, G);
+  cholesky(st, G, dp, R, Dinv, flag);
+  tri_inverse_padded(st, R, dp, W, trinv_scratch);
+}
+
+// SA[i][c] = scale sum_{k <= i} W[k][i] Y[k][c]  (SA = scale W^T Y, W upper triangular, ld ldw).  One thread
+// per output; a wavefront shares i, so W is read as a broadcast and Y row by row.
+__global__ __launch_bounds__(256) void k_haar_apply(const double* __restrict__ W, int64_t ldw,
+                                                    const double* __restrict__ Y, int64_t m, int64_t d,
+                                                    double scale, double* __restrict__ SA, int64_t ldsa) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= m * d) return;
+  const int64_t i = idx / d, c = idx % d;
+  double s0 = 0.0, s1 = 0.0;
+  int64_t k = 0;
+  for (; k + 1 <= i; k += 2) {
+    s0 = fma(W[k * ldw + i], Y[k * d + c], s0);
+    s1 = fma(W[(k + 1) * ldw + i], Y[(k + 1) * d + c], s1);
+  }
+  if (k <= i) s0 = fma(W[k * ldw + i], Y[k * d + c], s0);
+  SA[i * ldsa + c] = scale * (s0 + s1);
+}
+
+void haar_apply(hipStream_t st, const double* W, int64_t ldw, const double* Y, int64_t m, int64_t d, double scale,
+                double* SA, int64_t ldsa) {
+  hipLaunchKernelGGL(k_haar_apply, dim3((unsigned)((m * d + 255) / 256)), dim3(256), 0, st, W, ldw, Y, m, d, scale,
+                     SA, ldsa);
+}
+
 int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
                     double* R, int* flags, double* trinv_scratch) {
   const int64_t dp = cholqr_padded(d);

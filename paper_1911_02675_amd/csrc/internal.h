@@ -26,6 +26,8 @@ void launch_sjlt_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int6
                       int32_t* targets, int8_t* signs, int* err);
 void launch_gauss_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
                        int64_t ncols, float* G);
+// Gt (n x m, row-major FP32) = the unscaled normals transposed, Gt[j m + i] = g(i, j).
+void launch_gauss_draw_t(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, float* Gt);
 // Exclusive prefix sum of len int32 values; tmp needs scan_tmp_len(len) ints.
 size_t scan_tmp_len(int64_t len);
 void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, int* tmp);
@@ -92,6 +94,15 @@ int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_
 // Shifted CholeskyQR3 (any full-rank SA up to kappa ~ 1/u).  flags: 1 device int.
 int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
                     double* R, int* flags, double* trinv_scratch);
+// Haar embedding helpers.  W (dp x dp, dp = cholqr_padded(md)) = R^{-1} for R^T R = scale Z (Z: md x md
+// symmetric positive definite, row-major); flag set on a non-positive pivot.  scratch:
+// spd_inverse_scratch_len(md) doubles; trinv_scratch: trinv_scratch_len(dp).
+size_t spd_inverse_scratch_len(int64_t md);
+void spd_chol_inverse(hipStream_t st, const double* Z, int64_t md, double scale, double* scratch, double* W,
+                      int* flag, double* trinv_scratch);
+// SA = scale W^T Y for W upper triangular (m x m used, ld ldw) and Y (m x d, row-major).
+void haar_apply(hipStream_t st, const double* W, int64_t ldw, const double* Y, int64_t m, int64_t d, double scale,
+                double* SA, int64_t ldsa);
 extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder
 extern int g_srht_passb;   // tuning: FP32 SRHT pass B for large buckets, 0 = LDS-staged, 1 = register-direct
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers

@@ -13,8 +13,8 @@ LIB_PATH = os.path.join(HERE, "liblsq.so")
 LSQ_OK, LSQ_ERR_INVALID_ARG, LSQ_ERR_RANK, LSQ_ERR_NOT_CONVERGED = 0, 1, 2, 3
 LSQ_ERR_NONFINITE, LSQ_ERR_HIP, LSQ_ERR_NOMEM, LSQ_ERR_UNSUPPORTED = 4, 5, 6, 7
 LSQ_F64, LSQ_F32, LSQ_BF16 = 0, 1, 2
-LSQ_GAUSSIAN, LSQ_SRHT, LSQ_SJLT = 0, 1, 2
-KINDS = {"gaussian": LSQ_GAUSSIAN, "srht": LSQ_SRHT, "sjlt": LSQ_SJLT}
+LSQ_GAUSSIAN, LSQ_SRHT, LSQ_SJLT, LSQ_HAAR = 0, 1, 2, 3
+KINDS = {"gaussian": LSQ_GAUSSIAN, "srht": LSQ_SRHT, "sjlt": LSQ_SJLT, "haar": LSQ_HAAR}
 DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 
 EXPORTED = [
