@@ -29,14 +29,32 @@ def sketch_factor(A, kind, m, seed, t=0, s=1):
     return householder_qr(_sk.sketch(A, kind, m, seed, t, s))
 
 
+def svd_preconditioner(SA, rtol=1e-12):
+    """P = V Sigma^+ from numpy's SVD of S A (singular values at or below rtol * sigma_max dropped), so
+    that P P^T = H_S^+ (the LSRN form of the factor step; equal to R^{-1} R^{-T} for full-rank S A)."""
+    _, s, Vt = np.linalg.svd(np.asarray(SA, dtype=np.float64), full_matrices=False)
+    keep = s > rtol * s[0]
+    return Vt[keep].T / s[keep][None, :]
+
+
 def pcg(A, y, R, x0=None, tol=1e-10, max_iter=200, fixed_iters=None):
     """Run PCG.  Returns (x, iterates) where iterates[t] = x_t.  With fixed_iters the loop runs
     exactly that many iterations; otherwise it stops by the rule in the module docstring."""
+    return pcg_with(A, y, lambda r: apply_hs_inv(R, r), x0, tol, max_iter, fixed_iters)
+
+
+def pcg_svd(A, y, P, x0=None, tol=1e-10, max_iter=200, fixed_iters=None):
+    """PCG with the preconditioner P P^T (svd_preconditioner)."""
+    return pcg_with(A, y, lambda r: P @ (P.T @ r), x0, tol, max_iter, fixed_iters)
+
+
+def pcg_with(A, y, hs_inv, x0=None, tol=1e-10, max_iter=200, fixed_iters=None):
+    """The PCG loop with H_S^{-1} (or H_S^+) applied by hs_inv."""
     A = np.asarray(A, dtype=np.float64)
     d = A.shape[1]
     x = np.zeros(d) if x0 is None else np.array(x0, dtype=np.float64)
     r = A.T @ (y - A @ x)
-    rhat = apply_hs_inv(R, r)
+    rhat = hs_inv(r)
     p = rhat.copy()
     rho = float(r @ rhat)
     rho0 = rho
@@ -53,7 +71,7 @@ def pcg(A, y, R, x0=None, tol=1e-10, max_iter=200, fixed_iters=None):
         alpha = rho / pHp
         x = x + alpha * p
         r = r - alpha * Hp
-        rhat = apply_hs_inv(R, r)
+        rhat = hs_inv(r)
         rho_new = float(r @ rhat)
         p = rhat + (rho_new / rho) * p
         rho = rho_new

@@ -35,3 +35,12 @@ def normal_equation_residual(A, x, y):
     """||A^T (A x - y)|| / (||A||_2 ||A x - y||): zero at the exact minimiser."""
     r = A @ x - y
     return float(np.linalg.norm(A.T @ r) / (np.linalg.norm(A, 2) * np.linalg.norm(r)))
+
+
+def min_norm_lstsq(A, y, rcond=1e-12):
+    """x+ = V Sigma^+ U^T y, the minimum-norm least-squares solution (singular values at or below
+    rcond * sigma_max treated as zero), from numpy's SVD of A."""
+    U, s, Vt = np.linalg.svd(np.asarray(A, dtype=np.float64), full_matrices=False)
+    keep = s > rcond * s[0]
+    return Vt[keep].T @ ((U[:, keep].T @ np.asarray(y, dtype=np.float64)) / s[keep])
+
