@@ -62,6 +62,8 @@ struct lsq_ctx {
   hipEvent_t bev[3] = {};
   double* hx = nullptr;  // pinned host copy of a starting point (mixed solve)
   size_t hx_len = 0;
+  int w_dense = 0;        // the last factorization's W is dense (SVD form) rather than triangular
+  int svd_rank = 0, svd_sweeps = 0;
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -268,6 +270,28 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
   const hipStream_t st = c->st;
   double* tscr;
   CHK(wsT(c, "trinv", trinv_scratch_len(cholqr_padded(d)), &tscr));
+  c->w_dense = 0;
+  if (g_factor_mode == 2) {
+    // SVD form: R by Householder QR (m <= 8192; a zero pivot is allowed, rank deficiency is handled by
+    // the truncation) or CholeskyQR2, then one-sided Jacobi on R
+    if (m <= QR_M_MAX) {
+      double* X;
+      CHK(wsT(c, "qr_x", (size_t)m * d + (size_t)d * d, &X));
+      householder_qr(st, SA, m, d, lds, X, R, c->dflags);
+    } else {
+      double* cs;
+      CHK(wsT(c, "cholqr", cholqr_scratch_len(m, d), &cs));
+      if (cholqr_factor(st, SA, m, d, lds, cs, R, c->dflags + 4, c->hflags + 4, tscr) != 0)
+        return fail(LSQ_ERR_UNSUPPORTED, "SVD form above m = 8192 needs a full-rank, moderately conditioned S A");
+    }
+    double* vs;
+    CHK(wsT(c, "svd", svd_scratch_len(d), &vs));
+    c->svd_rank = svd_precond(st, R, d, SVD_RTOL, vs, W, WT, c->dflags + 6, c->hflags + 6, &c->svd_sweeps);
+    HIPCHK(hipGetLastError());
+    c->w_dense = 1;
+    if (c->svd_rank < 1) return fail(LSQ_ERR_RANK, "S A is zero");
+    return LSQ_OK;
+  }
   bool done = false;
   if (g_factor_mode == 0) {
     double* cs;
@@ -386,7 +410,7 @@ static lsq_status pcg_loop(lsq_ctx* c, const lsq_problem* pr, int f32_math, cons
       reduce_stage1(c->st, b.part, ng_, d, b.part2, &c->ds->done);
       pcg_update_xr(c->st, b.part2, REDUCE_SPLIT, d, z, b.r, b.p, c->ds);
       int ndot;
-      precond_apply(c->st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, &c->ds->done);
+      precond_apply_any(c->st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, &c->ds->done, c->w_dense);
       pcg_update_p(c->st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, z, b.r, x_ref, trace, trace_len);
     }
     HIPCHK(hipGetLastError());
@@ -557,7 +581,7 @@ static lsq_status inner_pcg(lsq_ctx* c, const lsq_problem* p, int f32_math, cons
                             int check_every, const double* x_ref, double* trace, int trace_len,
                             int* iters) {
   int ndot;
-  precond_apply(c->st, W, WT, p->d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+  precond_apply_any(c->st, W, WT, p->d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);
   pcg_init(c->st, p->d, b.rhat, b.p, b.dotpart, ndot, c->ds, tol_in, z, b.r, x_ref, trace);
   HIPCHK(hipGetLastError());
   return pcg_loop(c, p, f32_math, W, WT, b, z, max_iter, check_every, x_ref, trace, trace_len, iters);
@@ -656,7 +680,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       }
       passes += 1;
       int ndot;
-      precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+      precond_apply_any(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);
       pcg_init(st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, 1.0, x, b.r, nullptr, nullptr);
       CHK(sync_state(c));
       const double rho_s = c->hds->rho0;
@@ -805,7 +829,7 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
     reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
     int ndot;
-    precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);
+    precond_apply_any(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);
     ihs_update(st, d, x, xprev, b.rhat, mu, beta);
     HIPCHK(hipEventRecord(c->ev[1], st));
     HIPCHK(hipEventSynchronize(c->ev[1]));
@@ -907,7 +931,7 @@ lsq_status lsq_fcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     }
     HIPCHK(hipEventRecord(c->ev[0], st));
     int ndot;
-    precond_apply(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr);  // v_t
+    precond_apply_any(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);  // v_t
     const int kt = std::min(o->window, t);
     const int slot = t % ring;
     double* pt = P + (size_t)slot * d;
@@ -1001,7 +1025,8 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     return LSQ_OK;
   }
   if (k == "factor") {
-    if (value < 0 || value > 1) return fail(LSQ_ERR_INVALID_ARG, "factor: 0 (CholeskyQR2) or 1 (Householder)");
+    if (value < 0 || value > 2)
+      return fail(LSQ_ERR_INVALID_ARG, "factor: 0 (CholeskyQR2), 1 (Householder) or 2 (SVD preconditioner)");
     g_factor_mode = (int)value;
     return LSQ_OK;
   }

@@ -84,6 +84,11 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 __device__ __forceinline__ double wave_sum(double v) { return group_sum<LSQ_WAVE>(v); }
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int off = LSQ_WAVE / 2; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, LSQ_WAVE));
+  return v;
+}
 
 // Sums over aligned groups of G lanes, every lane of a group receiving the group's sum, without
 // LDS: DPP quad permutations (xor 1, xor 2) and mirrors (8- and 16-lane groups, whose halves are

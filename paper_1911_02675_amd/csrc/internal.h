@@ -103,7 +103,20 @@ void spd_chol_inverse(hipStream_t st, const double* Z, int64_t md, double scale,
 // SA = scale W^T Y for W upper triangular (m x m used, ld ldw) and Y (m x d, row-major).
 void haar_apply(hipStream_t st, const double* W, int64_t ldw, const double* Y, int64_t m, int64_t d, double scale,
                 double* SA, int64_t ldsa);
-extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder
+// ---- svd.hip ------------------------------------------------------------------------------------
+// One-sided Jacobi SVD of the d x d R (overwritten by Sigma V^T): W = V Sigma^+ and WT = W^T (dense),
+// singular values below rtol * sigma_max dropped.  Returns the number kept.  scratch: svd_scratch_len(d)
+// doubles; flags / hflags: 2 device ints and their pinned mirror.  *sweeps: Jacobi sweeps run.
+constexpr int SVD_MAX_SWEEPS = 40;
+constexpr double SVD_RTOL = 1e-12;  // singular values below rtol * sigma_max are dropped
+// rhat = W W^T r with the preconditioner's shape: triangular W (precond_apply) or dense W (the SVD form:
+// two full GEMVs, the same dot-product partials for r . rhat).
+void precond_apply_any(hipStream_t st, const double* W, const double* WT, int64_t d, const double* r, double* u,
+                       double* rhat, double* dotpart, int* ndot, const int* done, int dense);
+size_t svd_scratch_len(int64_t d);
+int svd_precond(hipStream_t st, double* R, int64_t d, double rtol, double* scratch, double* W, double* WT,
+                int* flags, int* hflags, int* sweeps);
+extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder, 2 = SVD (dense W)
 extern int g_srht_passb;   // tuning: FP32 SRHT pass B for large buckets, 0 = LDS-staged, 1 = register-direct
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
 constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization

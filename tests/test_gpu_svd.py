@@ -1,0 +1,103 @@
+"""SVD (LSRN) preconditioner on the GPU (lsq_tune("factor", 2): one-sided Jacobi on R, W = V Sigma^+
+dense) against the oracle.
+
+  full rank      PCG with W W^T follows the oracle's PCG iterates (the same H_S^{-1}) and R^T R = H_S
+  rank deficient duplicated / dependent columns: the dropped singular values give the rank, and PCG
+                 from x_0 = 0 reaches the minimum-norm solution, where the triangular form reports RANK
+"""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1911_02675_amd import lsq
+    c = lsq.Context()
+    yield c
+    lsq.tune("factor", 0)
+    c.close()
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("m,d,kappa", [(300, 40, 1e4), (1000, 129, 1e6)])
+def test_svd_factor_full_rank(ctx, m, d, kappa):
+    import torch
+    from oracle.pcg import svd_preconditioner
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    SA = make_problem(m, d, kappa, seed=m + d)["A"]
+    R = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    W = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    lsq.tune("factor", 2)
+    try:
+        ctx.factor(dev(SA), R, W)
+    finally:
+        lsq.tune("factor", 0)
+    Rh, Wh = R.cpu().numpy(), W.cpu().numpy()
+    H = SA.T @ SA
+    e1 = np.linalg.norm(Rh.T @ Rh - H) / np.linalg.norm(H)
+    P = svd_preconditioner(SA)
+    M = P @ P.T
+    e2 = np.linalg.norm(Wh @ Wh.T - M) / np.linalg.norm(M)
+    say("  svd factor", m, d, kappa, "|R^T R - H|/|H|", e1, "|W W^T - P P^T|/|.|", e2)
+    assert e1 <= 1e-13
+    assert e2 <= 1e-14 * kappa
+
+
+def test_svd_pcg_iterates_and_min_norm(ctx):
+    import torch
+    from oracle import sketch
+    from oracle.pcg import pcg_svd, svd_preconditioner
+    from oracle.solve import min_norm_lstsq
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    n, d, m = 8192, 48, 384
+    P = make_problem(n, d, 1e4, sigma=0.01, seed=51)
+    A, y = P["A"], P["y"]
+    x = torch.zeros(d, dtype=torch.float64, device="cuda")
+    tr = torch.zeros(7, dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc("srht", m, seed=9)
+    lsq.tune("factor", 2)
+    try:
+        # full rank: the first iterates against the oracle's PCG with its own SVD preconditioner
+        st, info = ctx.pcg_solve(dev(A), dev(y), desc, x, tol=1e-300, max_iter=6, stop_rule=1)
+        Pm = svd_preconditioner(sketch.sketch(A, "srht", m, 9, 0))
+        xo, _ = pcg_svd(A, y, Pm, fixed_iters=6)
+        e = np.linalg.norm(A @ (x.cpu().numpy() - xo)) / np.linalg.norm(A @ xo)
+        say("  svd pcg iterate 6 vs oracle:", e)
+        assert e <= 1e-10
+        # rank deficient: a repeated column and a combination of three others
+        rng = np.random.default_rng(5)
+        Ad = np.hstack([A, A[:, 7:8], A[:, :3] @ rng.standard_normal((3, 1))])
+        x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+        st, info = ctx.pcg_solve(dev(Ad), dev(y), desc, x, tol=1e-12, max_iter=100)
+        xm = min_norm_lstsq(Ad, y)
+        e = np.linalg.norm(x.cpu().numpy() - xm) / np.linalg.norm(xm)
+        say("  svd pcg rank deficient: status", st, "iters", info.iters, "|x - x+|/|x+|", e)
+        assert st == lsq.LSQ_OK
+        assert e <= 1e-9  # the null-space component of any other minimiser is O(1)
+        R = torch.empty((d + 2, d + 2), dtype=torch.float64, device="cuda")
+        SA = torch.empty((m, d + 2), dtype=torch.float64, device="cuda")
+        ctx.sketch(dev(Ad), dev(y), desc, SA)
+        ctx.factor(SA, R, None)
+        rank = int(np.sum(np.abs(R.cpu().numpy()).sum(axis=1) > 0))
+        assert rank == d
+    finally:
+        lsq.tune("factor", 0)
+    # the triangular form reports the rank deficiency
+    x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+    st, _ = ctx.pcg_solve(dev(Ad), dev(y), desc, x, tol=1e-12, max_iter=100, raise_on_error=False)
+    assert st == lsq.LSQ_ERR_RANK
