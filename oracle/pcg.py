@@ -37,6 +37,21 @@ def svd_preconditioner(SA, rtol=1e-12):
     return Vt[keep].T / s[keep][None, :]
 
 
+def qrcp_preconditioner(SA, rtol=1e-12):
+    """W = P [R11^{-1}; 0] from scipy's column-pivoted QR S A P = Q R, R11 the leading r x r block with
+    |R_kk| > rtol |R_00|: W W^T = H_S^{-1} at full rank, and the basic solution on the kept columns
+    otherwise.  Returns (W, r, piv)."""
+    import scipy.linalg
+    SA = np.asarray(SA, dtype=np.float64)
+    d = SA.shape[1]
+    _, R, piv = scipy.linalg.qr(SA, mode="economic", pivoting=True)
+    diag = np.abs(np.diag(R))
+    r = int(np.sum(diag > rtol * diag[0])) if diag[0] > 0 else 0
+    W = np.zeros((d, d))
+    W[piv[:r], :r] = np.linalg.inv(np.triu(R[:r, :r]))
+    return W, r, piv
+
+
 def pcg(A, y, R, x0=None, tol=1e-10, max_iter=200, fixed_iters=None):
     """Run PCG.  Returns (x, iterates) where iterates[t] = x_t.  With fixed_iters the loop runs
     exactly that many iterations; otherwise it stops by the rule in the module docstring."""

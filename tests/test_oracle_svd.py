@@ -61,3 +61,32 @@ def test_pcg_svd_reaches_min_norm_solution():
     _, it2 = pcg_svd(P["A"], y, Pf, fixed_iters=6)
     for a, b in zip(it1, it2):
         assert np.linalg.norm(a - b) <= 1e-8 * max(np.linalg.norm(it1[-1]), 1.0)
+
+
+def test_qrcp_preconditioner():
+    """Column-pivoted QR (scipy): |R_kk| non-increasing, S A P = Q R; W W^T = H_S^{-1} at full rank; with
+    dependent columns the rank is found and PCG gives the basic solution: zero on the dropped columns and
+    the least-squares residual (normal equations on every column)."""
+    import scipy.linalg
+
+    from oracle.pcg import pcg_with, qrcp_preconditioner
+    rng = np.random.default_rng(6)
+    SA = make_problem(300, 12, 1e3, seed=45)["A"]
+    Q, R, piv = scipy.linalg.qr(SA, mode="economic", pivoting=True)
+    dg = np.abs(np.diag(R))
+    assert np.all(dg[1:] <= dg[:-1] * (1 + 1e-12))
+    assert np.linalg.norm(SA[:, piv] - Q @ R) <= 1e-13 * np.linalg.norm(SA)
+    W, r, _ = qrcp_preconditioner(SA)
+    M = np.linalg.inv(SA.T @ SA)
+    assert r == 12 and np.linalg.norm(W @ W.T - M) <= 1e-9 * np.linalg.norm(M)
+    P = make_problem(2000, 16, 1e2, seed=46)
+    A = np.hstack([P["A"], P["A"][:, 2:3], P["A"][:, :2] @ rng.standard_normal((2, 1))])
+    y = P["y"]
+    S = rng.standard_normal((150, 2000)) / np.sqrt(150)
+    W, r, piv = qrcp_preconditioner(S @ A)
+    assert r == 16
+    x, _ = pcg_with(A, y, lambda v: W @ (W.T @ v), tol=1e-13, max_iter=100)
+    assert np.all(x[piv[r:]] == 0.0)
+    assert np.linalg.norm(A.T @ (A @ x - y)) <= 1e-9 * np.linalg.norm(A.T @ y)
+    xm = min_norm_lstsq(A, y)
+    assert abs(np.linalg.norm(A @ x - y) - np.linalg.norm(A @ xm - y)) <= 1e-10 * np.linalg.norm(y)
