@@ -193,7 +193,10 @@ lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_de
  * then one-sided Jacobi on R gives S A = U Sigma V^T; R is returned as Sigma V^T and W = V Sigma^+
  * (both dense; singular values at or below 1e-12 sigma_max dropped, their rows of R and columns of W
  * zero), and every solver then applies H_S^+ = W W^T, so that PCG from x_0 = 0 converges to the
- * minimum-norm solution of a rank-deficient problem.  R or W may be NULL.  RANK
+ * minimum-norm solution of a rank-deficient problem.  lsq_tune("factor", 3) selects column-pivoted
+ * Householder QR: R11 the leading block with |R_kk| > 1e-12 |R_00|, W = P [R11^{-1}; 0] (dense), R returned
+ * as R_pivoted P^T; PCG then returns the basic solution on the kept columns (the others exactly zero).
+ * R or W may be NULL.  RANK
  * when some |R_kk| <= 8 d eps max |R_jj|.  UNSUPPORTED for d > 1024 or m > 65536 (m > 8192 with
  * Householder). */
 lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int64_t lds, double* R,
@@ -277,7 +280,8 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
  * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
  * default 8); "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute
  * unit, else 1..65536); "factor" (0 = CholeskyQR2 with its fallbacks, the default; 1 = Householder QR
- * only; 2 = the SVD form, see lsq_factor; the batched form keeps its own Householder QR);
+ * only; 2 = the SVD form; 3 = column-pivoted QR, see lsq_factor; the batched form keeps its own
+ * Householder QR);
  * "srht_passb" (FP32 SRHT second pass for buckets of more than 24 selected rows on average: 0 = staged through LDS with every row tile of a bucket in one pass over its block
  * of the intermediate, the default; 1 = operands loaded straight into registers, six tiles per pass).
  * INVALID_ARG for an unknown key or an out-of-range value. */

@@ -271,6 +271,16 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
   double* tscr;
   CHK(wsT(c, "trinv", trinv_scratch_len(cholqr_padded(d)), &tscr));
   c->w_dense = 0;
+  if (g_factor_mode == 3) {
+    // column-pivoted QR: the basic solution on the kept columns for a rank-deficient S A
+    double* qs;
+    CHK(wsT(c, "qrcp", qrcp_scratch_len(m, d), &qs));
+    c->svd_rank = qrcp_precond(st, SA, m, d, lds, SVD_RTOL, qs, tscr, R, W, WT, c->dflags + 6, c->hflags + 6);
+    HIPCHK(hipGetLastError());
+    c->w_dense = 1;
+    if (c->svd_rank < 1) return fail(LSQ_ERR_RANK, "S A is zero");
+    return LSQ_OK;
+  }
   if (g_factor_mode == 2) {
     // SVD form: R by Householder QR (m <= 8192; a zero pivot is allowed, rank deficiency is handled by
     // the truncation) or CholeskyQR2, then one-sided Jacobi on R
@@ -1025,8 +1035,9 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     return LSQ_OK;
   }
   if (k == "factor") {
-    if (value < 0 || value > 2)
-      return fail(LSQ_ERR_INVALID_ARG, "factor: 0 (CholeskyQR2), 1 (Householder) or 2 (SVD preconditioner)");
+    if (value < 0 || value > 3)
+      return fail(LSQ_ERR_INVALID_ARG,
+                  "factor: 0 (CholeskyQR2), 1 (Householder), 2 (SVD) or 3 (column-pivoted QR)");
     g_factor_mode = (int)value;
     return LSQ_OK;
   }

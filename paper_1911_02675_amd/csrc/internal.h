@@ -116,7 +116,15 @@ void precond_apply_any(hipStream_t st, const double* W, const double* WT, int64_
 size_t svd_scratch_len(int64_t d);
 int svd_precond(hipStream_t st, double* R, int64_t d, double rtol, double* scratch, double* W, double* WT,
                 int* flags, int* hflags, int* sweeps);
-extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder, 2 = SVD (dense W)
+// ---- qrcp.hip -----------------------------------------------------------------------------------
+// Column-pivoted Householder QR of S A (m x d): R (d x d) = R_pivoted P^T, W = P [R11^{-1}; 0] and WT = W^T
+// (dense), R11 the leading r x r block with |R_kk| > rtol |R_00|.  Returns r.  scratch:
+// qrcp_scratch_len(m, d) doubles; trinv_scratch: trinv_scratch_len(d); flags / hflags: 1 device int and its
+// pinned mirror.
+size_t qrcp_scratch_len(int64_t m, int64_t d);
+int qrcp_precond(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double rtol, double* scratch,
+                 double* trinv_scratch, double* R, double* W, double* WT, int* flags, int* hflags);
+extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder, 2 = SVD, 3 = pivoted QR (2, 3: dense W)
 extern int g_srht_passb;   // tuning: FP32 SRHT pass B for large buckets, 0 = LDS-staged, 1 = register-direct
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
 constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization

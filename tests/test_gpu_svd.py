@@ -101,3 +101,59 @@ def test_svd_pcg_iterates_and_min_norm(ctx):
     x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
     st, _ = ctx.pcg_solve(dev(Ad), dev(y), desc, x, tol=1e-12, max_iter=100, raise_on_error=False)
     assert st == lsq.LSQ_ERR_RANK
+
+
+@pytest.mark.parametrize("m,d,kappa", [(300, 40, 1e4), (2000, 130, 1e6)])
+def test_qrcp_factor_full_rank(ctx, m, d, kappa):
+    import torch
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    SA = make_problem(m, d, kappa, seed=m + 2 * d)["A"]
+    R = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    W = torch.empty((d, d), dtype=torch.float64, device="cuda")
+    lsq.tune("factor", 3)
+    try:
+        ctx.factor(dev(SA), R, W)
+    finally:
+        lsq.tune("factor", 0)
+    from oracle.pcg import qrcp_preconditioner
+    Rh, Wh = R.cpu().numpy(), W.cpu().numpy()
+    H = SA.T @ SA
+    e1 = np.linalg.norm(Rh.T @ Rh - H) / np.linalg.norm(H)
+    # W W^T = H_S^{-1} is unique at full rank (the pivot order may differ); the oracle's is accurate to
+    # about u kappa, unlike an inverse of the normal equations (u kappa^2)
+    Wo, r, _ = qrcp_preconditioner(SA)
+    M = Wo @ Wo.T
+    e2 = np.linalg.norm(Wh @ Wh.T - M) / np.linalg.norm(M)
+    say("  qrcp factor", m, d, kappa, "|R^T R - H|/|H|", e1, "|W W^T - W_o W_o^T|/|.|", e2)
+    assert r == d
+    assert e1 <= 1e-13
+    assert e2 <= 1e-14 * kappa
+
+
+def test_qrcp_basic_solution(ctx):
+    import torch
+    from oracle.solve import min_norm_lstsq
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    n, d, m = 8192, 48, 384
+    P = make_problem(n, d, 1e3, sigma=0.01, seed=52)
+    rng = np.random.default_rng(8)
+    A = np.hstack([P["A"], P["A"][:, 11:12], P["A"][:, :3] @ rng.standard_normal((3, 1))])
+    y = P["y"]
+    desc = lsq.sketch_desc("srht", m, seed=10)
+    x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
+    lsq.tune("factor", 3)
+    try:
+        st, info = ctx.pcg_solve(dev(A), dev(y), desc, x, tol=1e-12, max_iter=100)
+    finally:
+        lsq.tune("factor", 0)
+    xh = x.cpu().numpy()
+    zeros = int(np.sum(xh == 0.0))
+    ne = np.linalg.norm(A.T @ (A @ xh - y)) / np.linalg.norm(A.T @ y)
+    xm = min_norm_lstsq(A, y)
+    dres = abs(np.linalg.norm(A @ xh - y) - np.linalg.norm(A @ xm - y)) / np.linalg.norm(y)
+    say("  qrcp basic solution: status", st, "iters", info.iters, "zeros", zeros, "normal eq", ne, "residual gap", dres)
+    assert st == lsq.LSQ_OK
+    assert zeros == 2  # the dropped columns stay exactly zero
+    assert ne <= 1e-9 and dres <= 1e-12
