@@ -769,7 +769,8 @@ static int srht_js_cap(int64_t N2) { return srht_js(N2); }
 // (16 values of j_a) x 64 columns are loaded two stages ahead into registers, written to a double
 // buffer in LDS (row pitch 68 floats: the 4 j_a of one MFMA step fall in distinct banks), and each
 // wavefront forms its tiles' U_e from the staged rows with two levels of +-1 fused adds (the same two
-// roundings as the butterfly).  FP32 chains of one stage (16 values of j_a) are folded into FP64.
+// roundings as the butterfly).  FP32 chains of two stages (32 values of j_a: at most 31 + 2 roundings per
+// term) are folded into FP64, within the (log2 N + 2) 2u of an FP32 SRHT since N >= 2^17 on this path.
 constexpr int SRHT_LP = 68;                     // LDS row pitch (floats)
 constexpr int SRHT_LSTAGE = 64 * SRHT_LP;       // floats per stage buffer
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
@@ -832,16 +833,20 @@ __device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, con
 }
 
 template <int TPW>
-__device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, int non, const int (&tv)[TPW],
-                                                 const uint32_t (&ka)[TPW], const float (&s1)[TPW],
-                                                 const float (&s2)[TPW], uint32_t ja_stage, int kk, int qi,
-                                                 lsq_f4v (&acc)[TPW][4]) {
+__device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, int non, const float (&pos)[TPW],
+                                                 const uint32_t (&ka)[TPW], const uint32_t (&lowpar)[TPW],
+                                                 const float (&s1)[TPW], const float (&s2)[TPW],
+                                                 uint32_t ja_stage, int kk, int qi, lsq_f4v (&acc)[TPW][4]) {
+  // (-1)^{k_a . j_a} with j_a = ja_stage + 4 step + kk, ja_stage a multiple of 16: the parity splits into
+  // that of k_a & ja_stage (once per stage) and that of k_a & (4 step + kk) (bit `step` of lowpar)
+  uint32_t sb[TPW];
+#pragma unroll
+  for (int i = 0; i < TPW; ++i) sb[i] = lowpar[i] ^ ((__popc(ka[i] & ja_stage) & 1) ? 0xFu : 0u);
 #pragma unroll 1
   for (int step = 0; step < 4; ++step) {
-    const uint32_t ja = ja_stage + 4 * step + kk;
     float a[TPW];
 #pragma unroll
-    for (int i = 0; i < TPW; ++i) a[i] = tv[i] ? ((__popc(ka[i] & ja) & 1) ? -1.f : 1.f) : 0.f;
+    for (int i = 0; i < TPW; ++i) a[i] = ((sb[i] >> step) & 1u) ? -pos[i] : pos[i];
     const float* r = L + (16 * step + 4 * kk) * SRHT_LP + qi;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
@@ -898,8 +903,8 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
     for (int tg = 0; tg < nt; tg += 4 * TPW) {
       // tiles tg + wv + 4 i, i < non, exist (non is uniform per wavefront)
       const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));
-      int tv[TPW];
-      uint32_t ka[TPW];
+      float pos[TPW];  // 1 for a lane's row slot that holds a row, 0 for an empty slot
+      uint32_t ka[TPW], lowpar[TPW];
       float s1[TPW], s2[TPW];
       lsq_f4v acc[TPW][4];
       lsq_d4 acc64[TPW][4];
@@ -907,8 +912,11 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
       for (int i = 0; i < TPW; ++i) {
         const int t = tg + wv + 4 * i;
         const int q = t < nt ? S.tq[t][qi] : -1;
-        tv[i] = q >= 0;
+        pos[i] = q >= 0 ? 1.f : 0.f;
         ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
+        lowpar[i] = 0u;
+#pragma unroll
+        for (int step = 0; step < 4; ++step) lowpar[i] |= (uint32_t)(__popc(ka[i] & (uint32_t)(4 * step + kk)) & 1) << step;
         const int e = t < nt ? S.te[t] : 0;
         s1[i] = (e & 1) ? -1.f : 1.f;
         s2[i] = (e & 2) ? -1.f : 1.f;
@@ -940,13 +948,12 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
       gload(min(2, nst - 1), ra);
       for (int st = 0; st < nst; st += 2) {
         // even stage: LDS buffer 0, next stage (st + 1) in rb, st + 2 in ra
-        srht_lds_compute<TPW>(L, non, tv, ka, s1, s2, ja0 + 16 * st, kk, qi, acc);
-        fold();
+        srht_lds_compute<TPW>(L, non, pos, ka, lowpar, s1, s2, ja0 + 16 * st, kk, qi, acc);
         lstore(1, rb);
         lds_barrier();
         gload(min(st + 3, nst - 1), rb);
         // odd stage: LDS buffer 1, next stage (st + 2) in ra, st + 3 in rb
-        srht_lds_compute<TPW>(L + SRHT_LSTAGE, non, tv, ka, s1, s2, ja0 + 16 * (st + 1), kk, qi, acc);
+        srht_lds_compute<TPW>(L + SRHT_LSTAGE, non, pos, ka, lowpar, s1, s2, ja0 + 16 * (st + 1), kk, qi, acc);
         fold();
         lstore(0, ra);
         lds_barrier();
