@@ -763,9 +763,9 @@ static int srht_js(int64_t N2) {
 static int srht_js_cap(int64_t N2) { return srht_js(N2); }
 
 // Large buckets, FP32 T, staged through LDS: the same fold by the 4-point transform as above, with
-// every tile of a bucket (up to 4 TPW per sweep) carried in one pass over its T block, so the block is
-// read from HBM once.  Workgroup: bucket k_lo, a j_hi range, 64 columns; wavefront w owns tiles
-// w, w + 4, ... (TPW of them) over all 64 columns (four 16-column MFMA blocks).  Stages of 64 T rows
+// every tile of a bucket (up to NW TPW per sweep) carried in one pass over its T block, so the block is
+// read from HBM once.  Workgroup: bucket k_lo, a j_hi range, 64 columns, NW wavefronts; wavefront w owns
+// tiles w, w + NW, ... (TPW of them) over all 64 columns (four 16-column MFMA blocks).  Stages of 64 T rows
 // (16 values of j_a) x 64 columns are loaded two stages ahead into registers, written to a double
 // buffer in LDS (row pitch 68 floats: the 4 j_a of one MFMA step fall in distinct banks), and each
 // wavefront forms its tiles' U_e from the staged rows with two levels of +-1 fused adds (the same two
@@ -863,8 +863,8 @@ __device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, in
   }
 }
 
-template <int TPW>
-__global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restrict__ T, int64_t N2, int64_t d,
+template <int TPW, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds(const float* __restrict__ T, int64_t N2, int64_t d,
                                                            int64_t dT, int L1, const int64_t* __restrict__ rows,
                                                            const int* __restrict__ slot,
                                                            const int* __restrict__ order,
@@ -885,24 +885,25 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
   const int qi = lane & 15, kk = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.z * 64;
   double* out = partial + (int64_t)js * m * d;
-  // staging map: thread -> rows lr + 16 i (i < 4) of a stage, columns lc .. lc + 3
+  // staging map: thread -> rows lr + 4 NW i (i < 16 / NW) of a stage, columns lc .. lc + 3
   // (columns past dT read the row's last 4 columns instead: those lanes' LDS words are never output)
   const int lr = tid >> 4, lc = (tid & 15) * 4;
   const float* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 4);
-  auto gload = [&](int st, f4(&v)[4]) {
+  constexpr int LI = 16 / NW;  // loads per thread per stage
+  auto gload = [&](int st, f4(&v)[LI]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-      v[i] = __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 16 * i) * dT));
+    for (int i = 0; i < LI; ++i)
+      v[i] = __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 4 * NW * i) * dT));
   };
-  auto lstore = [&](int buf, const f4(&v)[4]) {
+  auto lstore = [&](int buf, const f4(&v)[LI]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) *(f4*)(L + buf * SRHT_LSTAGE + (lr + 16 * i) * SRHT_LP + lc) = v[i];
+    for (int i = 0; i < LI; ++i) *(f4*)(L + buf * SRHT_LSTAGE + (lr + 4 * NW * i) * SRHT_LP + lc) = v[i];
   };
   for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
     const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
-    for (int tg = 0; tg < nt; tg += 4 * TPW) {
-      // tiles tg + wv + 4 i, i < non, exist (non is uniform per wavefront)
-      const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));
+    for (int tg = 0; tg < nt; tg += NW * TPW) {
+      // tiles tg + wv + NW i, i < non, exist (non is uniform per wavefront)
+      const int non = max(0, min(TPW, (nt - tg - wv + NW - 1) / NW));
       float pos[TPW];  // 1 for a lane's row slot that holds a row, 0 for an empty slot
       uint32_t ka[TPW], lowpar[TPW];
       float s1[TPW], s2[TPW];
@@ -910,7 +911,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
       lsq_d4 acc64[TPW][4];
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + 4 * i;
+        const int t = tg + wv + NW * i;
         const int q = t < nt ? S.tq[t][qi] : -1;
         pos[i] = q >= 0 ? 1.f : 0.f;
         ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
@@ -937,7 +938,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
           }
       };
       // two stages in flight in registers, one being consumed from LDS
-      f4 ra[4], rb[4];
+      f4 ra[LI], rb[LI];
       // nst is even.  Loads are issued without conditions (stages past the last reload the last one,
       // never used) so that the compiler's wait counts stay exact and two stages stay in flight.
       gload(0, ra);
@@ -961,7 +962,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds(const float* __restri
       }
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + 4 * i;
+        const int t = tg + wv + NW * i;
         if (t >= nt) continue;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -1158,13 +1159,19 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
   if constexpr (sizeof(TC) == 4) {
     const int64_t wgc = big ? 128 : 256;  // 64 VW columns per workgroup
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + wgc - 1) / wgc));
-    if (big && p.N2 >= 512 && g_srht_passb == 0) {
-      // up to 8 tiles per pass over the bucket's T block (two per wavefront); larger buckets take more
+    if (big && p.N2 >= 512 && g_srht_passb != 1) {
+      // up to 8 tiles per pass over the bucket's T block; larger buckets take more
       const int64_t ncb = (dT + 63) / 64;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
-      hipLaunchKernelGGL(k_srht_passB_lds<2>, gl, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
-                         order, bstart, p.m, partial);
+      // default: 8 wavefronts of one tile each (122 registers: four wavefronts per SIMD hide more latency
+      // than two at 226 registers with two tiles each, at twice the LDS reads); 2: the two-tile form
+      if (g_srht_passb == 2)
+        hipLaunchKernelGGL((k_srht_passB_lds<2, 4>), gl, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows,
+                           slot, order, bstart, p.m, partial);
+      else
+        hipLaunchKernelGGL((k_srht_passB_lds<1, 8>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1, rows,
+                           slot, order, bstart, p.m, partial);
     } else if (big && p.N2 >= 512)
       hipLaunchKernelGGL(k_srht_passB_f32w, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
@@ -1174,7 +1181,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     else
       hipLaunchKernelGGL(k_srht_passB_f32<2>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
-  } else if (big && p.N2 >= 512 && g_srht_passb == 0) {
+  } else if (big && p.N2 >= 512 && g_srht_passb != 1) {
     // tiles per wavefront from the expected bucket: e-groups of about m / (4 N1) rows, two standard
     // deviations over, in tiles of 16, over 4 wavefronts (at most 3 each); larger buckets take more
     // passes over T
