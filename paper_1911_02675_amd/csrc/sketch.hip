@@ -987,8 +987,8 @@ __global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds(const float* __re
 constexpr int SRHT_LP64 = 68;                    // LDS row pitch (doubles)
 constexpr int SRHT_LSTAGE64 = 32 * SRHT_LP64;    // doubles per stage buffer
 
-template <int TPW>
-__global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __restrict__ T, int64_t N2, int64_t d,
+template <int TPW, int NW>
+__global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds64(const double* __restrict__ T, int64_t N2, int64_t d,
                                                              int64_t dT, int L1, const int64_t* __restrict__ rows,
                                                              const int* __restrict__ slot,
                                                              const int* __restrict__ order,
@@ -1009,28 +1009,30 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
   const int qi = lane & 15, kk = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.z * 64;
   double* out = partial + (int64_t)js * m * d;
-  // staging map: thread -> rows lr + 8 i (i < 4) of a stage, columns lc, lc + 1
+  // staging map: thread -> rows lr + 2 NW i (i < 16 / NW) of a stage, columns lc, lc + 1
   const int lr = tid >> 5, lc = (tid & 31) * 2;
+  constexpr int LI = 16 / NW;
   const double* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 2);
-  auto gload = [&](int st, d2(&v)[4]) {
+  auto gload = [&](int st, d2(&v)[LI]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) v[i] = __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 8 * i) * dT));
+    for (int i = 0; i < LI; ++i)
+      v[i] = __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 2 * NW * i) * dT));
   };
-  auto lstore = [&](int buf, const d2(&v)[4]) {
+  auto lstore = [&](int buf, const d2(&v)[LI]) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) *(d2*)(L + buf * SRHT_LSTAGE64 + (lr + 8 * i) * SRHT_LP64 + lc) = v[i];
+    for (int i = 0; i < LI; ++i) *(d2*)(L + buf * SRHT_LSTAGE64 + (lr + 2 * NW * i) * SRHT_LP64 + lc) = v[i];
   };
   for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
     const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
-    for (int tg = 0; tg < nt; tg += 4 * TPW) {
-      const int non = max(0, min(TPW, (nt - tg - wv + 3) / 4));  // uniform per wavefront
+    for (int tg = 0; tg < nt; tg += NW * TPW) {
+      const int non = max(0, min(TPW, (nt - tg - wv + NW - 1) / NW));  // uniform per wavefront
       int tv[TPW];
       uint32_t ka[TPW];
       double s1[TPW], s2[TPW];
       lsq_d4 acc[TPW][4];
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + 4 * i;
+        const int t = tg + wv + NW * i;
         const int q = t < nt ? S.tq[t][qi] : -1;
         tv[i] = q >= 0;
         ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
@@ -1061,7 +1063,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
           }
         }
       };
-      d2 ra[4], rb[4];
+      d2 ra[LI], rb[LI];
       gload(0, ra);  // as in the FP32 form: nst even, unconditional loads
       gload(1, rb);
       lds_barrier();
@@ -1080,7 +1082,7 @@ __global__ __launch_bounds__(256, 2) void k_srht_passB_lds64(const double* __res
       }
 #pragma unroll
       for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + 4 * i;
+        const int t = tg + wv + NW * i;
         if (t >= nt) continue;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
@@ -1191,10 +1193,10 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     const double g = (double)p.m / (4.0 * (double)p.N1);
     const int tiles = 4 * (int)ceil((g + 2.0 * sqrt(g)) / 16.0);
     if (tiles <= 8)
-      hipLaunchKernelGGL(k_srht_passB_lds64<2>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+      hipLaunchKernelGGL((k_srht_passB_lds64<2, 4>), gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
-    else
-      hipLaunchKernelGGL(k_srht_passB_lds64<3>, gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+    else  // (eight wavefronts of two tiles, one workgroup per CU, measured no faster for larger buckets)
+      hipLaunchKernelGGL((k_srht_passB_lds64<3, 4>), gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
   } else if (big) {
     constexpr int WGC = SRHT_WGC / 2;
