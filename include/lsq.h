@@ -282,10 +282,11 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
  * unit, else 1..65536); "factor" (0 = CholeskyQR2 with its fallbacks, the default; 1 = Householder QR
  * only; 2 = the SVD form; 3 = column-pivoted QR, see lsq_factor; the batched form keeps its own
  * Householder QR);
- * "srht_passb" (FP32 SRHT second pass for buckets of more than 24 selected rows on average:
- * 0 = staged through LDS with every row tile of a bucket in one pass over its block of the
- * intermediate, eight wavefronts of one tile each, the default; 1 = operands loaded straight into
- * registers, six tiles per pass; 2 = staged through LDS, four wavefronts of two tiles each).
+ * "srht_passb" (SRHT second pass for buckets of more than 24 selected rows on average:
+ * 0 = staged through LDS, sixteen wavefronts of one row tile each, so that up to 16 tiles of a bucket
+ * share one pass over its block of the intermediate, the default; 1 = operands loaded straight into
+ * registers (FP32 intermediate; the FP64 one takes its general form); 2 = staged through LDS, eight
+ * wavefronts, the same arithmetic per element as 0).
  * INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
 

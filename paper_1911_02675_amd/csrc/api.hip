@@ -1044,8 +1044,8 @@ lsq_status lsq_tune(const char* key, int64_t value) {
   if (k == "srht_passb") {
     if (value < 0 || value > 2)
       return fail(LSQ_ERR_INVALID_ARG,
-                  "srht_passb: 0 (LDS-staged, 8 wavefronts x 1 tile, the default), 1 (register-direct) or "
-                  "2 (LDS-staged, 4 wavefronts x 2 tiles)");
+                  "srht_passb: 0 (LDS-staged, 16 wavefronts, the default), 1 (register-direct) or "
+                  "2 (LDS-staged, 8 wavefronts)");
     g_srht_passb = (int)value;
     return LSQ_OK;
   }

@@ -22,7 +22,7 @@ namespace lsq {
 constexpr int SRHT_N1_MAX = 512;
 
 // --------------------------------------------------------------------------------------------------
-// Grouping of the selected rows by k_lo (single workgroup).
+// Grouping of the selected rows by k_lo (single workgroup): bucket counts, their scan, a scatter.
 // --------------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void k_srht_groups(const int64_t* __restrict__ rows, int64_t m,
                                                       int N1, int* __restrict__ slot,
@@ -75,21 +75,9 @@ __global__ __launch_bounds__(1024) void k_srht_groups(const int64_t* __restrict_
     const int pos = atomicAdd(&cur[rows[q] & (N1 - 1)], 1);
     order[pos] = (int)q;
   }
-  __threadfence_block();
-  __syncthreads();
-  // insertion sort inside each bucket (buckets hold about m / N1 entries)
-  if (tid < N1) {
-    const int b0 = bstart[tid], b1 = b0 + c;
-    for (int i = b0 + 1; i < b1; ++i) {
-      const int v = order[i];
-      int k = i - 1;
-      while (k >= b0 && order[k] > v) {
-        order[k + 1] = order[k];
-        --k;
-      }
-      order[k + 1] = v;
-    }
-  }
+  // The order inside a bucket is left as the atomics made it: every selected row's value is a sum over
+  // j_hi computed by itself (the rows sharing a tile only share the loads of T), so no output bit depends
+  // on it.
   (void)sh;
 }
 
@@ -762,17 +750,6 @@ static int srht_js(int64_t N2) {
 }
 static int srht_js_cap(int64_t N2) { return srht_js(N2); }
 
-// Large buckets, FP32 T, staged through LDS: the same fold by the 4-point transform as above, with
-// every tile of a bucket (up to NW TPW per sweep) carried in one pass over its T block, so the block is
-// read from HBM once.  Workgroup: bucket k_lo, a j_hi range, 64 columns, NW wavefronts; wavefront w owns
-// tiles w, w + NW, ... (TPW of them) over all 64 columns (four 16-column MFMA blocks).  Stages of 64 T rows
-// (16 values of j_a) x 64 columns are loaded two stages ahead into registers, written to a double
-// buffer in LDS (row pitch 68 floats: the 4 j_a of one MFMA step fall in distinct banks), and each
-// wavefront forms its tiles' U_e from the staged rows with two levels of +-1 fused adds (the same two
-// roundings as the butterfly).  FP32 chains of two stages (32 values of j_a: at most 31 + 2 roundings per
-// term) are folded into FP64, within the (log2 N + 2) 2u of an FP32 SRHT since N >= 2^17 on this path.
-constexpr int SRHT_LP = 68;                     // LDS row pitch (floats)
-constexpr int SRHT_LSTAGE = 64 * SRHT_LP;       // floats per stage buffer
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
 constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 4; // tiles per build at most
 
@@ -832,115 +809,169 @@ __device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, con
   return S.nt;
 }
 
-template <int TPW>
-__device__ __forceinline__ void srht_lds_compute(const float* __restrict__ L, int non, const float (&pos)[TPW],
-                                                 const uint32_t (&ka)[TPW], const uint32_t (&lowpar)[TPW],
-                                                 const float (&s1)[TPW], const float (&s2)[TPW],
-                                                 uint32_t ja_stage, int kk, int qi, lsq_f4v (&acc)[TPW][4]) {
-  // (-1)^{k_a . j_a} with j_a = ja_stage + 4 step + kk, ja_stage a multiple of 16: the parity splits into
-  // that of k_a & ja_stage (once per stage) and that of k_a & (4 step + kk) (bit `step` of lowpar)
-  uint32_t sb[TPW];
-#pragma unroll
-  for (int i = 0; i < TPW; ++i) sb[i] = lowpar[i] ^ ((__popc(ka[i] & ja_stage) & 1) ? 0xFu : 0u);
-#pragma unroll 1
-  for (int step = 0; step < 4; ++step) {
-    float a[TPW];
-#pragma unroll
-    for (int i = 0; i < TPW; ++i) a[i] = ((sb[i] >> step) & 1u) ? -pos[i] : pos[i];
-    const float* r = L + (16 * step + 4 * kk) * SRHT_LP + qi;
-#pragma unroll
-    for (int cb = 0; cb < 4; ++cb) {
-      const float t0 = r[16 * cb], t1 = r[SRHT_LP + 16 * cb], t2 = r[2 * SRHT_LP + 16 * cb],
-                  t3 = r[3 * SRHT_LP + 16 * cb];
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        if (i >= non) break;  // the wavefront's tiles past the bucket's last (uniform)
-        // U_e = (t0 + s1 t1) + s2 (t2 + s1 t3), s1 = (-1)^{e_0}, s2 = (-1)^{e_1}
-        const float u = fmaf(s2[i], fmaf(s1[i], t3, t2), fmaf(s1[i], t1, t0));
-        acc[i][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], u, acc[i][cb], 0, 0, 0);
-      }
-    }
-  }
-}
+// Pass B over large buckets, staged through LDS with the fold by the 4-point transform done once per
+// staged element: the thread that loads rows 4 j_a + b (b = 0..3) of a column forms
+// U_e = sum_b (-1)^{popcount(e & b)} T[4 j_a + b] for all four e with one butterfly (the same two
+// roundings, in the same order, as the fold at the point of use) and stores the four U_e.  A wavefront
+// then reads its tile's U_e directly: one LDS read of four columns per MFMA step.
+//   Workgroup: bucket k_lo, a j_hi range, 64 columns, NW wavefronts; wavefront w owns tile w (then
+// w + NW, ... in later sweeps when a chunk has more than NW tiles) over all 64 columns, as four
+// 16-column MFMA blocks interleaved so that a lane's B operands are adjacent in LDS (FP32: block cb,
+// lane column qi is column 4 qi + cb).  With NW = 16 one sweep carries every tile of a typical bucket, so
+// the bucket's T block is read from HBM once.
+//   Stages of JA values of j_a (4 JA rows of T) x 64 columns are loaded two stages ahead into
+// registers, written as U_e[j_a][column] to a double buffer in LDS, and consumed JA / 4 MFMA steps
+// per stage.  FP32 T: JA = 32, chains of one stage (32 values of j_a: at most 31 + 2 roundings per term)
+// folded into FP64, within the (log2 N + 2) 2u of an FP32 SRHT since N >= 2^17 on this path.  FP64 T:
+// JA = 16, FP64 MFMA, no fold.
+template <typename TC>
+struct SrhtU;
+template <>
+struct SrhtU<float> {
+  static constexpr int JA = 32;  // j_a per stage
+  static constexpr int VU = 2;   // columns per staging unit (one 8-byte load per row)
+  typedef float vu_t __attribute__((ext_vector_type(2)));
+  // column of MFMA block c at lane column qi: a lane's four columns adjacent (one 16-byte LDS read)
+  static __device__ __forceinline__ int col(int qi, int c) { return 4 * qi + c; }
+};
+template <>
+struct SrhtU<double> {
+  static constexpr int JA = 16;
+  static constexpr int VU = 1;
+  typedef double vu_t;
+  // columns 2 qi, 2 qi + 1 (blocks 0, 1) and 32 + 2 qi, 33 + 2 qi (blocks 2, 3): two 16-byte LDS reads,
+  // each contiguous over the 16 lanes of a j_a
+  static __device__ __forceinline__ int col(int qi, int c) { return 32 * (c >> 1) + 2 * qi + (c & 1); }
+};
 
-template <int TPW, int NW>
-__global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds(const float* __restrict__ T, int64_t N2, int64_t d,
+template <typename TC, int NW>
+__global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restrict__ T, int64_t N2, int64_t d,
                                                            int64_t dT, int L1, const int64_t* __restrict__ rows,
                                                            const int* __restrict__ slot,
                                                            const int* __restrict__ order,
                                                            const int* __restrict__ bstart, int64_t m,
                                                            double* __restrict__ partial) {
-  typedef float f4 __attribute__((ext_vector_type(4)));
-  __shared__ __attribute__((aligned(16))) float L[2 * SRHT_LSTAGE];
+  constexpr int JA = SrhtU<TC>::JA, VU = SrhtU<TC>::VU;
+  constexpr int STAGE = 4 * JA * 64;            // elements per LDS stage buffer: U_e[j_a][64 columns]
+  constexpr int UNITS = JA * (64 / VU);         // staging units (j_a, column group) per stage
+  constexpr int UPT = UNITS / (64 * NW);        // units per thread
+  constexpr int NSTEP = JA / 4;                 // MFMA steps per stage
+  static_assert(UPT >= 1 && UNITS % (64 * NW) == 0, "staging map");
+  typedef typename SrhtU<TC>::vu_t vu_t;
+  __shared__ __attribute__((aligned(16))) TC L[2 * STAGE];
   __shared__ SrhtTiles S;
   const int klo = blockIdx.x;
   const int sl = slot[klo];
   if (sl < 0) return;
   const int js = blockIdx.y, JS = gridDim.y;
-  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 64
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 8 JA
   const uint32_t ja0 = (uint32_t)(jh0 >> 2);
-  const int nst = (int)((jh1 - jh0) >> 6);                      // stages of 64 T rows
+  const int nst = (int)((jh1 - jh0) / (4 * JA));                 // even
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int qi = lane & 15, kk = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.z * 64;
   double* out = partial + (int64_t)js * m * d;
-  // staging map: thread -> rows lr + 4 NW i (i < 16 / NW) of a stage, columns lc .. lc + 3
-  // (columns past dT read the row's last 4 columns instead: those lanes' LDS words are never output)
-  const int lr = tid >> 4, lc = (tid & 15) * 4;
-  const float* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 4);
-  constexpr int LI = 16 / NW;  // loads per thread per stage
-  auto gload = [&](int st, f4(&v)[LI]) {
+  // staging map: unit tid + 64 NW i -> j_a group uq (rows 4 uq + b of the stage), columns uc .. uc + VU - 1
+  // (columns past dT read the row's last VU columns instead: those LDS words are never output)
+  const TC* gsrc[UPT];
+  int lofs[UPT];
 #pragma unroll
-    for (int i = 0; i < LI; ++i)
-      v[i] = __builtin_nontemporal_load((const f4*)(gsrc + ((int64_t)64 * st + 4 * NW * i) * dT));
+  for (int i = 0; i < UPT; ++i) {
+    const int u = tid + 64 * NW * i;
+    const int uq = u / (64 / VU), uc = (u % (64 / VU)) * VU;
+    gsrc[i] = T + ((int64_t)sl * N2 + jh0 + 4 * uq) * dT + (c0 + uc < dT ? c0 + uc : dT - VU);
+    lofs[i] = uq * 64 + uc;
+  }
+  auto gload = [&](int st, vu_t(&v)[UPT][4]) {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        v[i][b] = __builtin_nontemporal_load((const vu_t*)(gsrc[i] + ((int64_t)(4 * JA) * st + b) * dT));
   };
-  auto lstore = [&](int buf, const f4(&v)[LI]) {
+  auto lstore = [&](int buf, const vu_t(&v)[UPT][4]) {
 #pragma unroll
-    for (int i = 0; i < LI; ++i) *(f4*)(L + buf * SRHT_LSTAGE + (lr + 4 * NW * i) * SRHT_LP + lc) = v[i];
+    for (int i = 0; i < UPT; ++i) {
+      const vu_t p0 = v[i][0] + v[i][1], p1 = v[i][0] - v[i][1];
+      const vu_t p2 = v[i][2] + v[i][3], p3 = v[i][2] - v[i][3];
+      TC* w = L + buf * STAGE + lofs[i];
+      *(vu_t*)(w) = p0 + p2;               // e = 0
+      *(vu_t*)(w + JA * 64) = p1 + p3;     // e = 1
+      *(vu_t*)(w + 2 * JA * 64) = p0 - p2; // e = 2
+      *(vu_t*)(w + 3 * JA * 64) = p1 - p3; // e = 3
+    }
   };
   for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
-    const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
-    for (int tg = 0; tg < nt; tg += NW * TPW) {
-      // tiles tg + wv + NW i, i < non, exist (non is uniform per wavefront)
-      const int non = max(0, min(TPW, (nt - tg - wv + NW - 1) / NW));
-      float pos[TPW];  // 1 for a lane's row slot that holds a row, 0 for an empty slot
-      uint32_t ka[TPW], lowpar[TPW];
-      float s1[TPW], s2[TPW];
-      lsq_f4v acc[TPW][4];
-      lsq_d4 acc64[TPW][4];
+    const int nt = __builtin_amdgcn_readfirstlane(srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1));
+    for (int tg = 0; tg < nt; tg += NW) {
+      const int t = tg + wv;
+      const bool has = t < nt;  // uniform per wavefront
+      const int q = has ? S.tq[t][qi] : -1;
+      const TC pos = q >= 0 ? (TC)1 : (TC)0;
+      const uint32_t ka = q >= 0 ? S.tka[t][qi] : 0u;
+      const int e = has ? S.te[t] : 0;
+      // (-1)^{k_a . j_a} with j_a = ja_stage + 4 s + kk, ja_stage a multiple of JA: the parity splits into
+      // that of k_a & ja_stage (once per stage) and that of k_a & (4 s + kk) (bit s of lowpar)
+      uint32_t lowpar = 0u;
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + NW * i;
-        const int q = t < nt ? S.tq[t][qi] : -1;
-        pos[i] = q >= 0 ? 1.f : 0.f;
-        ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
-        lowpar[i] = 0u;
+      for (int s = 0; s < NSTEP; ++s) lowpar |= (uint32_t)(__popc(ka & (uint32_t)(4 * s + kk)) & 1) << s;
+      constexpr uint32_t ALL = (1u << NSTEP) - 1u;
+      const int rofs = (e * JA + kk) * 64 + SrhtU<TC>::col(qi, 0);
+      typedef float f4 __attribute__((ext_vector_type(4)));
+      typedef double d2 __attribute__((ext_vector_type(2)));
+      lsq_f4v acc[4];
+      lsq_d4 acc64[4];
 #pragma unroll
-        for (int step = 0; step < 4; ++step) lowpar[i] |= (uint32_t)(__popc(ka[i] & (uint32_t)(4 * step + kk)) & 1) << step;
-        const int e = t < nt ? S.te[t] : 0;
-        s1[i] = (e & 1) ? -1.f : 1.f;
-        s2[i] = (e & 2) ? -1.f : 1.f;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          acc[i][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
-          acc64[i][c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
-        }
+      for (int c = 0; c < 4; ++c) {
+        acc[c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+        acc64[c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
       }
-      auto fold = [&]() {
+      auto compute = [&](const TC* Lb, uint32_t ja_stage) {
+        if (!has) return;
+        const uint32_t sb = lowpar ^ ((__popc(ka & ja_stage) & 1) ? ALL : 0u);
+        const TC* r = Lb + rofs;
+        if constexpr (sizeof(TC) == 4) {
+          // each step's LDS read is issued before the previous step's MFMAs
+          f4 un = *(const f4*)r;
 #pragma unroll
-        for (int i = 0; i < TPW; ++i)
+          for (int s = 0; s < NSTEP; ++s) {
+            const f4 u = un;
+            if (s + 1 < NSTEP) un = *(const f4*)(r + 4 * (s + 1) * 64);
+            const float a = ((sb >> s) & 1u) ? -pos : pos;
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.x, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.y, acc[1], 0, 0, 0);
+            acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.z, acc[2], 0, 0, 0);
+            acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.w, acc[3], 0, 0, 0);
+          }
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[i][c][v] += (double)acc[i][c][v];
-            acc[i][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+            for (int v = 0; v < 4; ++v) acc64[c][v] += (double)acc[c][v];
+            acc[c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
           }
+        } else {
+          d2 un0 = *(const d2*)r, un1 = *(const d2*)(r + 32);
+#pragma unroll
+          for (int s = 0; s < NSTEP; ++s) {
+            const d2 u0 = un0, u1 = un1;
+            if (s + 1 < NSTEP) {
+              un0 = *(const d2*)(r + 4 * (s + 1) * 64);
+              un1 = *(const d2*)(r + 4 * (s + 1) * 64 + 32);
+            }
+            const double a = ((sb >> s) & 1u) ? -pos : pos;
+            acc64[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.x, acc64[0], 0, 0, 0);
+            acc64[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.y, acc64[1], 0, 0, 0);
+            acc64[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u1.x, acc64[2], 0, 0, 0);
+            acc64[3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u1.y, acc64[3], 0, 0, 0);
+          }
+        }
       };
-      // two stages in flight in registers, one being consumed from LDS
-      f4 ra[LI], rb[LI];
-      // nst is even.  Loads are issued without conditions (stages past the last reload the last one,
-      // never used) so that the compiler's wait counts stay exact and two stages stay in flight.
+      // two stages in flight in registers, one being consumed from LDS.  nst is even; loads are issued
+      // without conditions (stages past the last reload the last one, never used) so that the compiler's
+      // wait counts stay exact and two stages stay in flight.
+      vu_t ra[UPT][4], rb[UPT][4];
       gload(0, ra);
       gload(1, rb);
       lds_barrier();  // the previous sweep's last stage has been consumed
@@ -948,150 +979,26 @@ __global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds(const float* __re
       lds_barrier();
       gload(min(2, nst - 1), ra);
       for (int st = 0; st < nst; st += 2) {
-        // even stage: LDS buffer 0, next stage (st + 1) in rb, st + 2 in ra
-        srht_lds_compute<TPW>(L, non, pos, ka, lowpar, s1, s2, ja0 + 16 * st, kk, qi, acc);
+        compute(L, ja0 + JA * st);
         lstore(1, rb);
         lds_barrier();
         gload(min(st + 3, nst - 1), rb);
-        // odd stage: LDS buffer 1, next stage (st + 2) in ra, st + 3 in rb
-        srht_lds_compute<TPW>(L + SRHT_LSTAGE, non, pos, ka, lowpar, s1, s2, ja0 + 16 * (st + 1), kk, qi, acc);
-        fold();
+        compute(L + STAGE, ja0 + JA * (st + 1));
         lstore(0, ra);
         lds_barrier();
         gload(min(st + 4, nst - 1), ra);
       }
+      if (has) {
+        // result lane l, register v: tile row 4 (l / 16) + v (FP32 MFMA) or l / 16 + 4 v (FP64 MFMA)
 #pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + NW * i;
-        if (t >= nt) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t col = c0 + 16 * c + qi;
-          if (col >= d) continue;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int q = S.tq[t][4 * kk + v];
-            if (q >= 0) out[(int64_t)order[q] * d + col] = acc64[i][c][v];
-          }
-        }
-      }
-    }
-  }
-}
-
-// The same for FP64 T (no FP32 chains to fold: the tiles accumulate in FP64 directly, so a wavefront
-// carries up to TPW = 3 tiles).  Stages of 32 T rows (8 values of j_a, two MFMA steps) x 64 columns,
-// row pitch 68 doubles (the four j_a of a step fall in the two bank halves, two lane groups each).
-// v_mfma_f64_16x16x4: A and B operands as in the FP32 form; result lane l, register v holds tile row
-// l / 16 + 4 v, column l % 16 of its block.
-constexpr int SRHT_LP64 = 68;                    // LDS row pitch (doubles)
-constexpr int SRHT_LSTAGE64 = 32 * SRHT_LP64;    // doubles per stage buffer
-
-template <int TPW, int NW>
-__global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds64(const double* __restrict__ T, int64_t N2, int64_t d,
-                                                             int64_t dT, int L1, const int64_t* __restrict__ rows,
-                                                             const int* __restrict__ slot,
-                                                             const int* __restrict__ order,
-                                                             const int* __restrict__ bstart, int64_t m,
-                                                             double* __restrict__ partial) {
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  __shared__ __attribute__((aligned(16))) double L[2 * SRHT_LSTAGE64];
-  __shared__ SrhtTiles S;
-  const int klo = blockIdx.x;
-  const int sl = slot[klo];
-  if (sl < 0) return;
-  const int js = blockIdx.y, JS = gridDim.y;
-  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 64
-  const uint32_t ja0 = (uint32_t)(jh0 >> 2);
-  const int nst = (int)((jh1 - jh0) >> 5);                      // stages of 32 T rows
-  const int b0 = bstart[klo], b1 = bstart[klo + 1];
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int qi = lane & 15, kk = lane >> 4;
-  const int64_t c0 = (int64_t)blockIdx.z * 64;
-  double* out = partial + (int64_t)js * m * d;
-  // staging map: thread -> rows lr + 2 NW i (i < 16 / NW) of a stage, columns lc, lc + 1
-  const int lr = tid >> 5, lc = (tid & 31) * 2;
-  constexpr int LI = 16 / NW;
-  const double* gsrc = T + ((int64_t)sl * N2 + jh0 + lr) * dT + (c0 + lc < dT ? c0 + lc : dT - 2);
-  auto gload = [&](int st, d2(&v)[LI]) {
-#pragma unroll
-    for (int i = 0; i < LI; ++i)
-      v[i] = __builtin_nontemporal_load((const d2*)(gsrc + ((int64_t)32 * st + 2 * NW * i) * dT));
-  };
-  auto lstore = [&](int buf, const d2(&v)[LI]) {
-#pragma unroll
-    for (int i = 0; i < LI; ++i) *(d2*)(L + buf * SRHT_LSTAGE64 + (lr + 2 * NW * i) * SRHT_LP64 + lc) = v[i];
-  };
-  for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
-    const int nt = srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1);
-    for (int tg = 0; tg < nt; tg += NW * TPW) {
-      const int non = max(0, min(TPW, (nt - tg - wv + NW - 1) / NW));  // uniform per wavefront
-      int tv[TPW];
-      uint32_t ka[TPW];
-      double s1[TPW], s2[TPW];
-      lsq_d4 acc[TPW][4];
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + NW * i;
-        const int q = t < nt ? S.tq[t][qi] : -1;
-        tv[i] = q >= 0;
-        ka[i] = q >= 0 ? S.tka[t][qi] : 0u;
-        const int e = t < nt ? S.te[t] : 0;
-        s1[i] = (e & 1) ? -1.0 : 1.0;
-        s2[i] = (e & 2) ? -1.0 : 1.0;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[i][c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
-      }
-      auto compute = [&](const double* Lb, uint32_t ja_stage) {
-#pragma unroll 1
-        for (int step = 0; step < 2; ++step) {
-          const uint32_t ja = ja_stage + 4 * step + kk;
-          double a[TPW];
-#pragma unroll
-          for (int i = 0; i < TPW; ++i) a[i] = tv[i] ? ((__popc(ka[i] & ja) & 1) ? -1.0 : 1.0) : 0.0;
-          const double* r = Lb + (16 * step + 4 * kk) * SRHT_LP64 + qi;
+        for (int v = 0; v < 4; ++v) {
+          const int qq = S.tq[t][sizeof(TC) == 4 ? 4 * kk + v : kk + 4 * v];
+          if (qq < 0) continue;
+          double* o = out + (int64_t)order[qq] * d;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const double t0 = r[16 * c], t1 = r[SRHT_LP64 + 16 * c], t2 = r[2 * SRHT_LP64 + 16 * c],
-                         t3 = r[3 * SRHT_LP64 + 16 * c];
-#pragma unroll
-            for (int i = 0; i < TPW; ++i) {
-              if (i >= non) break;
-              const double u = fma(s2[i], fma(s1[i], t3, t2), fma(s1[i], t1, t0));
-              acc[i][c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], u, acc[i][c], 0, 0, 0);
-            }
-          }
-        }
-      };
-      d2 ra[LI], rb[LI];
-      gload(0, ra);  // as in the FP32 form: nst even, unconditional loads
-      gload(1, rb);
-      lds_barrier();
-      lstore(0, ra);
-      lds_barrier();
-      gload(min(2, nst - 1), ra);
-      for (int st = 0; st < nst; st += 2) {
-        compute(L, ja0 + 8 * st);
-        lstore(1, rb);
-        lds_barrier();
-        gload(min(st + 3, nst - 1), rb);
-        compute(L + SRHT_LSTAGE64, ja0 + 8 * (st + 1));
-        lstore(0, ra);
-        lds_barrier();
-        gload(min(st + 4, nst - 1), ra);
-      }
-#pragma unroll
-      for (int i = 0; i < TPW; ++i) {
-        const int t = tg + wv + NW * i;
-        if (t >= nt) continue;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int64_t col = c0 + 16 * c + qi;
-          if (col >= d) continue;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int q = S.tq[t][kk + 4 * v];
-            if (q >= 0) out[(int64_t)order[q] * d + col] = acc[i][c][v];
+            const int64_t col = c0 + SrhtU<TC>::col(qi, c);
+            if (col < d) o[col] = acc64[c][v];
           }
         }
       }
@@ -1100,10 +1007,10 @@ __global__ __launch_bounds__(64 * NW, 2) void k_srht_passB_lds64(const double* _
 }
 
 // j_hi ranges of the LDS-staged pass B: about 8192 workgroups in all, at most the partial buffer's
-// ranges, at least one stage (64 rows of T) per range.
+// ranges, at least two stages (256 rows of T for FP32, 128 for FP64) per range.
 static int srht_js_lds(int64_t N1, int64_t N2, int64_t ncb) {
   int js = 1;
-  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 128 && 2 * js <= srht_js_cap(N2)) js *= 2;
+  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 256 && 2 * js <= srht_js_cap(N2)) js *= 2;
   return js;
 }
 
@@ -1162,18 +1069,16 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     const int64_t wgc = big ? 128 : 256;  // 64 VW columns per workgroup
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + wgc - 1) / wgc));
     if (big && p.N2 >= 512 && g_srht_passb != 1) {
-      // up to 8 tiles per pass over the bucket's T block; larger buckets take more
       const int64_t ncb = (dT + 63) / 64;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
-      // default: 8 wavefronts of one tile each (122 registers: four wavefronts per SIMD hide more latency
-      // than two at 226 registers with two tiles each, at twice the LDS reads); 2: the two-tile form
+      // default: sixteen wavefronts, one sweep over T for up to 16 tiles; 2: eight wavefronts
       if (g_srht_passb == 2)
-        hipLaunchKernelGGL((k_srht_passB_lds<2, 4>), gl, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows,
-                           slot, order, bstart, p.m, partial);
+        hipLaunchKernelGGL((k_srht_passB_u<float, 8>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
+                           rows, slot, order, bstart, p.m, partial);
       else
-        hipLaunchKernelGGL((k_srht_passB_lds<1, 8>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1, rows,
-                           slot, order, bstart, p.m, partial);
+        hipLaunchKernelGGL((k_srht_passB_u<float, 16>), gl, dim3(1024), 0, st, (const float*)T, p.N2, d, dT, L1,
+                           rows, slot, order, bstart, p.m, partial);
     } else if (big && p.N2 >= 512)
       hipLaunchKernelGGL(k_srht_passB_f32w, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
@@ -1184,20 +1089,15 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       hipLaunchKernelGGL(k_srht_passB_f32<2>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
   } else if (big && p.N2 >= 512 && g_srht_passb != 1) {
-    // tiles per wavefront from the expected bucket: e-groups of about m / (4 N1) rows, two standard
-    // deviations over, in tiles of 16, over 4 wavefronts (at most 3 each); larger buckets take more
-    // passes over T
     const int64_t ncb = (dT + 63) / 64;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
-    const double g = (double)p.m / (4.0 * (double)p.N1);
-    const int tiles = 4 * (int)ceil((g + 2.0 * sqrt(g)) / 16.0);
-    if (tiles <= 8)
-      hipLaunchKernelGGL((k_srht_passB_lds64<2, 4>), gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+    if (g_srht_passb == 2)
+      hipLaunchKernelGGL((k_srht_passB_u<double, 8>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
-    else  // (eight wavefronts of two tiles, one workgroup per CU, measured no faster for larger buckets)
-      hipLaunchKernelGGL((k_srht_passB_lds64<3, 4>), gl, dim3(256), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
-                         slot, order, bstart, p.m, partial);
+    else
+      hipLaunchKernelGGL((k_srht_passB_u<double, 16>), gl, dim3(1024), 0, st, (const double*)T, p.N2, d, dT, L1,
+                         rows, slot, order, bstart, p.m, partial);
   } else if (big) {
     constexpr int WGC = SRHT_WGC / 2;
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + WGC - 1) / WGC));

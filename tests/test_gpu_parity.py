@@ -154,6 +154,33 @@ def test_srht_sketch(ctx, n, d, m):
     assert np.all(np.abs(got32 - ref32) <= 8 * (math.log2(N) + 2) * 2.0 ** -24 * scale)
 
 
+@pytest.mark.parametrize("n,d,m", [(300000, 130, 20000), (1 << 17, 20, 100000)])
+def test_srht_pass_b_forms(ctx, n, d, m):
+    """The large-bucket forms of the sampled transform (tuning key srht_passb: 0 sixteen wavefronts,
+    2 eight, 1 register-direct for FP32 T) all meet the oracle bound; 0 and 2 take the same arithmetic per
+    output element and agree bitwise."""
+    from oracle import draws, sketch
+    from paper_1911_02675_amd import lsq
+    say("srht pass B forms", n, d, m)
+    A = np.random.default_rng(n - d).standard_normal((n, d))
+    N = draws.padded_length(n)
+    scale = np.abs(A).sum(axis=0)[None, :] / math.sqrt(m)
+    ref = sketch.srht_sketch(A, m, 9, 2)
+    ref32 = sketch.srht_sketch(A.astype(np.float32).astype(np.float64), m, 9, 2)
+    got = {}
+    try:
+        for mode in (0, 1, 2):
+            lsq.tune("srht_passb", mode)
+            got[mode] = (_sa(ctx, A, "srht", m, seed=9, t=2),
+                         _sa(ctx, A.astype(np.float32), "srht", m, seed=9, t=2, compute="f32"))
+    finally:
+        lsq.tune("srht_passb", 0)
+    for mode, (g64, g32) in got.items():
+        assert np.all(np.abs(g64 - ref) <= 8 * (math.log2(N) + 2) * EPS * scale), mode
+        assert np.all(np.abs(g32 - ref32) <= 8 * (math.log2(N) + 2) * 2.0 ** -24 * scale), mode
+    assert np.array_equal(got[0][0], got[2][0]) and np.array_equal(got[0][1], got[2][1])
+
+
 @pytest.mark.parametrize("n,d,m,s", [(100, 3, 16, 1), (5000, 64, 256, 4), (20001, 100, 512, 8),
                                      (9000, 257, 64, 2), (4096, 32, 4096, 1)])
 def test_sjlt_sketch(ctx, n, d, m, s):
