@@ -129,9 +129,12 @@ __global__ __launch_bounds__(1024) void k_gram_shift(const double* __restrict__ 
 // --------------------------------------------------------------------------------------------------
 // Diagonal block kb in one wavefront: lane j holds column j of the block in registers.  Step k takes
 // the pivot from lane k, scales row k (element k of every lane), publishes it through LDS, and every
-// lane j > k subtracts r_ki r_kj from its elements k < i <= j.  Then R_kk and its inverse (column j
-// by back substitution in lane j, rows of R_kk read from LDS) are written.  A pivot that is not
-// positive sets *flag and is replaced by 1 so that the factorization completes.
+// lane subtracts r_ki r_kj from its elements i > k.  Entries below the diagonal (i > j in lane j) are
+// updated too, without masks, and never read into a result: this keeps the step free of per-element
+// selects, so the LDS reads of row k can all be in flight together.  Then R_kk and its inverse are
+// written; the inverse overwrites the registers bottom-up (row i of X = R_kk^{-1} needs rows k > i of X
+// and row i of R_kk, which stays in LDS).  A pivot that is not positive sets *flag and is replaced by 1
+// so that the factorization completes.
 
 __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
                                                   double* __restrict__ R, double* __restrict__ Dinv,
@@ -149,27 +152,26 @@ __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, 
     bad = bad || !(piv > 0.0);
     const double rkk = piv > 0.0 ? sqrt(piv) : 1.0;
     const double inv = 1.0 / rkk;
-    a[k] = j == k ? rkk : (j > k ? a[k] * inv : a[k]);
-    Rs[k][j] = j >= k ? a[k] : 0.0;
+    a[k] = j == k ? rkk : a[k] * inv;
+    Rs[k][j] = a[k];  // row k of R_kk in entries j >= k
     __syncthreads();
 #pragma unroll
-    for (int i = k + 1; i < CQ_T; ++i)
-      if (i <= j) a[i] = fma(-Rs[k][i], a[k], a[i]);
+    for (int i = k + 1; i < CQ_T; ++i) a[i] = fma(-Rs[k][i], a[k], a[i]);
   }
   if (j == 0 && bad) *flag = 1;
 #pragma unroll
   for (int i = 0; i < CQ_T; ++i) R[(o + i) * dp + o + j] = i <= j ? a[i] : 0.0;
-  // inverse, column j: R w = e_j bottom-up
-  double w[CQ_T];
+  // inverse, column j: X[i][j] = (delta_ij - sum_{k > i} R[i][k] X[k][j]) / R[i][i], i = 63 .. 0, with
+  // X[k][j] = 0 for k > j
 #pragma unroll
   for (int i = CQ_T - 1; i >= 0; --i) {
     double s = 0.0;
 #pragma unroll
-    for (int k = i + 1; k < CQ_T; ++k) s = fma(Rs[i][k], w[k], s);
-    w[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / Rs[i][i]);
+    for (int k = i + 1; k < CQ_T; ++k) s = fma(Rs[i][k], a[k], s);
+    a[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / Rs[i][i]);
   }
 #pragma unroll
-  for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = w[i];
+  for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = a[i];
 }
 
 // Block row kb: R_kj = Dinv^T G_kj for column tiles right of the diagonal block.  One wavefront per

@@ -860,7 +860,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   typedef typename SrhtU<TC>::vu_t vu_t;
   __shared__ __attribute__((aligned(16))) TC L[2 * STAGE];
   __shared__ SrhtTiles S;
-  const int klo = blockIdx.x;
+  // column block fastest in the grid: workgroups that run together read whole rows of T
+  const int klo = blockIdx.z;
   const int sl = slot[klo];
   if (sl < 0) return;
   const int js = blockIdx.y, JS = gridDim.y;
@@ -871,7 +872,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int qi = lane & 15, kk = lane >> 4;
-  const int64_t c0 = (int64_t)blockIdx.z * 64;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
   double* out = partial + (int64_t)js * m * d;
   // staging map: unit tid + 64 NW i -> j_a group uq (rows 4 uq + b of the stage), columns uc .. uc + VU - 1
   // (columns past dT read the row's last VU columns instead: those LDS words are never output)
@@ -1071,7 +1072,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     if (big && p.N2 >= 512 && g_srht_passb != 1) {
       const int64_t ncb = (dT + 63) / 64;
       JS = srht_js_lds(p.N1, p.N2, ncb);
-      dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
+      dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
       // default: sixteen wavefronts, one sweep over T for up to 16 tiles; 2: eight wavefronts
       if (g_srht_passb == 2)
         hipLaunchKernelGGL((k_srht_passB_u<float, 8>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
@@ -1091,7 +1092,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
   } else if (big && p.N2 >= 512 && g_srht_passb != 1) {
     const int64_t ncb = (dT + 63) / 64;
     JS = srht_js_lds(p.N1, p.N2, ncb);
-    dim3 gl((unsigned)p.N1, (unsigned)JS, (unsigned)ncb);
+    dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
     if (g_srht_passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
