@@ -26,12 +26,18 @@ constexpr int CQ_LP = 65;  // padded LDS row (doubles)
 // --------------------------------------------------------------------------------------------------
 // Gram partials: part[s] = X[rows of split s]^T X[rows of split s] on the upper 64 x 64 tiles.
 // Grid (upper tile pairs, S).  Four wavefronts, each a 32 x 32 quarter of the tile (2 x 2 blocks of
-// 16 x 16).  Columns at or past d read as zero.
+// 16 x 16).  Stages of 32 rows of both 64-column slices pass through LDS; the next stage is loaded into
+// registers while the MFMAs consume the current one.  Columns at or past d read as zero.  VEC: d and
+// ldx even and X 16-byte aligned (16-byte loads of column pairs).
 // --------------------------------------------------------------------------------------------------
+constexpr int GR_KS = 32;  // rows of X per stage
+
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ X, int64_t m, int64_t d,
                                                    int64_t ldx, int64_t dp, double* __restrict__ part) {
-  __shared__ double As[CQ_KS][CQ_LP];
-  __shared__ double Bs[CQ_KS][CQ_LP];
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double As[GR_KS][CQ_LP];
+  __shared__ double Bs[GR_KS][CQ_LP];
   const int nt = (int)(dp / CQ_T);
   // tile pair p -> (bi, bj), bi <= bj, row-major over the upper triangle
   int p = blockIdx.x, bi = 0;
@@ -44,25 +50,50 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ X,
   const int64_t r0 = m * s / S, r1 = m * (s + 1) / S;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv >> 1, wj = wv & 1;
-  const int lr = tid >> 4, lc = (tid & 15) * 4;  // loader: row lr of the stage, 4 columns from lc
+  const int lr = tid >> 5, lc = (tid & 31) * 2;  // loader: rows lr + 8 i, columns lc, lc + 1 of both slices
   const int64_t i0 = (int64_t)bi * CQ_T, j0 = (int64_t)bj * CQ_T;
+  d2 ra[4], rb[4];
+  // loads are unconditional (addresses clamped into the matrix) and the values are masked when they
+  // are stored to LDS, so that the next stage's loads stay in flight during the MFMAs
+  const int64_t ca = i0 + lc, cb = j0 + lc;
+  auto ldpair = [&](const double* xr, int64_t c) -> d2 {
+    if constexpr (VEC)
+      return *(const d2*)(xr + (c < d ? c : 0));
+    else
+      return (d2){xr[c < d ? c : 0], xr[c + 1 < d ? c + 1 : 0]};
+  };
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t r = k0 + lr + 8 * i;
+      const double* xr = X + (r < r1 ? r : r0) * ldx;
+      ra[i] = ldpair(xr, ca);
+      rb[i] = ldpair(xr, cb);
+    }
+  };
   lsq_c_d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (lsq_c_d4){0.0, 0.0, 0.0, 0.0};
-  for (int64_t k0 = r0; k0 < r1; k0 += CQ_KS) {
-    const int64_t r = k0 + lr;
-    const bool rok = r < r1;
+  load(r0);
+  for (int64_t k0 = r0; k0 < r1; k0 += GR_KS) {
+    __syncthreads();  // the previous stage has been consumed
+    // rows past r1 and columns past d as zero: multiplied by 0 (the loads read elements of X, which are
+    // finite wherever the Gram is), so that no load is moved into a branch
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t ca = i0 + lc + e, cb = j0 + lc + e;
-      As[lr][lc + e] = (rok && ca < d) ? X[r * ldx + ca] : 0.0;
-      Bs[lr][lc + e] = (rok && cb < d) ? X[r * ldx + cb] : 0.0;
+    for (int i = 0; i < 4; ++i) {
+      const double rok = k0 + lr + 8 * i < r1 ? 1.0 : 0.0;
+      As[lr + 8 * i][lc] = ra[i].x * (ca < d ? rok : 0.0);
+      As[lr + 8 * i][lc + 1] = ra[i].y * (ca + 1 < d ? rok : 0.0);
+      Bs[lr + 8 * i][lc] = rb[i].x * (cb < d ? rok : 0.0);
+      Bs[lr + 8 * i][lc + 1] = rb[i].y * (cb + 1 < d ? rok : 0.0);
     }
     __syncthreads();
+    load(k0 + GR_KS);  // past r1: never stored
+    asm volatile("" ::: "memory");  // keeps the loads here, ahead of the MFMAs
 #pragma unroll
-    for (int kk = 0; kk < CQ_KS; kk += 4) {
+    for (int kk = 0; kk < GR_KS; kk += 4) {
       double av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = As[kk + (lane >> 4)][32 * wi + 16 * a + (lane & 15)];
@@ -73,7 +104,6 @@ __global__ __launch_bounds__(256) void k_gram_part(const double* __restrict__ X,
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d(av[a], bv[b], acc[a][b]);
     }
-    __syncthreads();
   }
   double* out = part + (int64_t)s * dp * dp;
 #pragma unroll
@@ -356,8 +386,10 @@ int64_t cholqr_padded(int64_t d) { return (d + CQ_T - 1) / CQ_T * CQ_T; }
 
 static int gram_splits(int64_t m, int64_t dp) {
   const int64_t tiles = (dp / CQ_T) * (dp / CQ_T + 1) / 2;
-  int64_t s = (1024 + tiles - 1) / tiles;  // about 1024 workgroups
-  const int64_t smax = (m + 255) / 256;    // at least 256 rows per split
+  // about 2048 workgroups: two rounds of four per compute unit (33 KB of LDS each), so that the last
+  // round is nearly full
+  int64_t s = (2048 + tiles / 2) / tiles;
+  const int64_t smax = (m + 255) / 256;  // at least 256 rows per split
   s = s > smax ? smax : s;
   return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));
 }
@@ -372,8 +404,11 @@ static void gram(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t 
                  const double* shift, double* G) {
   const int S = gram_splits(m, dp);
   const int64_t nt = dp / CQ_T;
-  hipLaunchKernelGGL(k_gram_part, dim3((unsigned)(nt * (nt + 1) / 2), (unsigned)S), dim3(256), 0, st, X, m, d, ldx,
-                     dp, part);
+  const dim3 grid((unsigned)(nt * (nt + 1) / 2), (unsigned)S);
+  if (d % 2 == 0 && ldx % 2 == 0 && (uintptr_t)X % 16 == 0)
+    hipLaunchKernelGGL(k_gram_part<true>, grid, dim3(256), 0, st, X, m, d, ldx, dp, part);
+  else
+    hipLaunchKernelGGL(k_gram_part<false>, grid, dim3(256), 0, st, X, m, d, ldx, dp, part);
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((dp * dp + 255) / 256)), dim3(256), 0, st, part, S, d, dp, shift,
                      G);
 }
