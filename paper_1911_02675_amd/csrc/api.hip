@@ -1042,10 +1042,10 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     return LSQ_OK;
   }
   if (k == "srht_passb") {
-    if (value < 0 || value > 2)
+    if (value < 0 || value > 4)
       return fail(LSQ_ERR_INVALID_ARG,
-                  "srht_passb: 0 (LDS-staged, 16 wavefronts, the default), 1 (register-direct) or "
-                  "2 (LDS-staged, 8 wavefronts)");
+                  "srht_passb: 0 (LDS-staged, fold width by bucket size, the default), 1 (register-direct), "
+                  "2 (LDS-staged, 8 wavefronts), 3 (16 wavefronts, 4-point fold) or 4 (16 wavefronts, 8-point fold)");
     g_srht_passb = (int)value;
     return LSQ_OK;
   }

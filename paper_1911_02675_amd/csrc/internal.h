@@ -125,7 +125,7 @@ size_t qrcp_scratch_len(int64_t m, int64_t d);
 int qrcp_precond(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double rtol, double* scratch,
                  double* trinv_scratch, double* R, double* W, double* WT, int* flags, int* hflags);
 extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder, 2 = SVD, 3 = pivoted QR (2, 3: dense W)
-extern int g_srht_passb;   // tuning: SRHT pass B for large buckets, 0 = LDS-staged (16 wavefronts), 1 = register-direct, 2 = LDS-staged (8)
+extern int g_srht_passb;   // tuning: SRHT pass B for large buckets, 0 = LDS-staged (16 wavefronts, fold width by bucket size), 1 = register-direct, 2 = LDS-staged (8), 3 / 4 = 16 wavefronts, 4- / 8-point fold
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
 constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 

@@ -751,7 +751,7 @@ static int srht_js(int64_t N2) {
 static int srht_js_cap(int64_t N2) { return srht_js(N2); }
 
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
-constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 4; // tiles per build at most
+constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 8; // tiles per build at most (up to 8 fold groups)
 
 // Workgroup barrier for data exchanged through LDS only: this wavefront's LDS accesses complete
 // (lgkmcnt), then s_barrier; loads from global memory stay in flight (__syncthreads also drains them).
@@ -764,34 +764,36 @@ __device__ __forceinline__ void lds_barrier() {
 }
 
 // Row tiles of one chunk [cb, ce) of a bucket's selected rows (ce - cb <= SRHT_LROWS), grouped by
-// e = k_hi & 3 in tiles of 16 (the order of rows inside a tile does not change any output row; empty
-// slots stay -1): one thread per row places itself with an LDS counter per group.  All threads of the
-// workgroup call it; returns the tile count.
+// e = k_hi mod F (F = 2^FB, the width of the fold) in tiles of 16 (the order of rows inside a tile does not
+// change any output row; empty slots stay -1): one thread per row places itself with an LDS counter per
+// group.  All threads of the workgroup call it; returns the tile count.
 struct SrhtTiles {
   int tq[SRHT_LMAXT][16];        // order[] positions of the tile's rows (-1: empty)
-  uint32_t tka[SRHT_LMAXT][16];  // k_a = k_hi >> 2 of each row
+  uint32_t tka[SRHT_LMAXT][16];  // k_a = k_hi >> FB of each row
   int te[SRHT_LMAXT];            // e of the tile
-  int cnt[4], tbase[4], nt;
+  int cnt[8], tbase[8], nt;
 };
 
+template <int FB>
 __device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, const int64_t* __restrict__ rows,
                                                const int* __restrict__ order, int L1) {
+  constexpr int F = 1 << FB;
   const int tid = threadIdx.x;
   __syncthreads();  // the previous chunk's tiles are no longer read
   for (int i = tid; i < SRHT_LMAXT * 16; i += blockDim.x) S.tq[i / 16][i % 16] = -1;
-  if (tid < 4) S.cnt[tid] = 0;
+  if (tid < F) S.cnt[tid] = 0;
   __syncthreads();
   int e_me = 0, slot_me = 0;
   uint32_t khi_me = 0;
   if (tid < ce - cb) {
     khi_me = (uint32_t)((uint64_t)rows[order[cb + tid]] >> L1);
-    e_me = (int)(khi_me & 3);
+    e_me = (int)(khi_me & (F - 1));
     slot_me = atomicAdd(&S.cnt[e_me], 1);
   }
   __syncthreads();
   if (tid == 0) {
     int nt = 0;
-    for (int e = 0; e < 4; ++e) {
+    for (int e = 0; e < F; ++e) {
       S.tbase[e] = nt;
       const int k = (S.cnt[e] + 15) / 16;
       for (int t = 0; t < k; ++t) S.te[nt + t] = e;
@@ -803,61 +805,81 @@ __device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, con
   if (tid < ce - cb) {
     const int t = S.tbase[e_me] + slot_me / 16;
     S.tq[t][slot_me % 16] = cb + tid;
-    S.tka[t][slot_me % 16] = khi_me >> 2;
+    S.tka[t][slot_me % 16] = khi_me >> FB;
   }
   __syncthreads();
   return S.nt;
 }
 
-// Pass B over large buckets, staged through LDS with the fold by the 4-point transform done once per
-// staged element: the thread that loads rows 4 j_a + b (b = 0..3) of a column forms
-// U_e = sum_b (-1)^{popcount(e & b)} T[4 j_a + b] for all four e with one butterfly (the same two
-// roundings, in the same order, as the fold at the point of use) and stores the four U_e.  A wavefront
-// then reads its tile's U_e directly: one LDS read of four columns per MFMA step.
+// Pass B over large buckets, staged through LDS with the fold by the F-point transform (F = 2^FB, 4 or
+// 8) done once per staged element: the thread that loads rows F j_a + b (b < F) of a column forms
+// U_e = sum_b (-1)^{popcount(e & b)} T[F j_a + b] for every e < F with one in-place butterfly and stores
+// them.  A tile's rows share e = k_hi mod F, and (-1)^{k_hi . j_hi} = (-1)^{k_a . j_a} (-1)^{e . b} with
+// k_hi = F k_a + e, j_hi = F j_a + b, so a row's value is sum_{j_a} (-1)^{k_a . j_a} U_e[j_a]: N2 / F MFMA
+// terms instead of N2.  A wavefront reads its tile's U_e directly, one LDS read per MFMA step.  The
+// wider fold takes fewer MFMA terms per row but splits a bucket into more, emptier tiles (F groups of
+// tiles of 16); F = 8 pays once groups average about 10 rows or more.
 //   Workgroup: bucket k_lo, a j_hi range, 64 columns, NW wavefronts; wavefront w owns tile w (then
 // w + NW, ... in later sweeps when a chunk has more than NW tiles) over all 64 columns, as four
 // 16-column MFMA blocks interleaved so that a lane's B operands are adjacent in LDS (FP32: block cb,
 // lane column qi is column 4 qi + cb).  With NW = 16 one sweep carries every tile of a typical bucket, so
 // the bucket's T block is read from HBM once.
-//   Stages of JA values of j_a (4 JA rows of T) x 64 columns are loaded two stages ahead into
-// registers, written as U_e[j_a][column] to a double buffer in LDS, and consumed JA / 4 MFMA steps
-// per stage.  FP32 T: JA = 32, chains of one stage (32 values of j_a: at most 31 + 2 roundings per term)
-// folded into FP64, within the (log2 N + 2) 2u of an FP32 SRHT since N >= 2^17 on this path.  FP64 T:
-// JA = 16, FP64 MFMA, no fold.
-template <typename TC>
+//   Stages of JA values of j_a (F JA rows of T) x 64 columns are loaded two stages ahead into registers,
+// written as U_e[j_a][column] to a double buffer in LDS, and consumed JA / 4 MFMA steps per stage.
+// FP32 T: FP32 chains of 32 values of j_a (at most 31 + FB roundings per term) folded into FP64, within
+// the (log2 N + 2) 2u of an FP32 SRHT since N >= 2^17 on this path.  FP64 T: FP64 MFMA, no fold.
+template <typename TC, int FB>
 struct SrhtU;
 template <>
-struct SrhtU<float> {
+struct SrhtU<float, 2> {
   static constexpr int JA = 32;  // j_a per stage
   static constexpr int VU = 2;   // columns per staging unit (one 8-byte load per row)
   typedef float vu_t __attribute__((ext_vector_type(2)));
-  // column of MFMA block c at lane column qi: a lane's four columns adjacent (one 16-byte LDS read)
-  static __device__ __forceinline__ int col(int qi, int c) { return 4 * qi + c; }
 };
 template <>
-struct SrhtU<double> {
+struct SrhtU<float, 3> {
+  static constexpr int JA = 16;
+  static constexpr int VU = 1;
+  typedef float vu_t;
+};
+template <>
+struct SrhtU<double, 2> {
   static constexpr int JA = 16;
   static constexpr int VU = 1;
   typedef double vu_t;
-  // columns 2 qi, 2 qi + 1 (blocks 0, 1) and 32 + 2 qi, 33 + 2 qi (blocks 2, 3): two 16-byte LDS reads,
-  // each contiguous over the 16 lanes of a j_a
-  static __device__ __forceinline__ int col(int qi, int c) { return 32 * (c >> 1) + 2 * qi + (c & 1); }
 };
+template <>
+struct SrhtU<double, 3> {
+  static constexpr int JA = 8;  // 512 staging units: the first eight wavefronts stage, all compute
+  static constexpr int VU = 1;
+  typedef double vu_t;
+};
+// column of MFMA block c at lane column qi.  FP32: a lane's four columns adjacent (one 16-byte LDS read);
+// FP64: columns 2 qi, 2 qi + 1 (blocks 0, 1) and 32 + 2 qi, 33 + 2 qi (blocks 2, 3), two 16-byte LDS
+// reads, each contiguous over the 16 lanes of a j_a.
+template <typename TC>
+__device__ __forceinline__ int srht_ucol(int qi, int c) {
+  return sizeof(TC) == 4 ? 4 * qi + c : 32 * (c >> 1) + 2 * qi + (c & 1);
+}
 
-template <typename TC, int NW>
+template <typename TC, int NW, int FB>
 __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restrict__ T, int64_t N2, int64_t d,
                                                            int64_t dT, int L1, const int64_t* __restrict__ rows,
                                                            const int* __restrict__ slot,
                                                            const int* __restrict__ order,
                                                            const int* __restrict__ bstart, int64_t m,
                                                            double* __restrict__ partial) {
-  constexpr int JA = SrhtU<TC>::JA, VU = SrhtU<TC>::VU;
-  constexpr int STAGE = 4 * JA * 64;            // elements per LDS stage buffer: U_e[j_a][64 columns]
+  constexpr int F = 1 << FB;
+  constexpr int JA = SrhtU<TC, FB>::JA, VU = SrhtU<TC, FB>::VU;
+  constexpr int STAGE = F * JA * 64;            // elements per LDS stage buffer: U_e[j_a][64 columns]
   constexpr int UNITS = JA * (64 / VU);         // staging units (j_a, column group) per stage
-  constexpr int UPT = UNITS / (64 * NW);        // units per thread
+  constexpr bool PART = UNITS < 64 * NW;        // only threads tid < UNITS stage (whole wavefronts)
+  constexpr int UPT = PART ? 1 : UNITS / (64 * NW);  // units per staging thread
   constexpr int NSTEP = JA / 4;                 // MFMA steps per stage
-  static_assert(UPT >= 1 && UNITS % (64 * NW) == 0, "staging map");
-  typedef typename SrhtU<TC>::vu_t vu_t;
+  constexpr int FOLD = 32 / JA;                 // stages per FP32 chain (32 values of j_a)
+  static_assert(PART ? UNITS % 64 == 0 : UNITS % (64 * NW) == 0, "staging map");
+  static_assert(sizeof(TC) == 8 || FOLD == 1 || FOLD == 2, "chain length");
+  typedef typename SrhtU<TC, FB>::vu_t vu_t;
   __shared__ __attribute__((aligned(16))) TC L[2 * STAGE];
   __shared__ SrhtTiles S;
   // column block fastest in the grid: workgroups that run together read whole rows of T
@@ -865,47 +887,60 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   const int sl = slot[klo];
   if (sl < 0) return;
   const int js = blockIdx.y, JS = gridDim.y;
-  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 8 JA
-  const uint32_t ja0 = (uint32_t)(jh0 >> 2);
-  const int nst = (int)((jh1 - jh0) / (4 * JA));                 // even
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of 2 F JA
+  const uint32_t ja0 = (uint32_t)(jh0 >> FB);
+  const int nst = (int)((jh1 - jh0) / (F * JA));                 // even
   const int b0 = bstart[klo], b1 = bstart[klo + 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int qi = lane & 15, kk = lane >> 4;
   const int64_t c0 = (int64_t)blockIdx.x * 64;
   double* out = partial + (int64_t)js * m * d;
-  // staging map: unit tid + 64 NW i -> j_a group uq (rows 4 uq + b of the stage), columns uc .. uc + VU - 1
+  // staging map: unit tid + 64 NW i -> j_a group uq (rows F uq + b of the stage), columns uc .. uc + VU - 1
   // (columns past dT read the row's last VU columns instead: those LDS words are never output)
+  const bool stager = !PART || tid < UNITS;  // uniform per wavefront
   const TC* gsrc[UPT];
   int lofs[UPT];
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
-    const int u = tid + 64 * NW * i;
+    const int u = stager ? tid + 64 * NW * i : 0;
     const int uq = u / (64 / VU), uc = (u % (64 / VU)) * VU;
-    gsrc[i] = T + ((int64_t)sl * N2 + jh0 + 4 * uq) * dT + (c0 + uc < dT ? c0 + uc : dT - VU);
+    gsrc[i] = T + ((int64_t)sl * N2 + jh0 + F * uq) * dT + (c0 + uc < dT ? c0 + uc : dT - VU);
     lofs[i] = uq * 64 + uc;
   }
-  auto gload = [&](int st, vu_t(&v)[UPT][4]) {
+  auto gload = [&](int st, vu_t(&v)[UPT][F]) {
+    if (!stager) return;
 #pragma unroll
     for (int i = 0; i < UPT; ++i)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        v[i][b] = __builtin_nontemporal_load((const vu_t*)(gsrc[i] + ((int64_t)(4 * JA) * st + b) * dT));
+      for (int b = 0; b < F; ++b)
+        v[i][b] = __builtin_nontemporal_load((const vu_t*)(gsrc[i] + ((int64_t)(F * JA) * st + b) * dT));
   };
-  auto lstore = [&](int buf, const vu_t(&v)[UPT][4]) {
+  auto lstore = [&](int buf, const vu_t(&v)[UPT][F]) {
+    if (!stager) return;
 #pragma unroll
     for (int i = 0; i < UPT; ++i) {
-      const vu_t p0 = v[i][0] + v[i][1], p1 = v[i][0] - v[i][1];
-      const vu_t p2 = v[i][2] + v[i][3], p3 = v[i][2] - v[i][3];
+      vu_t x[F];
+#pragma unroll
+      for (int b = 0; b < F; ++b) x[b] = v[i][b];
+      // in-place butterfly: afterwards x[e] = U_e (natural order)
+#pragma unroll
+      for (int h = 1; h < F; h <<= 1)
+#pragma unroll
+        for (int b = 0; b < F; ++b)
+          if ((b & h) == 0) {
+            const vu_t p = x[b], q = x[b + h];
+            x[b] = p + q;
+            x[b + h] = p - q;
+          }
       TC* w = L + buf * STAGE + lofs[i];
-      *(vu_t*)(w) = p0 + p2;               // e = 0
-      *(vu_t*)(w + JA * 64) = p1 + p3;     // e = 1
-      *(vu_t*)(w + 2 * JA * 64) = p0 - p2; // e = 2
-      *(vu_t*)(w + 3 * JA * 64) = p1 - p3; // e = 3
+#pragma unroll
+      for (int e = 0; e < F; ++e) *(vu_t*)(w + e * JA * 64) = x[e];
     }
   };
   for (int cb = b0; cb < b1; cb += SRHT_LROWS) {
-    const int nt = __builtin_amdgcn_readfirstlane(srht_tile_build(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1));
+    const int nt =
+        __builtin_amdgcn_readfirstlane(srht_tile_build<FB>(S, cb, min(b1, cb + SRHT_LROWS), rows, order, L1));
     for (int tg = 0; tg < nt; tg += NW) {
       const int t = tg + wv;
       const bool has = t < nt;  // uniform per wavefront
@@ -919,7 +954,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
 #pragma unroll
       for (int s = 0; s < NSTEP; ++s) lowpar |= (uint32_t)(__popc(ka & (uint32_t)(4 * s + kk)) & 1) << s;
       constexpr uint32_t ALL = (1u << NSTEP) - 1u;
-      const int rofs = (e * JA + kk) * 64 + SrhtU<TC>::col(qi, 0);
+      const int rofs = (e * JA + kk) * 64 + srht_ucol<TC>(qi, 0);
       typedef float f4 __attribute__((ext_vector_type(4)));
       typedef double d2 __attribute__((ext_vector_type(2)));
       lsq_f4v acc[4];
@@ -929,7 +964,8 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
         acc[c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
         acc64[c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
       }
-      auto compute = [&](const TC* Lb, uint32_t ja_stage) {
+      // one stage from LDS buffer Lb; fold: the FP32 chains end here
+      auto compute = [&](const TC* Lb, uint32_t ja_stage, bool fold) {
         if (!has) return;
         const uint32_t sb = lowpar ^ ((__popc(ka & ja_stage) & 1) ? ALL : 0u);
         const TC* r = Lb + rofs;
@@ -946,11 +982,13 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
             acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.z, acc[2], 0, 0, 0);
             acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.w, acc[3], 0, 0, 0);
           }
+          if (fold) {
 #pragma unroll
-          for (int c = 0; c < 4; ++c) {
+            for (int c = 0; c < 4; ++c) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) acc64[c][v] += (double)acc[c][v];
-            acc[c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+              for (int v = 0; v < 4; ++v) acc64[c][v] += (double)acc[c][v];
+              acc[c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+            }
           }
         } else {
           d2 un0 = *(const d2*)r, un1 = *(const d2*)(r + 32);
@@ -972,7 +1010,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
       // two stages in flight in registers, one being consumed from LDS.  nst is even; loads are issued
       // without conditions (stages past the last reload the last one, never used) so that the compiler's
       // wait counts stay exact and two stages stay in flight.
-      vu_t ra[UPT][4], rb[UPT][4];
+      vu_t ra[UPT][F], rb[UPT][F];
       gload(0, ra);
       gload(1, rb);
       lds_barrier();  // the previous sweep's last stage has been consumed
@@ -980,11 +1018,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
       lds_barrier();
       gload(min(2, nst - 1), ra);
       for (int st = 0; st < nst; st += 2) {
-        compute(L, ja0 + JA * st);
+        compute(L, ja0 + JA * st, FOLD == 1);
         lstore(1, rb);
         lds_barrier();
         gload(min(st + 3, nst - 1), rb);
-        compute(L + STAGE, ja0 + JA * (st + 1));
+        compute(L + STAGE, ja0 + JA * (st + 1), true);
         lstore(0, ra);
         lds_barrier();
         gload(min(st + 4, nst - 1), ra);
@@ -998,7 +1036,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
           double* o = out + (int64_t)order[qq] * d;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const int64_t col = c0 + SrhtU<TC>::col(qi, c);
+            const int64_t col = c0 + srht_ucol<TC>(qi, c);
             if (col < d) o[col] = acc64[c][v];
           }
         }
@@ -1073,12 +1111,19 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       const int64_t ncb = (dT + 63) / 64;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
-      // default: sixteen wavefronts, one sweep over T for up to 16 tiles; 2: eight wavefronts
+      // sixteen wavefronts, one sweep over T for up to 16 tiles.  The 8-point fold from 80 rows per bucket
+      // on average (measured at n = 2^22, d = 1024: 1-2 % slower at 64 rows, 1-8 % faster from 96 to 256,
+      // where its tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen,
+      // 4-point; 4 sixteen, 8-point.
+      const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 80 * p.N1);
       if (g_srht_passb == 2)
-        hipLaunchKernelGGL((k_srht_passB_u<float, 8>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
+        hipLaunchKernelGGL((k_srht_passB_u<float, 8, 2>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
+                           rows, slot, order, bstart, p.m, partial);
+      else if (f8)
+        hipLaunchKernelGGL((k_srht_passB_u<float, 16, 3>), gl, dim3(1024), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
       else
-        hipLaunchKernelGGL((k_srht_passB_u<float, 16>), gl, dim3(1024), 0, st, (const float*)T, p.N2, d, dT, L1,
+        hipLaunchKernelGGL((k_srht_passB_u<float, 16, 2>), gl, dim3(1024), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
     } else if (big && p.N2 >= 512)
       hipLaunchKernelGGL(k_srht_passB_f32w, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
@@ -1093,11 +1138,18 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     const int64_t ncb = (dT + 63) / 64;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
+    // as for FP32 T; the FP64 8-point form stages with half the wavefronts (512 units of eight rows), which
+    // pays only where its MFMA saving is largest (measured at n = 2^22, d = 1024: 0-4 % faster from 128 to
+    // 192 rows per bucket, 4 % slower at 96 and 256)
+    const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 128 * p.N1 && p.m <= 192 * p.N1);
     if (g_srht_passb == 2)
-      hipLaunchKernelGGL((k_srht_passB_u<double, 8>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
+      hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
+    else if (f8)
+      hipLaunchKernelGGL((k_srht_passB_u<double, 16, 3>), gl, dim3(1024), 0, st, (const double*)T, p.N2, d, dT, L1,
+                         rows, slot, order, bstart, p.m, partial);
     else
-      hipLaunchKernelGGL((k_srht_passB_u<double, 16>), gl, dim3(1024), 0, st, (const double*)T, p.N2, d, dT, L1,
+      hipLaunchKernelGGL((k_srht_passB_u<double, 16, 2>), gl, dim3(1024), 0, st, (const double*)T, p.N2, d, dT, L1,
                          rows, slot, order, bstart, p.m, partial);
   } else if (big) {
     constexpr int WGC = SRHT_WGC / 2;
