@@ -258,41 +258,61 @@ __global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int
 
 // --------------------------------------------------------------------------------------------------
 // Q = X W with W upper triangular (dp x dp, identity on the padding): Q[r][j] = sum_{k <= j} X[r][k] W[k][j].
-// Tile 64 rows x 64 columns per workgroup, four wavefronts of 32 x 32, X and W staged through LDS.
+// Tile 64 rows x 64 columns per workgroup, four wavefronts of 32 x 32; stages of 32 values of k of X and W
+// pass through LDS, the next stage's loads in flight during the MFMAs (as in the Gram kernel).  Column
+// blocks are taken from the right (the most stages) first.  VEC: d and ldx even and X 16-byte aligned.
 // --------------------------------------------------------------------------------------------------
+template <bool VEC>
 __global__ __launch_bounds__(256) void k_xw(const double* __restrict__ X, int64_t m, int64_t d, int64_t ldx,
                                             const double* __restrict__ W, int64_t dp, double* __restrict__ Q) {
-  __shared__ double Xs[CQ_T][CQ_KS + 1];
-  __shared__ double Ws[CQ_KS][CQ_LP];
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  __shared__ double Xs[CQ_T][GR_KS + 1];
+  __shared__ double Ws[GR_KS][CQ_LP];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wi = wv >> 1, wj = wv & 1;
-  const int64_t r0 = (int64_t)blockIdx.x * CQ_T, j0 = (int64_t)blockIdx.y * CQ_T;
+  const int64_t r0 = (int64_t)blockIdx.x * CQ_T, j0 = (int64_t)(gridDim.y - 1 - blockIdx.y) * CQ_T;
+  // loaders: X row xr, columns xc .. xc + 7 of the stage; W row wr, columns wc .. wc + 7 of the tile
+  const int xr = tid >> 2, xc = (tid & 3) * 8, wr = tid >> 3, wc = (tid & 7) * 8;
+  const int64_t rx = r0 + xr;
+  const double* xrow = X + (rx < m ? rx : m - 1) * ldx;  // rows past m are multiplied by 0 below
+  const double xok = rx < m ? 1.0 : 0.0;
+  d2 xv[4], wvv[4];
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t c = k0 + xc + 2 * e;
+      if constexpr (VEC)
+        xv[e] = *(const d2*)(xrow + (c < d ? c : 0));
+      else
+        xv[e] = (d2){xrow[c < d ? c : 0], xrow[c + 1 < d ? c + 1 : 0]};
+    }
+    const int64_t k = k0 + wr < dp ? k0 + wr : dp - 1;  // past the last stage: never stored
+#pragma unroll
+    for (int e = 0; e < 4; ++e) wvv[e] = *(const d2*)(W + k * dp + j0 + wc + 2 * e);
+  };
   lsq_c_d4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = (lsq_c_d4){0.0, 0.0, 0.0, 0.0};
   const int64_t kend = j0 + CQ_T;  // W[k][j] = 0 for k > j
-  for (int64_t k0 = 0; k0 < kend; k0 += CQ_KS) {
-    // X tile: 64 rows x 16 columns (thread: row tid / 4, columns 4 (tid % 4) ..)
-    {
-      const int rr = tid >> 2, cc = (tid & 3) * 4;
-      const int64_t r = r0 + rr;
+  load(0);
+  for (int64_t k0 = 0; k0 < kend; k0 += GR_KS) {
+    __syncthreads();  // the previous stage has been consumed
+    // columns past d and rows past m as zero (multiplied, so that no load is moved into a branch)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t c = k0 + cc + e;
-        Xs[rr][cc + e] = (r < m && c < d) ? X[r * ldx + c] : 0.0;
-      }
-    }
-    // W tile: 16 rows x 64 columns
-    {
-      const int rr = tid >> 4, cc = (tid & 15) * 4;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) Ws[rr][cc + e] = W[(k0 + rr) * dp + j0 + cc + e];
+    for (int e = 0; e < 4; ++e) {
+      const int64_t c = k0 + xc + 2 * e;
+      Xs[xr][xc + 2 * e] = xv[e].x * (c < d ? xok : 0.0);
+      Xs[xr][xc + 2 * e + 1] = xv[e].y * (c + 1 < d ? xok : 0.0);
+      Ws[wr][wc + 2 * e] = wvv[e].x;
+      Ws[wr][wc + 2 * e + 1] = wvv[e].y;
     }
     __syncthreads();
+    load(k0 + GR_KS);
+    asm volatile("" ::: "memory");  // keeps the loads here, ahead of the MFMAs
 #pragma unroll
-    for (int kk = 0; kk < CQ_KS; kk += 4) {
+    for (int kk = 0; kk < GR_KS; kk += 4) {
       double av[2], bv[2];
 #pragma unroll
       for (int a = 0; a < 2; ++a) av[a] = Xs[32 * wi + 16 * a + (lane & 15)][kk + (lane >> 4)];
@@ -303,7 +323,6 @@ __global__ __launch_bounds__(256) void k_xw(const double* __restrict__ X, int64_
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = mfma_d(av[a], bv[b], acc[a][b]);
     }
-    __syncthreads();
   }
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -315,6 +334,14 @@ __global__ __launch_bounds__(256) void k_xw(const double* __restrict__ X, int64_
         const int64_t j = j0 + 32 * wj + 16 * b + (lane & 15);
         if (r < m) Q[r * dp + j] = acc[a][b][v];
       }
+}
+
+static void launch_xw(hipStream_t st, dim3 grid, const double* X, int64_t m, int64_t d, int64_t ldx,
+                      const double* W, int64_t dp, double* Q) {
+  if (d % 2 == 0 && ldx % 2 == 0 && (uintptr_t)X % 16 == 0)
+    hipLaunchKernelGGL(k_xw<true>, grid, dim3(256), 0, st, X, m, d, ldx, W, dp, Q);
+  else
+    hipLaunchKernelGGL(k_xw<false>, grid, dim3(256), 0, st, X, m, d, ldx, W, dp, Q);
 }
 
 // C = A B for upper triangular A, B (dp x dp): C[i][j] = sum_{i <= k <= j} A[i][k] B[k][j], upper 16 x 16
@@ -459,7 +486,7 @@ int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_
   if (hflags[0] || hflags[1]) return 1;  // caller chooses the robust path
   // Q1 = X R1^{-1}; pass 2 on Q1; R = R2 R1
   tri_inverse_padded(st, Ra, dp, Wt, trinv_scratch);
-  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, SA, m, d, lds, Wt, dp, Q);
+  launch_xw(st, gx, SA, m, d, lds, Wt, dp, Q);
   cq_pass(st, Q, m, d, dp, dp, part, G, nullptr, Rb, Dinv, flags);
   hipLaunchKernelGGL(k_trtr, dim3((unsigned)((dp / 16) * (dp / 16) / 4 + 1)), dim3(256), 0, st, Rb, Ra, dp, Rc);
   hipLaunchKernelGGL(k_chol_extract, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rc, dp, d, R);
@@ -540,12 +567,12 @@ int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int6
   cholesky(st, G, dp, Ra, Dinv, flags);
   // Q1 = X R1^{-1}, R2 = chol(Q1^T Q1), R21 = R2 R1
   tri_inverse_padded(st, Ra, dp, Wt, trinv_scratch);
-  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, SA, m, d, lds, Wt, dp, Q);
+  launch_xw(st, gx, SA, m, d, lds, Wt, dp, Q);
   cq_pass(st, Q, m, d, dp, dp, part, G, nullptr, Rb, Dinv, flags);
   hipLaunchKernelGGL(k_trtr, dim3(gt), dim3(256), 0, st, Rb, Ra, dp, Rc);
   // Q2 = Q1 R2^{-1}, R3 = chol(Q2^T Q2), R = R3 R21
   tri_inverse_padded(st, Rb, dp, Wt, trinv_scratch);
-  hipLaunchKernelGGL(k_xw, gx, dim3(256), 0, st, Q, m, d, dp, Wt, dp, Q2);
+  launch_xw(st, gx, Q, m, d, dp, Wt, dp, Q2);
   cq_pass(st, Q2, m, d, dp, dp, part, G, nullptr, Ra, Dinv, flags);
   hipLaunchKernelGGL(k_trtr, dim3(gt), dim3(256), 0, st, Ra, Rc, dp, Rb);
   hipLaunchKernelGGL(k_chol_extract, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Rb, dp, d, R);
