@@ -166,6 +166,18 @@ __global__ __launch_bounds__(1024) void k_gram_shift(const double* __restrict__ 
 // and row i of R_kk, which stays in LDS).  A pivot that is not positive sets *flag and is replaced by 1
 // so that the factorization completes.
 
+// 1 / sqrt(p) for p > 0: the hardware estimate and two Newton steps y <- y + (y / 2)(1 - p y^2), each of
+// which squares the relative error, to within about an ulp.
+__device__ __forceinline__ double rsqrt_newton(double p) {
+  double y = __builtin_amdgcn_rsq(p);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-p * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, int64_t dp, int kb,
                                                   double* __restrict__ R, double* __restrict__ Dinv,
                                                   int* __restrict__ flag) {
@@ -180,13 +192,16 @@ __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, 
   for (int k = 0; k < CQ_T; ++k) {
     const double piv = readlane_d(a[k], k);
     bad = bad || !(piv > 0.0);
-    const double rkk = piv > 0.0 ? sqrt(piv) : 1.0;
-    const double inv = 1.0 / rkk;
+    // r_kk = sqrt(piv) and its reciprocal from one refined reciprocal square root (no division on the
+    // step's serial chain)
+    const double inv = piv > 0.0 ? rsqrt_newton(piv) : 1.0;
+    const double rkk = piv > 0.0 ? piv * inv : 1.0;
     a[k] = j == k ? rkk : a[k] * inv;
     Rs[k][j] = a[k];  // row k of R_kk in entries j >= k
     __syncthreads();
 #pragma unroll
     for (int i = k + 1; i < CQ_T; ++i) a[i] = fma(-Rs[k][i], a[k], a[i]);
+    __builtin_amdgcn_sched_barrier(0);  // one step at a time: hoisting later steps' reads only adds registers
   }
   if (j == 0 && bad) *flag = 1;
 #pragma unroll
@@ -199,6 +214,7 @@ __global__ __launch_bounds__(64) void k_chol_diag(const double* __restrict__ G, 
 #pragma unroll
     for (int k = i + 1; k < CQ_T; ++k) s = fma(Rs[i][k], a[k], s);
     a[i] = i > j ? 0.0 : ((i == j ? 1.0 : -s) / Rs[i][i]);
+    __builtin_amdgcn_sched_barrier(0);
   }
 #pragma unroll
   for (int i = 0; i < CQ_T; ++i) Dinv[i * CQ_T + j] = a[i];
