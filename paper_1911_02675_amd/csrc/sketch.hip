@@ -6,11 +6,12 @@
 //     (H E A)[k] = sum_{j_hi} (-1)^popcount(k_hi & j_hi) T[j_hi, k_lo],
 //     T[j_hi, k_lo] = sum_{j_lo} H_{N1}[k_lo, j_lo] e_j A[j].
 // Pass A computes T block by block (a column slice of N1 = 256 consecutive rows, or N rows when
-// N < 256), keeping only the k_lo that some selected row needs.  T is stored k_lo-major,
-// T[(slot(k_lo) N2 + j_hi) dT + col] with the row stride dT = d rounded up to 16 bytes, so that pass B
-// streams each bucket's N2 x dT block contiguously while it evaluates the high-bit sum for the
-// bucket's selected rows on the FP64 matrix cores.  HBM traffic is about |A| + 2 f |T| with f the
-// fraction of k_lo values used; pass B does m N2 d multiply-adds.
+// N < 256), keeping only the k_lo that some selected row needs.  T is stored k_lo-major: row-major,
+// T[(slot(k_lo) N2 + j_hi) dT + col] with dT = d rounded up to 16 bytes, or, for the LDS-staged pass B,
+// in stripes of 64 columns, T[((slot(k_lo) ncbs + col / 64) N2 + j_hi) 64 + col mod 64], so that each
+// pass B workgroup streams its bucket's N2 x 64 stripe contiguously while it evaluates the high-bit sum
+// for the bucket's selected rows on the matrix cores.  HBM traffic is about |A| + 2 f |T| with f the
+// fraction of k_lo values used; pass B does m N2 d / F multiply-adds after an F-point fold.
 //
 // SJLT: the hashed scatter is done as a stable counting sort of the (target, row) pairs followed by
 // a segmented reduction per target row, in increasing row order: no atomics touch S A, and the
@@ -93,8 +94,18 @@ static int64_t srht_dT(int64_t d, int compute_f32) {
   return (d + v - 1) / v * v;
 }
 
+// T is sized for either layout: row-major rows of dT, or 64-column stripes (dT rounded up to 64).
 size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32) {
-  return (size_t)N2 * (size_t)nneeded * (size_t)srht_dT(d, compute_f32) * (compute_f32 ? 4 : 8);
+  const int64_t w = (srht_dT(d, compute_f32) + 63) / 64 * 64;
+  return (size_t)N2 * (size_t)nneeded * (size_t)w * (compute_f32 ? 4 : 8);
+}
+
+// Element (slot sl, j_hi, column col) of T.  ncbs = 0: row-major, rows of dT; otherwise each slot's
+// block is ncbs stripes of 64 columns, each stripe N2 rows of 64 contiguous elements, so that a
+// workgroup of the LDS-staged pass B streams its stripe as one contiguous range.
+__device__ __forceinline__ int64_t srht_tpos(int64_t sl, int64_t jh, int64_t col, int64_t N2, int64_t dT,
+                                             int64_t ncbs) {
+  return ncbs ? ((sl * ncbs + (col >> 6)) * N2 + jh) * 64 + (col & 63) : (sl * N2 + jh) * dT + col;
 }
 
 template <typename T, int W>
@@ -148,7 +159,7 @@ template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A, int64_t n, int64_t d,
                                                             int64_t lda, const int8_t* __restrict__ signs,
                                                             const int* __restrict__ slot, int64_t N2,
-                                                            int64_t dT, TC* __restrict__ T) {
+                                                            int64_t dT, int64_t ncbs, TC* __restrict__ T) {
   constexpr int VW = 16 / sizeof(TC);
   typedef typename SVec<TA, VW>::t va;
   typedef typename SVec<TC, VW>::t vc;
@@ -209,7 +220,7 @@ __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A
 #pragma unroll
       for (int j = 0; j < G; ++j) {
         const int sl = slot_s[G * h + j];
-        if (sl >= 0) __builtin_nontemporal_store(z[j], (vc*)(T + ((int64_t)sl * N2 + jhi) * dT + col));
+        if (sl >= 0) __builtin_nontemporal_store(z[j], (vc*)(T + srht_tpos(sl, jhi, col, N2, dT, ncbs)));
       }
     }
     __syncthreads();
@@ -245,7 +256,7 @@ template <typename TA, typename TC>
 __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, int64_t n, int64_t d,
                                                      int64_t lda, const int8_t* __restrict__ signs,
                                                      const int* __restrict__ slot, int64_t N2,
-                                                     int64_t dT, TC* __restrict__ T) {
+                                                     int64_t dT, int64_t ncbs, TC* __restrict__ T) {
   constexpr int DC = 128 / sizeof(TC);   // columns per slice
   constexpr int G = 256 / DC;            // row groups (low row bits)
   constexpr int V = SRHT_N1 / G;         // rows per thread
@@ -285,7 +296,7 @@ __global__ __launch_bounds__(256) void k_srht_passA2(const TA* __restrict__ A, i
       for (int j = 0; j < G; ++j) {
         const int r = G * (h + G * k) + j;
         const int sl = slot_s[r];
-        if (sl >= 0 && col < d) __builtin_nontemporal_store(z[j], T + ((int64_t)sl * N2 + jhi) * dT + col);
+        if (sl >= 0 && col < d) __builtin_nontemporal_store(z[j], T + srht_tpos(sl, jhi, col, N2, dT, ncbs));
       }
     }
     __syncthreads();
@@ -897,7 +908,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   const int64_t c0 = (int64_t)blockIdx.x * 64;
   double* out = partial + (int64_t)js * m * d;
   // staging map: unit tid + 64 NW i -> j_a group uq (rows F uq + b of the stage), columns uc .. uc + VU - 1
-  // (columns past dT read the row's last VU columns instead: those LDS words are never output)
+  // of the workgroup's 64-column stripe of T (columns past d hold no data and are never output)
   const bool stager = !PART || tid < UNITS;  // uniform per wavefront
   const TC* gsrc[UPT];
   int lofs[UPT];
@@ -905,7 +916,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   for (int i = 0; i < UPT; ++i) {
     const int u = stager ? tid + 64 * NW * i : 0;
     const int uq = u / (64 / VU), uc = (u % (64 / VU)) * VU;
-    gsrc[i] = T + ((int64_t)sl * N2 + jh0 + F * uq) * dT + (c0 + uc < dT ? c0 + uc : dT - VU);
+    gsrc[i] = T + (((int64_t)sl * gridDim.x + blockIdx.x) * N2 + jh0 + F * uq) * 64 + uc;
     lofs[i] = uq * 64 + uc;
   }
   auto gload = [&](int st, vu_t(&v)[UPT][F]) {
@@ -914,7 +925,7 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
     for (int i = 0; i < UPT; ++i)
 #pragma unroll
       for (int b = 0; b < F; ++b)
-        v[i][b] = __builtin_nontemporal_load((const vu_t*)(gsrc[i] + ((int64_t)(F * JA) * st + b) * dT));
+        v[i][b] = __builtin_nontemporal_load((const vu_t*)(gsrc[i] + ((int64_t)(F * JA) * st + b) * 64));
   };
   auto lstore = [&](int buf, const vu_t(&v)[UPT][F]) {
     if (!stager) return;
@@ -1076,6 +1087,11 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
   const int64_t dT = srht_dT(d, sizeof(TC) == 4);
   int L1 = 0;
   while ((1ll << L1) < p.N1) ++L1;
+  // buckets of more than about 24 selected rows on average: 64-row chunks (one sweep of T per bucket)
+  const bool big = p.m > 24 * p.N1;
+  // the LDS-staged pass B reads T in 64-column stripes, written so by pass A
+  const bool lds_b = p.N1 == SRHT_N1 && big && p.N2 >= 512 && g_srht_passb != 1;
+  const int64_t ncbs = lds_b ? (dT + 63) / 64 : 0;
   if (p.N1 == SRHT_N1) {
     const bool vec = d % VW == 0 && lda % VW == 0 && ((uintptr_t)A % (VW * sizeof(TA))) == 0;
     if (vec) {
@@ -1086,14 +1102,14 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       int64_t sg = (target + p.N2 - 1) / p.N2;
       sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
       hipLaunchKernelGGL((k_srht_passA_vec<TA, TC>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st, A,
-                         n, d, lda, signs, slot, p.N2, dT, T);
+                         n, d, lda, signs, slot, p.N2, dT, ncbs, T);
     } else {
       constexpr int64_t DC = 128 / sizeof(TC);
       const int64_t nslices = (d + DC - 1) / DC;
       int64_t sg = (4096 + p.N2 - 1) / p.N2;
       sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
       hipLaunchKernelGGL((k_srht_passA2<TA, TC>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st, A, n,
-                         d, lda, signs, slot, p.N2, dT, T);
+                         d, lda, signs, slot, p.N2, dT, ncbs, T);
     }
   } else {
     constexpr int64_t DC = 128 / sizeof(TC);
@@ -1102,13 +1118,11 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                        n, d, lda, (int)p.N1, signs, slot, p.N2, dT, T);
   }
   int JS = srht_js(p.N2);
-  // buckets of more than about 24 selected rows on average: 64-row chunks (one sweep of T per bucket)
-  const bool big = p.m > 24 * p.N1;
   if constexpr (sizeof(TC) == 4) {
     const int64_t wgc = big ? 128 : 256;  // 64 VW columns per workgroup
     dim3 gb((unsigned)p.N1, (unsigned)JS, (unsigned)((dT + wgc - 1) / wgc));
-    if (big && p.N2 >= 512 && g_srht_passb != 1) {
-      const int64_t ncb = (dT + 63) / 64;
+    if (lds_b) {
+      const int64_t ncb = ncbs;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
       // sixteen wavefronts, one sweep over T for up to 16 tiles.  The 8-point fold from 80 rows per bucket
@@ -1134,8 +1148,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     else
       hipLaunchKernelGGL(k_srht_passB_f32<2>, gb, dim3(256), 0, st, (const float*)T, p.N2, d, dT, L1, rows, slot,
                          order, bstart, p.m, partial);
-  } else if (big && p.N2 >= 512 && g_srht_passb != 1) {
-    const int64_t ncb = (dT + 63) / 64;
+  } else if (lds_b) {
+    const int64_t ncb = ncbs;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
     // as for FP32 T; the FP64 8-point form stages with half the wavefronts (512 units of eight rows), which
