@@ -1125,11 +1125,11 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       const int64_t ncb = ncbs;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
-      // sixteen wavefronts, one sweep over T for up to 16 tiles.  The 8-point fold from 80 rows per bucket
-      // on average (measured at n = 2^22, d = 1024: 1-2 % slower at 64 rows, 1-8 % faster from 96 to 256,
-      // where its tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen,
-      // 4-point; 4 sixteen, 8-point.
-      const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 80 * p.N1);
+      // sixteen wavefronts, one sweep over T for up to 16 tiles.  The 8-point fold from 64 rows per bucket
+      // on average (measured at n = 2^22, d = 1024: sketches 3-8 % faster from 64 to 256 rows, where its
+      // tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen, 4-point;
+      // 4 sixteen, 8-point.
+      const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 64 * p.N1);
       if (g_srht_passb == 2)
         hipLaunchKernelGGL((k_srht_passB_u<float, 8, 2>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
@@ -1153,8 +1153,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
     // as for FP32 T; the FP64 8-point form stages with half the wavefronts (512 units of eight rows), which
-    // pays only where its MFMA saving is largest (measured at n = 2^22, d = 1024: 0-4 % faster from 128 to
-    // 192 rows per bucket, 4 % slower at 96 and 256)
+    // pays only where its MFMA saving is largest (measured at n = 2^22, d = 1024: 2-6 % faster from 128 to
+    // 192 rows per bucket, 3 % slower at 96 and 256)
     const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 128 * p.N1 && p.m <= 192 * p.N1);
     if (g_srht_passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
