@@ -166,8 +166,11 @@ static lsq_status check_sketch(const lsq_problem* p, const lsq_sketch_desc* s, b
 // ------------------------------------------------------------------------------------------------
 // sketch
 // ------------------------------------------------------------------------------------------------
+// grad (optional): for an SRHT sketch whose first pass takes the vector form, *grad points at the N2
+// partial rows of A^T y left by that pass and *grad_rows = N2; otherwise *grad = nullptr.
 static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s, uint64_t t,
-                            double* SA, int64_t ldsa) {
+                            double* SA, int64_t ldsa, double** grad = nullptr, int* grad_rows = nullptr) {
+  if (grad) *grad = nullptr;
   const hipStream_t st = c->st;
   const int a_f32 = p->a_dtype == LSQ_F32;
   if (s->kind == LSQ_SRHT) {
@@ -202,8 +205,13 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     CHK(ws(c, "srht_tbuf", srht_tbuf_bytes(plan.N2, plan.nneeded, p->d, cf32), &tbuf));
     double* partial;
     CHK(wsT(c, "srht_partial", srht_partial_bytes(plan.N2, s->m, p->d) / sizeof(double), &partial));
-    srht_apply(st, p->A, a_f32, p->n, p->d, p->lda, cf32, plan, signs, rows, slot, order, bstart, tbuf,
-               partial, SA, ldsa);
+    double* gpart = nullptr;
+    if (grad) CHK(wsT(c, "srht_grad", (size_t)plan.N2 * (p->d + 1), &gpart));
+    if (srht_apply(st, p->A, a_f32, p->n, p->d, p->lda, cf32, plan, signs, rows, slot, order, bstart, tbuf,
+                   partial, SA, ldsa, p->y, gpart)) {
+      *grad = gpart;
+      *grad_rows = (int)plan.N2;
+    }
   } else if (s->kind == LSQ_SJLT) {
     SjltScratch sc;
     const int64_t nblk = sjlt_nblk(p->n);
@@ -619,8 +627,24 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   CHK(solve_bufs(c, p->n, d, &b));
   const double a_bytes = (double)p->n * d * (p->a_dtype == LSQ_F32 ? 4.0 : 8.0);
 
+  // From x_0 = 0 the first gradient is A^T y, which the SRHT's first pass forms while it streams A
+  // (do_sketch), saving a pass.
+  if (c->hx_len < (size_t)d) {
+    if (c->hx) HIPCHK(hipHostFree(c->hx));
+    c->hx = nullptr;
+    c->hx_len = 0;
+    HIPCHK(hipHostMalloc(&c->hx, sizeof(double) * d, hipHostMallocDefault));
+    c->hx_len = d;
+  }
+  HIPCHK(hipMemcpyAsync(c->hx, x, sizeof(double) * d, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  bool x0_zero = true;
+  for (int64_t i = 0; i < d && x0_zero; ++i) x0_zero = c->hx[i] == 0.0;
+  double* grad = nullptr;
+  int grad_rows = 0;
+
   HIPCHK(hipEventRecord(c->ev[0], st));
-  CHK(do_sketch(c, p, s, s->t, SA, d));
+  CHK(do_sketch(c, p, s, s->t, SA, d, x0_zero || o->x_ref ? &grad : nullptr, &grad_rows));
   HIPCHK(hipEventRecord(c->ev[1], st));
   CHK(do_factor(c, SA, m, d, d, R, W, WT));
   HIPCHK(hipEventRecord(c->ev[2], st));
@@ -632,19 +656,27 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   const int trace_len = o->max_iter + 1;
 
   if (o->x_ref) {
-    // x_ref^T b with b = A^T y: one residual pass at v = 0
-    vec_zero(st, b.dx, d);
-    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, b.dx, p->y, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    // x_ref^T b with b = A^T y: one residual pass at v = 0 (or the first pass's partials)
+    if (grad) {
+      reduce_partials(st, grad, b.part2, grad_rows, d, b.red, nullptr);
+    } else {
+      vec_zero(st, b.dx, d);
+      const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, b.dx, p->y, b.part, b.nwg, nullptr);
+      reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+      passes += 1;
+    }
     dot_to_state(st, d, o->x_ref, b.red, c->ds);
-    passes += 1;
   }
 
   if (!o->mixed) {
     // r_0 = A^T (y - A x_0)
-    const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
-    reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
-    passes += 1;
+    if (grad && x0_zero) {
+      reduce_partials(st, grad, b.part2, grad_rows, d, b.r, nullptr);
+    } else {
+      const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
+      reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
+      passes += 1;
+    }
     int it = 0;
     CHK(inner_pcg(c, p, 0, W, WT, b, x, tol, o->max_iter, check_every, o->x_ref, err_trace, trace_len,
                   &it));
@@ -658,19 +690,9 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     double* rpart;
     CHK(wsT(c, "resid_dd", resid_dd_part_len(d), &rpart));
     if (d > 1024) return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
-    // From x_0 = 0 the first residual is A^T y, with no cancellation: one plain pass (FP64 arithmetic)
-    // gives it to working accuracy.  Any other start takes the double-double residual from the outset.
-    if (c->hx_len < (size_t)d) {
-      if (c->hx) HIPCHK(hipHostFree(c->hx));
-      c->hx = nullptr;
-      c->hx_len = 0;
-      HIPCHK(hipHostMalloc(&c->hx, sizeof(double) * d, hipHostMallocDefault));
-      c->hx_len = d;
-    }
-    HIPCHK(hipMemcpyAsync(c->hx, x, sizeof(double) * d, hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    bool x0_zero = true;
-    for (int64_t i = 0; i < d && x0_zero; ++i) x0_zero = c->hx[i] == 0.0;
+    // From x_0 = 0 the first residual is A^T y, with no cancellation: FP64 products and sums (the SRHT's
+    // first pass, or one plain pass) give it to working accuracy.  Any other start takes the
+    // double-double residual from the outset.
     double est_carried = -1.0;
     for (int k = 0; k < o->max_refine; ++k) {
       // After a correction solved from an accurate residual (k >= 2: the first check, k = 1, measures
@@ -681,14 +703,18 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
         est = est_carried;
         break;
       }
-      if (k == 0 && x0_zero) {
+      if (k == 0 && x0_zero && grad) {
+        reduce_partials(st, grad, b.part2, grad_rows, d, b.r, nullptr);
+      } else if (k == 0 && x0_zero) {
         const int ng_ = fused_pass(st, p->A, a_f32, 0, p->n, d, p->lda, 1, x, p->y, b.part, b.nwg, nullptr);
         reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
+        passes += 1;
       } else if (!resid_dd(st, p->A, a_f32, p->n, d, p->lda, x, p->y, rpart, b.r, nullptr)) {
         // outer residual in double-double (rounded once), so that it stays accurate near the solution
         return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
+      } else {
+        passes += 1;
       }
-      passes += 1;
       int ndot;
       precond_apply_any(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);
       pcg_init(st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, 1.0, x, b.r, nullptr, nullptr);

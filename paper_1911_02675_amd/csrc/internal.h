@@ -45,10 +45,12 @@ size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32);
 void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1, int* slot,
                       int* order, int* bstart, int* nneeded_dev);
 size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d);
-void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
+// With gpart (N2 rows of d + 1 doubles) and y, pass A also leaves A^T y in the fused pass's partial layout
+// (column d: sum of y^2) when it takes its vector form; returns whether it did.
+bool srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
                 int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
                 const int* slot, const int* order, const int* bstart, void* tbuf, double* partial,
-                double* SA, int64_t ldsa);
+                double* SA, int64_t ldsa, const double* y = nullptr, double* gpart = nullptr);
 
 struct SjltScratch {
   int32_t* targets;  // n*s

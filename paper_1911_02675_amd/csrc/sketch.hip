@@ -155,11 +155,19 @@ __device__ __forceinline__ void fwht_regs(T (&x)[V]) {
 // n - 1 and are multiplied by a zero sign.  Grid (N2, slice groups): a workgroup walks the column
 // slices blockIdx.y, blockIdx.y + gridDim.y, ... of its block, loading the next slice while
 // transforming the current one.
-template <typename TA, typename TC>
+//   GRAD: the workgroup also forms its block's share of A^T y (the first gradient of the least-squares
+// solve from x = 0, taken here while the rows are in registers instead of in a separate pass over A):
+// row jhi of gpart (width d + 1) gets sum_r y_r A[r][col] over the block's 256 rows for every column of
+// its slices, and the slice group 0 workgroup adds sum_r y_r^2 in column d, in the layout of the fused
+// pass's partials.  FP64 products and sums: per thread over its 16 rows, then across the 4 row groups of
+// a wavefront, then across the 4 wavefronts, in that order.
+template <typename TA, typename TC, bool GRAD>
 __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A, int64_t n, int64_t d,
                                                             int64_t lda, const int8_t* __restrict__ signs,
                                                             const int* __restrict__ slot, int64_t N2,
-                                                            int64_t dT, int64_t ncbs, TC* __restrict__ T) {
+                                                            int64_t dT, int64_t ncbs, TC* __restrict__ T,
+                                                            const double* __restrict__ y,
+                                                            double* __restrict__ gpart) {
   constexpr int VW = 16 / sizeof(TC);
   typedef typename SVec<TA, VW>::t va;
   typedef typename SVec<TC, VW>::t vc;
@@ -172,6 +180,9 @@ __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A
   __shared__ vc tile[SRHT_N1 * RS];
   __shared__ int slot_s[SRHT_N1];
   __shared__ int8_t sg_s[SRHT_N1];
+  __shared__ double ys[GRAD ? SRHT_N1 : 1];        // y of the block's rows (0 past n)
+  __shared__ double gred[GRAD ? 4 * LR * VW : 1];  // per-wavefront column partials of A^T y
+  __shared__ double yred[GRAD ? 4 : 1];
   const int64_t jhi = blockIdx.x;
   const int tid = threadIdx.x;
   const int c = tid % LR, g = tid / LR, h = g;
@@ -180,7 +191,16 @@ __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A
   const bool full = rbase + SRHT_N1 <= n;
   slot_s[tid] = slot[tid];
   sg_s[tid] = rbase + tid < n ? signs[rbase + tid] : (int8_t)0;
+  if constexpr (GRAD) {
+    const double yv = rbase + tid < n ? y[rbase + tid] : 0.0;
+    ys[tid] = yv;
+    const double yy = wave_sum(yv * yv);
+    if ((tid & 63) == 0) yred[tid >> 6] = yy;
+  }
   __syncthreads();
+  if constexpr (GRAD) {
+    if (blockIdx.y == 0 && tid == 0) gpart[jhi * (d + 1) + d] = ((yred[0] + yred[1]) + yred[2]) + yred[3];
+  }
   int sidx = blockIdx.y;
   if (sidx >= nslices) return;
   const int64_t step = (int64_t)G * lda / VW;
@@ -206,12 +226,39 @@ __global__ __launch_bounds__(256) void k_srht_passA_vec(const TA* __restrict__ A
     const int nxt = sidx + gridDim.y;
     vc xn[V];
     if (nxt < nslices) load(nxt, xn);
+    if constexpr (GRAD) {
+      // rows g + 16 i of the block, columns col .. col + VW - 1, before the sign flips
+      double sg[VW];
+#pragma unroll
+      for (int u = 0; u < VW; ++u) sg[u] = 0.0;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        const double yv = ys[g + G * i];
+#pragma unroll
+        for (int u = 0; u < VW; ++u) sg[u] = fma(yv, (double)x[i][u], sg[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < VW; ++u) {
+        sg[u] += __shfl_xor(sg[u], 16, 64);
+        sg[u] += __shfl_xor(sg[u], 32, 64);
+      }
+      if ((tid & 63) < LR)
+#pragma unroll
+        for (int u = 0; u < VW; ++u) gred[((tid >> 6) * LR + c) * VW + u] = sg[u];
+    }
 #pragma unroll
     for (int i = 0; i < V; ++i) x[i] *= (TC)sg_s[g + G * i];
     fwht_regs<V>(x);
 #pragma unroll
     for (int i = 0; i < V; ++i) tile[(g + G * i) * RS + c] = x[i];
     __syncthreads();
+    if constexpr (GRAD) {
+      if (tid < LR && col < d)
+#pragma unroll
+        for (int u = 0; u < VW; ++u)
+          gpart[jhi * (d + 1) + col + u] = ((gred[c * VW + u] + gred[(LR + c) * VW + u]) +
+                                            gred[(2 * LR + c) * VW + u]) + gred[(3 * LR + c) * VW + u];
+    }
     vc z[G];
 #pragma unroll
     for (int j = 0; j < G; ++j) z[j] = tile[(G * h + j) * RS + c];
@@ -1082,8 +1129,10 @@ template <typename TA, typename TC>
 static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int64_t lda,
                          const SrhtPlan& p, const int8_t* signs, const int64_t* rows,
                          const int* slot, const int* order, const int* bstart, TC* T,
-                         double* partial, double* SA, int64_t ldsa) {
+                         double* partial, double* SA, int64_t ldsa, const double* y, double* gpart,
+                         bool* grad_done) {
   constexpr int VW = 16 / sizeof(TC);
+  *grad_done = false;
   const int64_t dT = srht_dT(d, sizeof(TC) == 4);
   int L1 = 0;
   while ((1ll << L1) < p.N1) ++L1;
@@ -1101,8 +1150,15 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       const int64_t target = sizeof(TC) == 4 ? (1 << 17) : (1 << 15);
       int64_t sg = (target + p.N2 - 1) / p.N2;
       sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
-      hipLaunchKernelGGL((k_srht_passA_vec<TA, TC>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st, A,
-                         n, d, lda, signs, slot, p.N2, dT, ncbs, T);
+      // (the gradient needs A's values exactly: not with an FP32 transform of FP64 A)
+      if (gpart && sizeof(TC) >= sizeof(TA)) {
+        hipLaunchKernelGGL((k_srht_passA_vec<TA, TC, true>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st,
+                           A, n, d, lda, signs, slot, p.N2, dT, ncbs, T, y, gpart);
+        *grad_done = true;
+      } else {
+        hipLaunchKernelGGL((k_srht_passA_vec<TA, TC, false>), dim3((unsigned)p.N2, (unsigned)sg), dim3(256), 0, st,
+                           A, n, d, lda, signs, slot, p.N2, dT, ncbs, T, nullptr, nullptr);
+      }
     } else {
       constexpr int64_t DC = 128 / sizeof(TC);
       const int64_t nslices = (d + DC - 1) / DC;
@@ -1179,22 +1235,24 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
                      p.m, d, 1.0 / sqrt((double)p.m), SA, ldsa);
 }
 
-void srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
+bool srht_apply(hipStream_t st, const void* A, int a_f32, int64_t n, int64_t d, int64_t lda,
                 int compute_f32, const SrhtPlan& plan, const int8_t* signs, const int64_t* rows,
                 const int* slot, const int* order, const int* bstart, void* tbuf, double* partial,
-                double* SA, int64_t ldsa) {
+                double* SA, int64_t ldsa, const double* y, double* gpart) {
+  bool g = false;
   if (a_f32 && compute_f32)
     srht_apply_t<float, float>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order, bstart,
-                               (float*)tbuf, partial, SA, ldsa);
+                               (float*)tbuf, partial, SA, ldsa, y, gpart, &g);
   else if (a_f32)
     srht_apply_t<float, double>(st, (const float*)A, n, d, lda, plan, signs, rows, slot, order,
-                                bstart, (double*)tbuf, partial, SA, ldsa);
+                                bstart, (double*)tbuf, partial, SA, ldsa, y, gpart, &g);
   else if (compute_f32)
     srht_apply_t<double, float>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
-                                bstart, (float*)tbuf, partial, SA, ldsa);
+                                bstart, (float*)tbuf, partial, SA, ldsa, y, gpart, &g);
   else
     srht_apply_t<double, double>(st, (const double*)A, n, d, lda, plan, signs, rows, slot, order,
-                                 bstart, (double*)tbuf, partial, SA, ldsa);
+                                 bstart, (double*)tbuf, partial, SA, ldsa, y, gpart, &g);
+  return g;
 }
 
 // --------------------------------------------------------------------------------------------------
