@@ -99,8 +99,8 @@ typedef struct {
  *   mixed:      0 = plain form (A as given, FP64 arithmetic);
  *               1 = iterative refinement: FP64 residual A^T (y - A x) with A read in its storage type,
  *                   inner PCG on the correction, x += dx in FP64.  From x = 0 the first residual is
- *                   one plain pass; every later one is taken in double-double arithmetic and rounded
- *                   once.  The check after the first correction is always measured; after a later
+ *                   A^T y in FP64 arithmetic; every later one is taken in double-double arithmetic and
+ *                   rounded once.  The check after the first correction is always measured; after a later
  *                   correction the estimate is the measured one times that correction solve's own
  *                   relative reduction, so the solve ends without a further residual.
  *   max_refine: outer refinement steps (mixed = 1).
@@ -217,7 +217,10 @@ lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, i
  * and the solution on exit.  The stop rule measures the error relative to that of x_0 (for x_0 = 0,
  * relative to ||A x*||): a warm start already near x* asks for a correspondingly smaller error and
  * can end in LSQ_ERR_NOT_CONVERGED at the rounding floor.  err_trace (device, optional) receives max_iter+1 values per inner solve
- * (see lsq_pcg_opts.x_ref); info (host, optional). */
+ * (see lsq_pcg_opts.x_ref); info (host, optional).  From x_0 = 0 with an SRHT sketch whose first pass
+ * streams A in vector form (d and lda multiples of 16 bytes' worth of elements, A aligned, the
+ * transform no narrower than A), that pass also forms the first residual A^T y, so the solve reads A
+ * once less; x_0 is copied to the host once to decide this. */
 lsq_status lsq_pcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc,
                          const lsq_pcg_opts* opts, double* x, double* err_trace, lsq_info* info);
 
