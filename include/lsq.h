@@ -288,7 +288,7 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
  * "srht_passb" (SRHT second pass for buckets of more than 24 selected rows on average:
  * 0 = staged through LDS, sixteen wavefronts of one row tile each, so that up to 16 tiles of a bucket
  * share one pass over its block of the intermediate, folding by the 8-point transform when a bucket
- * averages 64 rows or more (FP32 intermediate) or 128 to 192 rows (FP64) and by the 4-point one
+ * averages 64 rows or more (FP32 intermediate) or 128 rows or more (FP64) and by the 4-point one
  * otherwise, the default; 1 = operands loaded straight into registers (FP32 intermediate; the FP64 one
  * takes its general form); 2 = staged through LDS, eight wavefronts, 4-point fold; 3 = sixteen
  * wavefronts, 4-point fold; 4 = sixteen wavefronts, 8-point fold).

@@ -908,7 +908,7 @@ struct SrhtU<double, 2> {
 };
 template <>
 struct SrhtU<double, 3> {
-  static constexpr int JA = 8;  // 512 staging units: the first eight wavefronts stage, all compute
+  static constexpr int JA = 16;  // 64 KB per stage buffer: one workgroup per CU
   static constexpr int VU = 1;
   typedef double vu_t;
 };
@@ -1208,10 +1208,9 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     const int64_t ncb = ncbs;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
-    // as for FP32 T; the FP64 8-point form stages with half the wavefronts (512 units of eight rows), which
-    // pays only where its MFMA saving is largest (measured at n = 2^22, d = 1024: 2-6 % faster from 128 to
-    // 192 rows per bucket, 3 % slower at 96 and 256)
-    const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 128 * p.N1 && p.m <= 192 * p.N1);
+    // as for FP32 T; the FP64 8-point form's 64 KB stages leave one workgroup per CU (measured at n = 2^22,
+    // d = 1024: sketches 5-9 % faster from 128 to 256 rows per bucket, even at 96)
+    const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 128 * p.N1);
     if (g_srht_passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
