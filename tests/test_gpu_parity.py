@@ -320,6 +320,43 @@ def test_pcg_mixed_fp32_storage(ctx, inner_f32, kappa):
     assert e <= max(1e-10, floor)
 
 
+@pytest.mark.parametrize("mixed", [0, 1])
+def test_pcg_first_gradient_from_pass_a(ctx, mixed):
+    """From x_0 = 0 with the SRHT in its vector form, the first gradient A^T y comes from the sketch's
+    first pass.  A start of 1e-200 e_0 has the same first residual to rounding but takes it from a pass
+    of its own (plain, or double-double in the mixed form), with the same sketch: the iterates after three
+    fixed iterations agree to rounding.  With lda not a multiple of 16 bytes the sketch takes its general
+    form and the solve a plain first pass; it converges to the same solution."""
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    n, d, m = 30001, 128, 512
+    say("first gradient", mixed)
+    P = make_problem(n, d, 1e4, sigma=0.01, seed=77)
+    A, y = P["A"], P["y"]
+    if mixed:
+        A = A.astype(np.float32).astype(np.float64)
+    dt = torch.float32 if mixed else torch.float64
+    Ad = torch.tensor(A, dtype=dt, device="cuda")
+    yd = dev(y)
+    desc = lsq.sketch_desc("srht", m, seed=5, compute="f32" if mixed else "f64")
+    xs = []
+    for x0 in (0.0, 1e-200):
+        x = torch.zeros(d, dtype=torch.float64, device="cuda")
+        x[0] = x0
+        ctx.pcg_solve(Ad, yd, desc, x, tol=1e-10, max_iter=3, stop_rule=1, mixed=mixed, max_refine=1)
+        xs.append(host(x))
+    assert np.linalg.norm(xs[0] - xs[1]) <= 1e-11 * np.linalg.norm(xs[1])
+    wide = torch.zeros((n, d + 1), dtype=dt, device="cuda")
+    wide[:, :d] = Ad
+    xf, fl = _floor(A, y)
+    for Am in (Ad, wide[:, :d]):  # lda = d, d + 1
+        x = torch.zeros(d, dtype=torch.float64, device="cuda")
+        ctx.pcg_solve(Am, yd, desc, x, tol=1e-10, mixed=mixed, max_refine=30)
+        assert a_norm_error(A, host(x), xf) <= max(1e-10, 4 * fl)
+
+
 def test_pcg_planted_exact(ctx):
     """Planted problem (noise orthogonal to range(A)): x* is known exactly."""
     from oracle.solve import a_norm_error
