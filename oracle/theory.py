@@ -33,6 +33,25 @@ def theta1_haar_exact(n, d, m):
     return (n - d - 1) / (m - d - 1)
 
 
+def theta2_haar_exact(n, d, m):
+    """theta_2 = d^{-1} tr E[C_S^{-2}] for a Haar embedding with orthonormal rows, exactly (m > d + 3).
+    With the rows of an n x d standard Gaussian Z split into the first m and the other k = n - m,
+    X = Z_1^T Z_1 ~ W_d(m, I) and Y = Z_2^T Z_2 ~ W_d(k, I) are independent and C_S has the law of
+    (X + Y)^{-1/2} X (X + Y)^{-1/2} (the same matrix-variate beta as in theta1_haar_exact), so
+        tr C_S^{-2} = tr (I + X^{-1} Y)^2 = d + 2 tr(X^{-1} Y) + tr(X^{-1} Y X^{-1} Y).
+    Averaging over Y first (E[Y M Y] = k(k+1) M + k tr(M) I for symmetric M, from the fourth moments of
+    a Gaussian vector) and then over X with the inverse-Wishart moments
+        E[X^{-1}] = I / (m-d-1),   E[X^{-2}] = (m-1) I / D,   E[tr(X^{-1}) X^{-1}] = ((m-d-2) d + 2) I / D,
+    D = (m-d)(m-d-1)(m-d-3), gives
+        theta_2 = 1 + 2k / (m-d-1) + k ((k+1)(m-1) + (m-d-2) d + 2) / D.
+    Section 2's (n - d)(d^2 + m n - 2 d m)/(m - d)^3 is its large-size limit."""
+    if m <= d + 3:
+        raise ValueError("needs m > d + 3")
+    k = n - m
+    D = (m - d) * (m - d - 1) * (m - d - 3)
+    return 1.0 + 2.0 * k / (m - d - 1) + k * ((k + 1) * (m - 1) + (m - d - 2) * d + 2) / D
+
+
 def srht_thetas_scaled(N, d, m):
     """theta's of the SRHT as scaled here (S = m^{-1/2} R H E, so S S^T = (N/m) I): the Haar values
     for an m x N embedding with orthonormal rows, times (m/N) and (m/N)^2."""
