@@ -92,23 +92,34 @@ typedef struct {
 /* PCG options.
  *   tol:        target relative A-norm error ||A (x - x*)|| / ||A x*||.  The stop rule uses
  *               rho_t = r_t^T H_S^{-1} r_t = Delta_t^T C_S^{-1} Delta_t: it stops when
- *               sqrt(rho_t / rho_0) <= tol / 4, which implies the target whenever the eigenvalues of
+ *               4 sqrt(rho_t / rho_0) <= tol, which implies the target whenever the eigenvalues of
  *               C_S = U^T S^T S U span a ratio of at most 16 (the subspace-embedding event of Section 3).
- *   max_iter:   PCG iteration budget (per inner solve in the mixed form).
- *   stop_rule:  0 = the rule above; 1 = exactly max_iter iterations.
- *   mixed:      0 = plain form (A as given, FP64 arithmetic);
- *               1 = iterative refinement: FP64 residual A^T (y - A x) with A read in its storage type,
- *                   inner PCG on the correction, x += dx in FP64.  From x = 0 the first residual is
- *                   A^T y in FP64 arithmetic; every later one is taken in double-double arithmetic and
- *                   rounded once.  The check after the first correction is always measured; after a later
- *                   correction the estimate is the measured one times that correction solve's own
- *                   relative reduction, so the solve ends without a further residual.
- *   max_refine: outer refinement steps (mixed = 1).
+ *               With stop_rule = 0 the result is verified: PCG runs until its recursively updated
+ *               residual meets the rule, then the residual A^T (y - A x) is measured in double-double
+ *               arithmetic (rounded once) and the rule is applied to the measured value.  When the
+ *               measured residual falls short (the recursive one drifts from the true one by about
+ *               u kappa(A) relative to its start, which matters near the FP64 conditioning floor), PCG
+ *               solves for the correction from the measured residual and x += dx (residual
+ *               replacement), up to max_refine correction solves in all; LSQ_ERR_NOT_CONVERGED when the
+ *               budget ends, or when a measured residual is not half the previous one.  After a
+ *               correction solved from a measured residual the new estimate is the measured one times
+ *               that solve's own relative reduction (the rounding in that solve is relative to the
+ *               correction), so the call ends without a further residual once that meets tol (not with
+ *               x_ref).  From x = 0 the first residual is A^T y in FP64 arithmetic (no cancellation).
+ *   max_iter:   PCG iteration budget of each correction solve.
+ *   stop_rule:  0 = the rule above; 1 = exactly max_iter iterations (plain form: one solve, no
+ *               measurement; mixed form: one correction solve after the first residual).
+ *   mixed:      0 = plain form: A as given (FP64 or FP32 storage), FP64 arithmetic; the first correction
+ *                   accumulates into x itself;
+ *               1 = precision form: as above with every correction solved in a separate vector (x += dx
+ *                   in FP64) and, with inner_f32, FP32-arithmetic inner products.
+ *   max_refine: budget of correction solves (both forms; the plain form takes values below 1 as 1).
  *   inner_f32:  mixed = 1 only: 1 = inner matrix-vector products in FP32 arithmetic (p rounded to
  *               FP32); 0 = FP32 storage read into FP64 registers.
  *   x_ref:      optional device pointer to the exact minimiser; when given, err_trace holds the exact
- *               relative A-norm error per iteration (computed as sqrt(-(x_t - x*)^T r_t / x*^T b)),
- *               otherwise the stop-rule estimate 4 sqrt(rho_t / rho_0). */
+ *               relative A-norm error per iteration of the first correction solve (computed as
+ *               sqrt(-(x_t - x*)^T r_t / x*^T b)), otherwise the stop-rule estimate 4 sqrt(rho_t / rho_0),
+ *               and info->est_rel_err is the exact error at the last measured residual. */
 typedef struct {
   double tol;
   int32_t max_iter;
@@ -163,8 +174,8 @@ typedef struct {
 
 /* Per-call report (host).  Times are HIP-event times on the context stream. */
 typedef struct {
-  int32_t iters;       /* PCG iterations (summed over inner solves), IHS or FCG iterations */
-  int32_t refinements; /* outer refinement steps (mixed form)                           */
+  int32_t iters;       /* PCG iterations (summed over correction solves), IHS or FCG iterations */
+  int32_t refinements; /* correction solves (lsq_pcg_solve, stop_rule 0 or mixed)          */
   double est_rel_err;  /* final stop-rule estimate (or exact error when x_ref was given) */
   double t_sketch_ms, t_factor_ms, t_iter_ms, t_total_ms;
   double bytes_streamed; /* algorithmic bytes of A read by the iteration passes           */
@@ -175,6 +186,8 @@ typedef struct {
 } lsq_info;
 
 /* S A (m x d) into SA (device, row-major, leading dimension ldsa >= d).  sa_dtype must be LSQ_F64.
+ * A NaN or an infinity in A propagates into S A (every embedding here mixes each row of A into at
+ * least one row of S A); lsq_factor and the solvers report it as LSQ_ERR_NONFINITE.
  * Section 2.  Errors: INVALID_ARG for m < 1, m > N (SRHT), m > n (Haar), s outside [1, min(m, 32)]
  * (SJLT), a compute other than LSQ_F64 for Haar, lda < d, null pointers; UNSUPPORTED for d > 1024 or,
  * for Haar, m > min(1024, n/4) (the m x m Gram of the draws is factored once on the device, which keeps
@@ -196,9 +209,9 @@ lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_de
  * minimum-norm solution of a rank-deficient problem.  lsq_tune("factor", 3) selects column-pivoted
  * Householder QR: R11 the leading block with |R_kk| > 1e-12 |R_00|, W = P [R11^{-1}; 0] (dense), R returned
  * as R_pivoted P^T; PCG then returns the basic solution on the kept columns (the others exactly zero).
- * R or W may be NULL.  RANK
+ * R or W may be NULL.  NONFINITE when SA holds a NaN or an infinity (checked before factoring).  RANK
  * when some |R_kk| <= 8 d eps max |R_jj|.  UNSUPPORTED for d > 1024 or m > 65536 (m > 8192 with
- * Householder). */
+ * Householder).  The form is this context's option "factor" (lsq_set_option). */
 lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int64_t lds, double* R,
                       double* W);
 
@@ -279,21 +292,29 @@ lsq_status lsq_draw_gaussian(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t m,
 lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, double* avg_ms,
                                  int64_t* launches);
 
-/* Process-wide tuning parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
- * measured table.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64,
- * default 8); "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute
- * unit, else 1..65536); "factor" (0 = CholeskyQR2 with its fallbacks, the default; 1 = Householder QR
- * only; 2 = the SVD form; 3 = column-pivoted QR, see lsq_factor; the batched form keeps its own
- * Householder QR);
- * "srht_passb" (SRHT second pass for buckets of more than 24 selected rows on average:
- * 0 = staged through LDS, sixteen wavefronts of one row tile each, so that up to 16 tiles of a bucket
- * share one pass over its block of the intermediate, folding by the 8-point transform when a bucket
- * averages 64 rows or more (FP32 intermediate) or 128 rows or more (FP64) and by the 4-point one
- * otherwise, the default; 1 = operands loaded straight into registers (FP32 intermediate; the FP64 one
- * takes its general form); 2 = staged through LDS, eight wavefronts, 4-point fold; 3 = sixteen
- * wavefronts, 4-point fold; 4 = sixteen wavefronts, 8-point fold).
- * INVALID_ARG for an unknown key or an out-of-range value. */
+/* Process-wide launch parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
+ * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
+ * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);
+ * "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute unit, else
+ * 1..65536).  INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
+
+/* Numerics options of one context (each context starts with the defaults; calls on other contexts are
+ * unaffected).  Keys:
+ *   "factor" (Section 1.2 names QR of S A or a Cholesky factor of H_S; Section 6 the same; pivoted QR and
+ *     the SVD are the alternatives it cites): 0 = CholeskyQR2 with its fallbacks, the default; 1 =
+ *     Householder QR only; 2 = the SVD form; 3 = column-pivoted QR (see lsq_factor).  The batched form
+ *     keeps its own Householder QR.
+ *   "srht_passb" (Section 2, SRHT; which kernel evaluates the high-bit sum for buckets of more than 24
+ *     selected rows on average): 0 = staged through LDS, sixteen wavefronts of one row tile each, so
+ *     that up to 16 tiles of a bucket share one pass over its block of the intermediate, folding by the
+ *     8-point transform when a bucket averages 64 rows or more (FP32 intermediate) or 128 rows or more
+ *     (FP64) and by the 4-point one otherwise, the default; 1 = operands loaded straight into registers
+ *     (FP32 intermediate; the FP64 one takes its general form); 2 = staged through LDS, eight
+ *     wavefronts, 4-point fold; 3 = sixteen wavefronts, 4-point fold; 4 = sixteen wavefronts, 8-point
+ *     fold.  Every form computes the same sums (exactly, for integer-valued A).
+ * INVALID_ARG for a null context, an unknown key or an out-of-range value. */
+lsq_status lsq_set_option(lsq_ctx* ctx, const char* key, int64_t value);
 
 const char* lsq_status_string(lsq_status s);
 const char* lsq_last_error(void);

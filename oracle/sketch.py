@@ -33,11 +33,7 @@ def fwht_rows(X):
 def hadamard_entry(k, j):
     """H_N[k, j] = (-1)^popcount(k & j) for integer arrays k, j."""
     x = np.bitwise_and(np.asarray(k, dtype=np.int64), np.asarray(j, dtype=np.int64))
-    pc = np.zeros_like(x)
-    while np.any(x):
-        pc += x & 1
-        x >>= 1
-    return np.where(pc % 2 == 1, -1.0, 1.0)
+    return np.where(np.bitwise_count(x) % 2 == 1, -1.0, 1.0)
 
 
 def srht_sketch(A, m, seed, t=0):
@@ -52,20 +48,21 @@ def srht_sketch(A, m, seed, t=0):
     return Y[rows] / np.sqrt(m)
 
 
-def srht_sketch_rows(A, m, seed, t, which, cols=None):
-    """Selected output rows `which` (positions in [0, m)) of S A, each computed directly as
-    m^{-1/2} sum_j H_N[k, j] e_j A[j, cols], one row at a time (for spot checks at large n)."""
+def srht_sketch_rows(A, m, seed, t, which, cols=None, row_block=1 << 16):
+    """Selected output rows `which` (positions in [0, m)) of S A, computed directly from the definition
+    m^{-1/2} sum_j H_N[k, j] e_j A[j, cols] (for spot checks at large n): the +-1 coefficients of those
+    rows are formed explicitly for a block of rows j of A at a time and multiplied with that block
+    (A may be of any real or integer dtype; the block is promoted to FP64)."""
     n, d = A.shape
     N = draws.padded_length(n)
     cols = np.arange(d) if cols is None else np.asarray(cols)
     e = draws.srht_signs(seed, t, N)[:n]
-    rows = draws.srht_rows(seed, t, N, m)
-    j = np.arange(n)
-    out = np.empty((len(which), len(cols)))
-    for a, pos in enumerate(which):
-        k = rows[pos]
-        coef = hadamard_entry(k, j) * e
-        out[a] = coef @ A[:, cols]
+    k = draws.srht_rows(seed, t, N, m)[np.asarray(which)]
+    out = np.zeros((len(k), len(cols)))
+    for j0 in range(0, n, row_block):
+        j1 = min(n, j0 + row_block)
+        coef = hadamard_entry(k[:, None], np.arange(j0, j1)[None, :]) * e[None, j0:j1]
+        out += coef @ np.asarray(A[j0:j1][:, cols], dtype=np.float64)
     return out / np.sqrt(m)
 
 

@@ -1,6 +1,7 @@
 // Host driver and C ABI of liblsq (declared in include/lsq.h).
 #include <math.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -64,7 +65,27 @@ struct lsq_ctx {
   size_t hx_len = 0;
   int w_dense = 0;        // the last factorization's W is dense (SVD form) rather than triangular
   int svd_rank = 0, svd_sweeps = 0;
+  // numerics options of this context (lsq_set_option)
+  int factor_mode = 0;    // 0 CholeskyQR2 with fallbacks, 1 Householder, 2 SVD, 3 column-pivoted QR
+  int srht_passb = 0;     // SRHT pass B form for large buckets
 };
+
+// Per-call trace on stderr when the environment variable LSQ_LOG is set to a non-zero value.
+static bool log_on() {
+  static const int on = [] {
+    const char* v = getenv("LSQ_LOG");
+    return v && *v && strcmp(v, "0") != 0 ? 1 : 0;
+  }();
+  return on != 0;
+}
+#define LSQ_TRACE(...)                     \
+  do {                                     \
+    if (log_on()) {                        \
+      fprintf(stderr, "[lsq] " __VA_ARGS__); \
+      fputc('\n', stderr);                 \
+      fflush(stderr);                      \
+    }                                      \
+  } while (0)
 
 // ------------------------------------------------------------------------------------------------
 // workspace
@@ -125,12 +146,13 @@ static lsq_status check_problem(const lsq_ctx* c, const lsq_problem* p) {
   return LSQ_OK;
 }
 
-static lsq_status check_sketch(const lsq_problem* p, const lsq_sketch_desc* s, bool need_factor) {
+static lsq_status check_sketch(const lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
+                               bool need_factor) {
   if (!s) return fail(LSQ_ERR_INVALID_ARG, "null sketch descriptor");
   if (s->m < 1) return fail(LSQ_ERR_INVALID_ARG, "m < 1");
   if (need_factor && s->m < p->d) return fail(LSQ_ERR_INVALID_ARG, "m < d: S A cannot have full rank");
   if (need_factor && s->m > FACTOR_M_MAX) return fail(LSQ_ERR_UNSUPPORTED, "m > 65536 is not implemented");
-  if (need_factor && g_factor_mode == 1 && s->m > QR_M_MAX)
+  if (need_factor && c->factor_mode == 1 && s->m > QR_M_MAX)
     return fail(LSQ_ERR_UNSUPPORTED, "Householder QR limited to m <= 8192");
   switch (s->kind) {
     case LSQ_SRHT:
@@ -193,6 +215,7 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     plan.N1 = N < 256 ? N : 256;
     plan.N2 = N / plan.N1;
     plan.m = s->m;
+    plan.passb = c->srht_passb;
     CHK(wsT(c, "srht_slot", plan.N1, &slot));
     CHK(wsT(c, "srht_order", s->m, &order));
     CHK(wsT(c, "srht_bstart", plan.N1 + 1, &bstart));
@@ -265,11 +288,6 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
   return LSQ_OK;
 }
 
-namespace lsq {
-int g_factor_mode = 0;
-int g_srht_passb = 0;
-}  // namespace lsq
-
 // Factor S A -> R, W = R^{-1}, W^T.  CholeskyQR2 (Gram matrices on the matrix cores) when the first
 // Cholesky is usable, otherwise Householder QR (m <= 8192) or shifted CholeskyQR3 (larger m); the
 // Householder form alone with lsq_tune("factor", 1).
@@ -279,7 +297,14 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
   double* tscr;
   CHK(wsT(c, "trinv", trinv_scratch_len(cholqr_padded(d)), &tscr));
   c->w_dense = 0;
-  if (g_factor_mode == 3) {
+  // A NaN or an infinity in A (or in a caller's S A) reaches S A: report it as such rather than as the
+  // breakdown it would cause in the factorization
+  HIPCHK(hipMemsetAsync(c->dflags + 7, 0, sizeof(int), st));
+  nonfinite_scan(st, SA, m, d, lds, c->dflags + 7);
+  HIPCHK(hipMemcpyAsync(c->hflags + 7, c->dflags + 7, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (c->hflags[7]) return fail(LSQ_ERR_NONFINITE, "S A holds a NaN or an infinity (non-finite values in A)");
+  if (c->factor_mode == 3) {
     // column-pivoted QR: the basic solution on the kept columns for a rank-deficient S A
     double* qs;
     CHK(wsT(c, "qrcp", qrcp_scratch_len(m, d), &qs));
@@ -289,7 +314,7 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
     if (c->svd_rank < 1) return fail(LSQ_ERR_RANK, "S A is zero");
     return LSQ_OK;
   }
-  if (g_factor_mode == 2) {
+  if (c->factor_mode == 2) {
     // SVD form: R by Householder QR (m <= 8192; a zero pivot is allowed, rank deficiency is handled by
     // the truncation) or CholeskyQR2, then one-sided Jacobi on R
     if (m <= QR_M_MAX) {
@@ -311,7 +336,7 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
     return LSQ_OK;
   }
   bool done = false;
-  if (g_factor_mode == 0) {
+  if (c->factor_mode == 0) {
     double* cs;
     CHK(wsT(c, "cholqr", cholqr_scratch_len(m, d), &cs));
     if (cholqr_factor(st, SA, m, d, lds, cs, R, c->dflags + 4, c->hflags + 4, tscr) == 0) {
@@ -520,7 +545,7 @@ void lsq_destroy(lsq_ctx* c) {
 lsq_status lsq_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s, void* SA,
                       int64_t ldsa, int32_t sa_dtype) {
   CHK(check_problem(c, p));
-  CHK(check_sketch(p, s, false));
+  CHK(check_sketch(c, p, s, false));
   if (!SA) return fail(LSQ_ERR_INVALID_ARG, "null SA");
   if (ldsa < p->d) return fail(LSQ_ERR_INVALID_ARG, "ldsa < d");
   if (sa_dtype != LSQ_F64) return fail(LSQ_ERR_INVALID_ARG, "sa_dtype must be LSQ_F64");
@@ -608,7 +633,7 @@ static lsq_status inner_pcg(lsq_ctx* c, const lsq_problem* p, int f32_math, cons
 lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
                          const lsq_pcg_opts* o, double* x, double* err_trace, lsq_info* info) {
   CHK(check_problem(c, p));
-  CHK(check_sketch(p, s, true));
+  CHK(check_sketch(c, p, s, true));
   if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
   if (o->max_iter < 1) return fail(LSQ_ERR_INVALID_ARG, "max_iter < 1");
   if (!(o->tol > 0.0) && o->stop_rule == 0) return fail(LSQ_ERR_INVALID_ARG, "tol must be > 0");
@@ -668,8 +693,9 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     dot_to_state(st, d, o->x_ref, b.red, c->ds);
   }
 
-  if (!o->mixed) {
-    // r_0 = A^T (y - A x_0)
+  bool measured_ok = false;
+  if (!o->mixed && o->stop_rule == 1) {
+    // exactly max_iter PCG iterations from r_0 = A^T (y - A x_0)
     if (grad && x0_zero) {
       reduce_partials(st, grad, b.part2, grad_rows, d, b.r, nullptr);
     } else {
@@ -684,9 +710,17 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     passes += it;
     est = c->hds->est;
   } else {
-    // iterative refinement: outer FP64 residual, inner PCG on the correction
-    double rho_b = -1.0;
+    // PCG on the correction system H dx = r from an accurate residual r = A^T (y - A x), then x += dx
+    // and a new residual in double-double arithmetic (rounded once) measures the result.  PCG's
+    // recursively updated residual drifts from the true one by about u kappa(A) relative to its start,
+    // so near the FP64 conditioning floor it reports progress that x no longer makes; the measured
+    // residual exposes that, and the next correction starts from it (residual replacement).  The plain
+    // form (FP64 A as given, FP64 arithmetic) and the mixed form (FP32 storage of A read into FP64
+    // registers, or FP32 arithmetic with inner_f32) share this loop; the plain form's first correction
+    // accumulates into x itself, so that its error trace follows the iterates.
+    double rho_b = -1.0, est_meas_prev = -1.0, est_exact = -1.0;
     const double floor_in = o->inner_f32 ? 1e-6 : 1e-13;
+    const int max_steps = std::max(o->max_refine, 1);
     double* rpart;
     CHK(wsT(c, "resid_dd", resid_dd_part_len(d), &rpart));
     if (d > 1024) return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
@@ -694,15 +728,18 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     // first pass, or one plain pass) give it to working accuracy.  Any other start takes the
     // double-double residual from the outset.
     double est_carried = -1.0;
-    for (int k = 0; k < o->max_refine; ++k) {
+    for (int k = 0; k <= max_steps; ++k) {
       // After a correction solved from an accurate residual (k >= 2: the first check, k = 1, measures
       // the PCG's own drift and is always taken), the new error estimate is the old one times the
       // correction solve's relative reduction; the rounding inside that solve is relative to the
       // correction, so the carried value stands in for one more residual.
-      if (k >= 2 && o->stop_rule == 0 && est_carried >= 0.0 && est_carried <= o->tol) {
+      if (k >= 2 && o->stop_rule == 0 && !o->x_ref && est_carried >= 0.0 && est_carried <= o->tol) {
         est = est_carried;
+        LSQ_TRACE("pcg step %d: carried estimate %.3e <= tol, done", k, est);
+        measured_ok = true;
         break;
       }
+      const bool measured = !(k == 0 && x0_zero);
       if (k == 0 && x0_zero && grad) {
         reduce_partials(st, grad, b.part2, grad_rows, d, b.r, nullptr);
       } else if (k == 0 && x0_zero) {
@@ -710,35 +747,55 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
         reduce_partials(st, b.part, b.part2, ng_, d, b.r, nullptr);
         passes += 1;
       } else if (!resid_dd(st, p->A, a_f32, p->n, d, p->lda, x, p->y, rpart, b.r, nullptr)) {
-        // outer residual in double-double (rounded once), so that it stays accurate near the solution
         return fail(LSQ_ERR_UNSUPPORTED, "double-double residual limited to d <= 1024");
       } else {
         passes += 1;
       }
       int ndot;
       precond_apply_any(st, W, WT, d, b.r, b.u, b.rhat, b.dotpart, &ndot, nullptr, c->w_dense);
-      pcg_init(st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, 1.0, x, b.r, nullptr, nullptr);
+      // (with x_ref: the exact error of x, from this residual)
+      pcg_init(st, d, b.rhat, b.p, b.dotpart, ndot, c->ds, 1.0, x, b.r, o->x_ref, nullptr);
       CHK(sync_state(c));
+      if (c->hds->status) break;  // a non-finite residual
+      if (o->x_ref) est_exact = c->hds->est;
       const double rho_s = c->hds->rho0;
       if (rho_b < 0.0) rho_b = rho_s;  // relative to the starting residual (x_0 = 0: to ||A x*||)
       est = rho_b > 0.0 ? 4.0 * sqrt(fmax(rho_s, 0.0) / rho_b) : 0.0;
-      if (o->stop_rule == 0 && est <= o->tol) break;
+      LSQ_TRACE("pcg step %d: %s residual, estimate %.3e (carried %.3e)", k,
+                measured ? "measured" : "first", est, est_carried);
+      if (o->stop_rule == 0 && est <= o->tol) {
+        measured_ok = true;
+        break;
+      }
       if (o->stop_rule == 1 && k > 0) break;
+      if (k == max_steps) break;  // budget of corrections spent
+      // a measured residual that did not halve since the last one: x is at the attainable accuracy
+      if (measured && est_meas_prev > 0.0 && est > 0.5 * est_meas_prev) {
+        LSQ_TRACE("pcg step %d: no progress since the last measured residual (%.3e), stop", k, est_meas_prev);
+        break;
+      }
+      if (measured) est_meas_prev = est;
       refinements += 1;
       // the inner stop rule bounds the error of the correction relative to the current error, whose
       // estimate is est = 4 sqrt(rho_s / rho_b): asking 0.9 tol / (est / 4) of it lands at 0.9 tol
       const double rel = fmax(est / 4.0, 1e-300);
       const double tol_in = o->stop_rule == 1 ? -1.0 : fmax(0.9 * o->tol / rel, floor_in);
-      vec_zero(st, b.dx, d);
+      const bool direct = !o->mixed && k == 0;  // the plain form's first correction: into x
+      double* z = direct ? x : b.dx;
+      if (!direct) vec_zero(st, b.dx, d);
       int it = 0;
-      CHK(inner_pcg(c, p, o->inner_f32, W, WT, b, b.dx, tol_in, o->max_iter, check_every, nullptr,
-                    nullptr, 0, &it));
+      CHK(inner_pcg(c, p, o->inner_f32, W, WT, b, z, tol_in, o->max_iter, check_every,
+                    direct ? o->x_ref : nullptr, direct ? err_trace : nullptr, direct ? trace_len : 0, &it));
       total_iters += it;
       passes += it;
+      LSQ_TRACE("pcg step %d: correction solve to %.3e relative: %d iterations, its estimate %.3e%s", k, tol_in,
+                it, c->hds->est, c->hds->done ? "" : " (budget spent)");
       if (c->hds->status) break;
       est_carried = est * (c->hds->est / 4.0);
-      vec_axpy(st, x, b.dx, 1.0, d);
+      if (!direct) vec_axpy(st, x, b.dx, 1.0, d);
+      if (!c->hds->done && o->stop_rule == 0) break;  // the iteration budget ended this solve
     }
+    if (o->x_ref && est_exact >= 0.0) est = est_exact;
   }
   HIPCHK(hipEventRecord(c->ev[3], st));
   HIPCHK(hipStreamSynchronize(st));
@@ -764,10 +821,8 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   lsq_status ret = LSQ_OK;
   if (dev_status == LSQ_ERR_RANK) ret = fail(LSQ_ERR_RANK, "breakdown: p^T H p <= 0");
   else if (dev_status == LSQ_ERR_NONFINITE) ret = fail(LSQ_ERR_NONFINITE, "non-finite value in PCG");
-  else if (o->stop_rule == 0) {
-    const bool ok = o->mixed ? (est <= o->tol) : (c->hds->done != 0);
-    if (!ok) ret = fail(LSQ_ERR_NOT_CONVERGED, "iteration budget spent before the stop rule held");
-  }
+  else if (o->stop_rule == 0 && !measured_ok)
+    ret = fail(LSQ_ERR_NOT_CONVERGED, "the measured residual did not meet the tolerance within the budget");
   if (info) info->status = ret;
   return ret;
 }
@@ -775,7 +830,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
 lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
                          const lsq_ihs_opts* o, double* x, double* err_trace, lsq_info* info) {
   CHK(check_problem(c, p));
-  CHK(check_sketch(p, s, true));
+  CHK(check_sketch(c, p, s, true));
   if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
   if (o->iters < 0) return fail(LSQ_ERR_INVALID_ARG, "iters < 0");
   if (err_trace && !o->x_ref) return fail(LSQ_ERR_INVALID_ARG, "err_trace needs x_ref");
@@ -903,7 +958,7 @@ lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
 lsq_status lsq_fcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
                          const lsq_fcg_opts* o, double* x, double* err_trace, lsq_info* info) {
   CHK(check_problem(c, p));
-  CHK(check_sketch(p, s, true));
+  CHK(check_sketch(c, p, s, true));
   if (!o || !x) return fail(LSQ_ERR_INVALID_ARG, "null options or x");
   if (o->iters < 0) return fail(LSQ_ERR_INVALID_ARG, "iters < 0");
   if (o->window < 0) return fail(LSQ_ERR_INVALID_ARG, "window < 0");
@@ -1060,11 +1115,22 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     g_fused_groups_per_cu = (int)value;
     return LSQ_OK;
   }
+  if (k == "batched_slots") {
+    if (value < 0 || value > 65536) return fail(LSQ_ERR_INVALID_ARG, "batched_slots in [0, 65536]");
+    g_batched_slots = (int)value;
+    return LSQ_OK;
+  }
+  return fail(LSQ_ERR_INVALID_ARG, "unknown tuning key: " + k);
+}
+
+lsq_status lsq_set_option(lsq_ctx* c, const char* key, int64_t value) {
+  if (!c || !key) return fail(LSQ_ERR_INVALID_ARG, "null context or key");
+  const std::string k(key);
   if (k == "factor") {
     if (value < 0 || value > 3)
       return fail(LSQ_ERR_INVALID_ARG,
                   "factor: 0 (CholeskyQR2), 1 (Householder), 2 (SVD) or 3 (column-pivoted QR)");
-    g_factor_mode = (int)value;
+    c->factor_mode = (int)value;
     return LSQ_OK;
   }
   if (k == "srht_passb") {
@@ -1072,15 +1138,10 @@ lsq_status lsq_tune(const char* key, int64_t value) {
       return fail(LSQ_ERR_INVALID_ARG,
                   "srht_passb: 0 (LDS-staged, fold width by bucket size, the default), 1 (register-direct), "
                   "2 (LDS-staged, 8 wavefronts), 3 (16 wavefronts, 4-point fold) or 4 (16 wavefronts, 8-point fold)");
-    g_srht_passb = (int)value;
+    c->srht_passb = (int)value;
     return LSQ_OK;
   }
-  if (k == "batched_slots") {
-    if (value < 0 || value > 65536) return fail(LSQ_ERR_INVALID_ARG, "batched_slots in [0, 65536]");
-    g_batched_slots = (int)value;
-    return LSQ_OK;
-  }
-  return fail(LSQ_ERR_INVALID_ARG, "unknown tuning key: " + k);
+  return fail(LSQ_ERR_INVALID_ARG, "unknown option: " + k);
 }
 
 lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* probs,

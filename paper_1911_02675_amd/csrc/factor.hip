@@ -6,6 +6,8 @@
 // factor T (Q_panel = I - V T V^T), and applies Q_panel^T to its own share of the trailing columns.
 // No grid-wide synchronisation is needed inside a launch; the panel is re-read from L2/MALL by each
 // workgroup instead.  Column-major scratch X keeps every column contiguous.
+#include <algorithm>
+
 #include "internal.h"
 
 namespace lsq {
@@ -361,6 +363,22 @@ void tri_inverse_padded(hipStream_t st, const double* R, int64_t n, double* W, d
   hipLaunchKernelGGL(k_trinv_pad, dim3((unsigned)((dq * dq + 255) / 256)), dim3(256), 0, st, R, n, dq, Rp, Wp);
   trinv_levels(st, Rp, Wp, Tp, dq);
   hipLaunchKernelGGL(k_trinv_copy, dim3((unsigned)((n * n + 255) / 256)), dim3(256), 0, st, Wp, dq, n, W);
+}
+
+// flag = 1 when some entry of X (m x d, row stride ld) is NaN or infinite.  Every writer stores the same
+// value, so the unordered stores need no atomics.
+__global__ __launch_bounds__(256) void k_nonfinite_scan(const double* __restrict__ X, int64_t m, int64_t d,
+                                                        int64_t ld, int* __restrict__ flag) {
+  bool bad = false;
+  const int64_t total = m * d, stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride)
+    bad |= !isfinite(X[(i / d) * ld + i % d]);
+  if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) *flag = 1;
+}
+
+void nonfinite_scan(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t ld, int* flag) {
+  const int64_t blocks = std::min<int64_t>((m * d + 255) / 256, 2048);
+  hipLaunchKernelGGL(k_nonfinite_scan, dim3((unsigned)blocks), dim3(256), 0, st, X, m, d, ld, flag);
 }
 
 void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status) {

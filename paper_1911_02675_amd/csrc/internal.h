@@ -38,6 +38,7 @@ void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, in
 struct SrhtPlan {
   int64_t N, N1, N2, m;
   int nneeded;             // distinct k_lo among the selected rows
+  int passb = 0;           // form of pass B for large buckets (lsq_set_option "srht_passb")
 };
 size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32);
 // Groups the selected rows by k_lo: slot (N1 ints, -1 if unused), order (m ints), bstart (N1+1 ints).
@@ -83,6 +84,8 @@ void tri_inverse(hipStream_t st, const double* R, int64_t d, double* W, double* 
 // W = R^{-1} for an n x n upper R (row-major, ld n) into W (n x n); scratch: trinv_scratch_len(n) doubles.
 void tri_inverse_padded(hipStream_t st, const double* R, int64_t n, double* W, double* scratch);
 // status |= 1 when some |R_kk| <= 8 d eps max |R_jj|.
+// flag (device int, cleared by the caller) = 1 when X (m x d, row stride ld) holds a NaN or an infinity.
+void nonfinite_scan(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t ld, int* flag);
 void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status);
 
 // ---- chol.hip -----------------------------------------------------------------------------------
@@ -126,8 +129,6 @@ int svd_precond(hipStream_t st, double* R, int64_t d, double rtol, double* scrat
 size_t qrcp_scratch_len(int64_t m, int64_t d);
 int qrcp_precond(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double rtol, double* scratch,
                  double* trinv_scratch, double* R, double* W, double* WT, int* flags, int* hflags);
-extern int g_factor_mode;  // tuning: 0 = CholeskyQR2 with fallbacks, 1 = Householder, 2 = SVD, 3 = pivoted QR (2, 3: dense W)
-extern int g_srht_passb;   // tuning: SRHT pass B for large buckets, 0 = LDS-staged (16 wavefronts, fold width by bucket size), 1 = register-direct, 2 = LDS-staged (8), 3 / 4 = 16 wavefronts, 4- / 8-point fold
 constexpr int64_t QR_M_MAX = 8192;       // Householder QR: rows held in registers
 constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 

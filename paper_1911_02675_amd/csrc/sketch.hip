@@ -1139,7 +1139,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
   // buckets of more than about 24 selected rows on average: 64-row chunks (one sweep of T per bucket)
   const bool big = p.m > 24 * p.N1;
   // the LDS-staged pass B reads T in 64-column stripes, written so by pass A
-  const bool lds_b = p.N1 == SRHT_N1 && big && p.N2 >= 512 && g_srht_passb != 1;
+  const bool lds_b = p.N1 == SRHT_N1 && big && p.N2 >= 512 && p.passb != 1;
   const int64_t ncbs = lds_b ? (dT + 63) / 64 : 0;
   if (p.N1 == SRHT_N1) {
     const bool vec = d % VW == 0 && lda % VW == 0 && ((uintptr_t)A % (VW * sizeof(TA))) == 0;
@@ -1185,8 +1185,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       // on average (measured at n = 2^22, d = 1024: sketches 3-8 % faster from 64 to 256 rows, where its
       // tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen, 4-point;
       // 4 sixteen, 8-point.
-      const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 64 * p.N1);
-      if (g_srht_passb == 2)
+      const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= 64 * p.N1);
+      if (p.passb == 2)
         hipLaunchKernelGGL((k_srht_passB_u<float, 8, 2>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
       else if (f8)
@@ -1210,8 +1210,8 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
     // as for FP32 T; the FP64 8-point form's 64 KB stages leave one workgroup per CU (measured at n = 2^22,
     // d = 1024: sketches 5-9 % faster from 128 to 256 rows per bucket, even at 96)
-    const bool f8 = g_srht_passb == 4 || (g_srht_passb == 0 && p.m >= 128 * p.N1);
-    if (g_srht_passb == 2)
+    const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= 128 * p.N1);
+    if (p.passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
     else if (f8)

@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_timing", "lsq_tune", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_timing", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -98,6 +98,7 @@ def load():
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
         "lsq_fused_pass_timing": ([P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)], I32),
         "lsq_tune": ([C.c_char_p, I64], I32),
+        "lsq_set_option": ([P, C.c_char_p, I64], I32),
         "lsq_status_string": ([I32], C.c_char_p),
         "lsq_last_error": ([], C.c_char_p),
         "lsq_version": ([], C.c_char_p),
@@ -121,7 +122,7 @@ def _check(status):
 
 
 def tune(key, value):
-    """Set a process-wide tuning parameter of the library (see lsq_tune in include/lsq.h)."""
+    """Set a process-wide launch parameter of the library (see lsq_tune in include/lsq.h)."""
     _check(load().lsq_tune(key.encode(), int(value)))
 
 
@@ -183,6 +184,10 @@ class Context:
         self.close()
 
     # ---- entry points (same names as the C ABI, without the prefix) ----
+    def set_option(self, key, value):
+        """A numerics option of this context ("factor", "srht_passb"; see lsq_set_option)."""
+        _check(self.lib.lsq_set_option(self.h, key.encode(), int(value)))
+
     def sketch(self, A, y, desc, SA):
         p = problem(A, y)
         _check(self.lib.lsq_sketch(self.h, C.byref(p), C.byref(desc), _ptr(SA), SA.stride(0), LSQ_F64))

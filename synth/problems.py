@@ -119,3 +119,21 @@ def _matvec(A, x):
     for r0 in range(0, A.shape[0], CHUNK):
         y[r0:r0 + CHUNK] = A[r0:r0 + CHUNK].astype(np.float64, copy=False) @ x
     return y
+
+
+def make_integer_matrix(n, d, amax, seed=0):
+    """n x d int8 matrix with entries uniform on {-amax, ..., amax} (amax <= 127), by row chunks.
+    With small integers every partial sum of a signed transform stays an exact integer in FP32 as long
+    as amax * n < 2^24, which turns floating-point parity checks into exact ones."""
+    if not 0 < amax <= 127:
+        raise ValueError("needs 0 < amax <= 127")
+    A = np.empty((n, d), dtype=np.int8)
+    chunks = [(c0, min(n, c0 + CHUNK)) for c0 in range(0, n, CHUNK)]
+
+    def gen(ci):
+        c0, c1 = chunks[ci]
+        A[c0:c1] = _rng(seed, 31, ci).integers(-amax, amax + 1, size=(c1 - c0, d), dtype=np.int8)
+
+    with cf.ThreadPoolExecutor(_threads()) as ex:
+        list(ex.map(gen, range(len(chunks))))
+    return A

@@ -22,7 +22,6 @@ def ctx():
     from paper_1911_02675_amd import lsq
     c = lsq.Context()
     yield c
-    lsq.tune("factor", 0)
     c.close()
 
 
@@ -47,7 +46,7 @@ def test_factor_paths(ctx, m, d, kappa, mode):
     from paper_1911_02675_amd import lsq
     from synth import make_problem
     say("factor path", m, d, kappa, mode)
-    lsq.tune("factor", mode)
+    ctx.set_option("factor", mode)
     try:
         X = make_problem(m, d, kappa, seed=m + d)["A"]
         R = torch.empty((d, d), dtype=torch.float64, device="cuda")
@@ -56,7 +55,7 @@ def test_factor_paths(ctx, m, d, kappa, mode):
         torch.cuda.synchronize()
         _check(X, R.cpu().numpy(), W.cpu().numpy(), kappa)
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
 
 
 def test_factor_limits_and_rank(ctx):
@@ -70,20 +69,20 @@ def test_factor_limits_and_rank(ctx):
     with pytest.raises(lsq.LsqError) as e:
         ctx.factor(torch.from_numpy(X).cuda(), R, None)  # rank deficient above the Householder limit
     assert e.value.status == lsq.LSQ_ERR_RANK
-    lsq.tune("factor", 1)
+    ctx.set_option("factor", 1)
     try:
         X = rng.standard_normal((9000, 12))
         with pytest.raises(lsq.LsqError) as e:
             ctx.factor(torch.from_numpy(X).cuda(), R, None)
         assert e.value.status == lsq.LSQ_ERR_UNSUPPORTED
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
     try:
         with pytest.raises(lsq.LsqError) as e:
-            lsq.tune("factor", 4)  # 0..3 are the factor forms
+            ctx.set_option("factor", 4)  # 0..3 are the factor forms
         assert e.value.status == lsq.LSQ_ERR_INVALID_ARG
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
 
 
 def test_pcg_with_sketch_above_householder_limit(ctx):

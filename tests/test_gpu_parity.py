@@ -171,15 +171,53 @@ def test_srht_pass_b_forms(ctx, n, d, m):
     got = {}
     try:
         for mode in (0, 1, 2, 3, 4):
-            lsq.tune("srht_passb", mode)
+            ctx.set_option("srht_passb", mode)
             got[mode] = (_sa(ctx, A, "srht", m, seed=9, t=2),
                          _sa(ctx, A.astype(np.float32), "srht", m, seed=9, t=2, compute="f32"))
     finally:
-        lsq.tune("srht_passb", 0)
+        ctx.set_option("srht_passb", 0)
     for mode, (g64, g32) in got.items():
         assert np.all(np.abs(g64 - ref) <= 8 * (math.log2(N) + 2) * EPS * scale), mode
         assert np.all(np.abs(g32 - ref32) <= 8 * (math.log2(N) + 2) * 2.0 ** -24 * scale), mode
     assert np.array_equal(got[2][0], got[3][0]) and np.array_equal(got[2][1], got[3][1])
+
+
+@pytest.mark.parametrize("n,d,m", [(100, 3, 16), (4096, 64, 256), (20000, 129, 700), (1 << 15, 48, 12000),
+                                   (300000, 130, 20000), (1 << 17, 20, 100000), (1 << 18, 64, 40000)])
+def test_srht_exact_integer(ctx, n, d, m):
+    """Exact parity of every SRHT form.  With A in {-2..2} every partial sum of the transform is an
+    integer of magnitude at most 2 N < 2^24, exact in FP32 and FP64 alike, so S A sqrt(m) must equal
+    the oracle's transform exactly: every pass B form (tuning key srht_passb 0-4, each taken where the
+    buckets are large), FP64 and FP32 A, FP64 and FP32 transforms, the 16-byte vector pass A and the
+    scalar one (leading dimension d + 1).  A wrong sign, index or fold in any of them changes some
+    output integer."""
+    from oracle import sketch
+    from paper_1911_02675_amd import lsq
+    torch = _torch()
+    say("srht exact", n, d, m)
+    Ai = np.random.default_rng(n + 3 * d).integers(-2, 3, size=(n, d)).astype(np.float64)
+    ref = sketch.srht_sketch(Ai, m, 9, 2) * math.sqrt(m)
+    assert np.max(np.abs(ref - np.rint(ref))) < 1e-6
+    ref = np.rint(ref)
+    pad = torch.zeros((n, d + 1), dtype=torch.float64, device="cuda")
+    pad[:, :d] = dev(Ai)
+    y0 = torch.zeros(n, dtype=torch.float64, device="cuda")
+    cases = {"f64/f64": (dev(Ai), "f64"), "f32/f32": (dev(Ai.astype(np.float32)), "f32"),
+             "f32/f64": (dev(Ai.astype(np.float32)), "f64"), "f64/f32": (dev(Ai), "f32"),
+             "f64 lda=d+1": (pad[:, :d], "f64"), "f32 lda=d+1": (pad.float()[:, :d], "f32")}
+    modes = (0, 1, 2, 3, 4) if m > 24 * 256 else (0,)
+    try:
+        for mode in modes:
+            ctx.set_option("srht_passb", mode)
+            for name, (A, compute) in cases.items():
+                SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+                ctx.sketch(A, y0, lsq.sketch_desc("srht", m, seed=9, t=2, compute=compute), SA)
+                got = host(SA) * math.sqrt(m)
+                bad = int(np.sum(np.rint(got) != ref))
+                assert bad == 0, (mode, name, bad)
+                assert np.max(np.abs(got - ref)) <= 4 * EPS * max(1.0, np.abs(ref).max()), (mode, name)
+    finally:
+        ctx.set_option("srht_passb", 0)
 
 
 @pytest.mark.parametrize("n,d,m,s", [(100, 3, 16, 1), (5000, 64, 256, 4), (20001, 100, 512, 8),
@@ -320,19 +358,20 @@ def test_pcg_mixed_fp32_storage(ctx, inner_f32, kappa):
     assert e <= max(1e-10, floor)
 
 
-@pytest.mark.parametrize("mixed", [0, 1])
-def test_pcg_first_gradient_from_pass_a(ctx, mixed):
+@pytest.mark.parametrize("mixed,compute", [(0, "f64"), (1, "f32"), (1, "f64")])
+def test_pcg_first_gradient_from_pass_a(ctx, mixed, compute):
     """From x_0 = 0 with the SRHT in its vector form, the first gradient A^T y comes from the sketch's
     first pass.  A start of 1e-200 e_0 has the same first residual to rounding but takes it from a pass
     of its own (plain, or double-double in the mixed form), with the same sketch: the iterates after three
     fixed iterations agree to rounding.  With lda not a multiple of 16 bytes the sketch takes its general
-    form and the solve a plain first pass; it converges to the same solution."""
+    form and the solve a plain first pass; it converges to the same solution.  The mixed form runs with
+    an FP32 and with an FP64 transform of its FP32 A (the latter converts the loaded rows to FP64)."""
     from oracle.solve import a_norm_error
     from paper_1911_02675_amd import lsq
     from synth import make_problem
     torch = _torch()
     n, d, m = 30001, 128, 512
-    say("first gradient", mixed)
+    say("first gradient", mixed, compute)
     P = make_problem(n, d, 1e4, sigma=0.01, seed=77)
     A, y = P["A"], P["y"]
     if mixed:
@@ -340,7 +379,7 @@ def test_pcg_first_gradient_from_pass_a(ctx, mixed):
     dt = torch.float32 if mixed else torch.float64
     Ad = torch.tensor(A, dtype=dt, device="cuda")
     yd = dev(y)
-    desc = lsq.sketch_desc("srht", m, seed=5, compute="f32" if mixed else "f64")
+    desc = lsq.sketch_desc("srht", m, seed=5, compute=compute)
     xs = []
     for x0 in (0.0, 1e-200):
         x = torch.zeros(d, dtype=torch.float64, device="cuda")
@@ -397,6 +436,62 @@ def test_pcg_errors(ctx):
     Xb[:, 5] = Xb[:, 9]
     st, _ = ctx.pcg_solve(dev(Xb), y, lsq.sketch_desc("gaussian", 80), x, raise_on_error=False)
     assert st == lsq.LSQ_ERR_RANK
+
+
+@pytest.mark.parametrize("kind,s", [("srht", 1), ("sjlt", 2), ("gaussian", 1)])
+def test_pcg_nonfinite(ctx, kind, s):
+    """A NaN or an infinity in A reaches S A (every embedding mixes each row of A into some row of S A)
+    and is reported as such before the factorization; one in y reaches the first residual."""
+    from paper_1911_02675_amd import lsq
+    from synth import make_problem
+    torch = _torch()
+    say("nonfinite", kind)
+    P = make_problem(3000, 20, 1e3, seed=5)
+    for where, val, a32 in [("A", np.nan, False), ("A", np.inf, False), ("y", np.nan, False), ("y", -np.inf, False),
+                            ("A", np.nan, True), ("y", np.inf, True)]:
+        A, y = P["A"].copy(), P["y"].copy()
+        if where == "A":
+            A[1234, 7] = val
+        else:
+            y[777] = val
+        Ad = dev(A.astype(np.float32)) if a32 else dev(A)
+        x = torch.zeros(20, dtype=torch.float64, device="cuda")
+        st, _ = ctx.pcg_solve(Ad, dev(y), lsq.sketch_desc(kind, 80, seed=2, s=s,
+                                                          compute="f32" if a32 and kind == "srht" else "f64"),
+                              x, mixed=int(a32), raise_on_error=False)
+        assert st == lsq.LSQ_ERR_NONFINITE, (where, val, a32, st)
+    SA = np.random.default_rng(1).standard_normal((100, 20))
+    SA[3, 4] = np.nan
+    R = torch.empty((20, 20), dtype=torch.float64, device="cuda")
+    with pytest.raises(lsq.LsqError) as e:
+        ctx.factor(dev(SA), R, None)
+    assert e.value.status == lsq.LSQ_ERR_NONFINITE
+
+
+def test_pcg_plain_verified_beyond_fp64_floor(ctx):
+    """Plain FP64 form at kappa = 1e8 on a planted noisy problem (x* exact): PCG's recursively updated
+    residual keeps meeting the proxy after the true error has stalled near the FP64 floor, so the result
+    is measured with a double-double residual.  With one correction solve the status must not claim the
+    tolerance unless x meets it; with the default budget, residual replacement reaches it."""
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    torch = _torch()
+    n, d, m = 1 << 16, 128, 1024
+    P = make_planted(n, d, 1e8, sigma=0.01, seed=93)
+    A, y, xs = P["A64"], P["y64"], P["x_star"]
+    Ad, yd = dev(A), dev(y)
+    for max_refine in (1, 8):
+        x = torch.zeros(d, dtype=torch.float64, device="cuda")
+        st, info = ctx.pcg_solve(Ad, yd, lsq.sketch_desc("srht", m, seed=4), x, tol=1e-10, max_iter=300,
+                                 max_refine=max_refine, raise_on_error=False)
+        e = a_norm_error(A, host(x), xs)
+        say("  plain kappa 1e8, max_refine", max_refine, "status", st, "solves", info.refinements,
+            "iters", info.iters, "estimate", info.est_rel_err, "e_A", e)
+        assert st in (lsq.LSQ_OK, lsq.LSQ_ERR_NOT_CONVERGED)
+        if st == lsq.LSQ_OK:
+            assert e <= 1e-10
+    assert st == lsq.LSQ_OK and e <= 1e-10
 
 
 # ----------------------------------------------------------------------------------------------

@@ -1,4 +1,4 @@
-"""SVD (LSRN) preconditioner on the GPU (lsq_tune("factor", 2): one-sided Jacobi on R, W = V Sigma^+
+"""SVD (LSRN) preconditioner on the GPU (lsq_set_option("factor", 2): one-sided Jacobi on R, W = V Sigma^+
 dense) against the oracle.
 
   full rank      PCG with W W^T follows the oracle's PCG iterates (the same H_S^{-1}) and R^T R = H_S
@@ -23,7 +23,6 @@ def ctx():
     from paper_1911_02675_amd import lsq
     c = lsq.Context()
     yield c
-    lsq.tune("factor", 0)
     c.close()
 
 
@@ -41,11 +40,11 @@ def test_svd_factor_full_rank(ctx, m, d, kappa):
     SA = make_problem(m, d, kappa, seed=m + d)["A"]
     R = torch.empty((d, d), dtype=torch.float64, device="cuda")
     W = torch.empty((d, d), dtype=torch.float64, device="cuda")
-    lsq.tune("factor", 2)
+    ctx.set_option("factor", 2)
     try:
         ctx.factor(dev(SA), R, W)
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
     Rh, Wh = R.cpu().numpy(), W.cpu().numpy()
     H = SA.T @ SA
     e1 = np.linalg.norm(Rh.T @ Rh - H) / np.linalg.norm(H)
@@ -70,7 +69,7 @@ def test_svd_pcg_iterates_and_min_norm(ctx):
     x = torch.zeros(d, dtype=torch.float64, device="cuda")
     tr = torch.zeros(7, dtype=torch.float64, device="cuda")
     desc = lsq.sketch_desc("srht", m, seed=9)
-    lsq.tune("factor", 2)
+    ctx.set_option("factor", 2)
     try:
         # full rank: the first iterates against the oracle's PCG with its own SVD preconditioner
         st, info = ctx.pcg_solve(dev(A), dev(y), desc, x, tol=1e-300, max_iter=6, stop_rule=1)
@@ -96,7 +95,7 @@ def test_svd_pcg_iterates_and_min_norm(ctx):
         rank = int(np.sum(np.abs(R.cpu().numpy()).sum(axis=1) > 0))
         assert rank == d
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
     # the triangular form reports the rank deficiency
     x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
     st, _ = ctx.pcg_solve(dev(Ad), dev(y), desc, x, tol=1e-12, max_iter=100, raise_on_error=False)
@@ -111,11 +110,11 @@ def test_qrcp_factor_full_rank(ctx, m, d, kappa):
     SA = make_problem(m, d, kappa, seed=m + 2 * d)["A"]
     R = torch.empty((d, d), dtype=torch.float64, device="cuda")
     W = torch.empty((d, d), dtype=torch.float64, device="cuda")
-    lsq.tune("factor", 3)
+    ctx.set_option("factor", 3)
     try:
         ctx.factor(dev(SA), R, W)
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
     from oracle.pcg import qrcp_preconditioner
     Rh, Wh = R.cpu().numpy(), W.cpu().numpy()
     H = SA.T @ SA
@@ -143,11 +142,11 @@ def test_qrcp_basic_solution(ctx):
     y = P["y"]
     desc = lsq.sketch_desc("srht", m, seed=10)
     x = torch.zeros(d + 2, dtype=torch.float64, device="cuda")
-    lsq.tune("factor", 3)
+    ctx.set_option("factor", 3)
     try:
         st, info = ctx.pcg_solve(dev(A), dev(y), desc, x, tol=1e-12, max_iter=100)
     finally:
-        lsq.tune("factor", 0)
+        ctx.set_option("factor", 0)
     xh = x.cpu().numpy()
     zeros = int(np.sum(xh == 0.0))
     ne = np.linalg.norm(A.T @ (A @ xh - y)) / np.linalg.norm(A.T @ y)

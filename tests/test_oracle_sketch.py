@@ -36,6 +36,13 @@ def test_srht_sketch_equals_dense_and_rowwise():
         assert np.allclose(SA, sketch.srht_matrix(n, 24, 9, 2) @ Ap, atol=1e-12)
         pick = sketch.srht_sketch_rows(A, 24, 9, 2, [0, 7, 23], cols=[1, 4])
         assert np.allclose(pick, SA[[0, 7, 23]][:, [1, 4]], atol=1e-12)
+    # small-integer A: every sum is exact, so the blocked row form (several blocks and a ragged one,
+    # int8 storage) equals the full transform bit for bit before the 1/sqrt(m) scale
+    Ai = rng.integers(-3, 4, size=(1000, 6)).astype(np.int8)
+    full = sketch.srht_sketch(Ai.astype(np.float64), 40, seed=4, t=1) * np.sqrt(40)
+    rows = sketch.srht_sketch_rows(Ai, 40, 4, 1, [0, 13, 39], row_block=96) * np.sqrt(40)
+    assert np.array_equal(np.rint(rows), np.rint(full[[0, 13, 39]]))
+    assert np.max(np.abs(rows - np.rint(rows))) < 1e-9
 
 
 def test_sjlt_columns_unit_norm_and_scatter():
