@@ -226,6 +226,19 @@ lsq_status lsq_factor(lsq_ctx* ctx, const double* SA, int64_t m, int64_t d, int6
 lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, int32_t f32_math,
                           const double* v, double* w, double* scal);
 
+/* lsq_fused_pass (modes 0 and 1) for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  It calls no allocating routine and does
+ * not touch the context's workspace: the per-workgroup partials and both reduction stages live in a static
+ * device array of 8 MiB per device (NOALLOC: 2^20 doubles), loaded with the library and held until the
+ * process ends; the workgroup count is capped so that nwg (d + 1) + 33 (d + 1) doubles fit, so results can
+ * differ from lsq_fused_pass in the last bits when its grid is larger.  Asynchronous: the work is queued on
+ * the context's stream and the call returns without waiting (errors of the launches surface at the
+ * caller's next synchronisation).  Every call on one GPU shares that GPU's array (it keeps the last call's
+ * contents; every value read is written first by the same call): calls that overlap on one GPU, from any
+ * context or stream, race.  INVALID_ARG as lsq_fused_pass; UNSUPPORTED for mode 2. */
+lsq_status lsq_fused_pass_noalloc(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, int32_t f32_math,
+                                  const double* v, double* w, double* scal);
+
 /* PCG with a fixed sketch (Section 1.2): x (device, d) holds x_0 on entry (zeros are a valid start)
  * and the solution on exit.  The stop rule measures the error relative to that of x_0 (for x_0 = 0,
  * relative to ||A x*||): a warm start already near x* asks for a correspondingly smaller error and

@@ -68,6 +68,7 @@ struct lsq_ctx {
   // numerics options of this context (lsq_set_option)
   int factor_mode = 0;    // 0 CholeskyQR2 with fallbacks, 1 Householder, 2 SVD, 3 column-pivoted QR
   int srht_passb = 0;     // SRHT pass B form for large buckets
+  double* noalloc = nullptr;  // this device's static array for lsq_fused_pass_noalloc
 };
 
 // Per-call trace on stderr when the environment variable LSQ_LOG is set to a non-zero value.
@@ -509,6 +510,11 @@ lsq_status lsq_create(lsq_ctx** out, void* stream) {
   }
   hipMemset(c->ds, 0, sizeof(DevState));
   hipMemset(c->dflags, 0, 8 * sizeof(int));
+  // the allocation-free entry point's array: its address on this (current) device, once per device
+  if (noalloc_scratch(c->dev, &c->noalloc) != hipSuccess) {
+    lsq_destroy(c);
+    return fail(LSQ_ERR_HIP, "hipGetSymbolAddress of the static partials array failed");
+  }
   *out = c;
   return LSQ_OK;
 }
@@ -601,6 +607,34 @@ lsq_status lsq_fused_pass(lsq_ctx* c, const lsq_problem* p, int32_t mode, int32_
   HIPCHK(hipStreamSynchronize(c->st));
   if (e) fused_account(c, ev0, 1);
   c->fused_used = ev0;
+  return LSQ_OK;
+}
+
+lsq_status lsq_fused_pass_noalloc(lsq_ctx* c, const lsq_problem* p, int32_t mode, int32_t f32_math,
+                                  const double* v, double* w, double* scal) {
+  CHK(check_problem(c, p));
+  if (!v || !w || !scal) return fail(LSQ_ERR_INVALID_ARG, "null v, w or scal");
+  if (mode == 2)
+    return fail(LSQ_ERR_UNSUPPORTED, "lsq_fused_pass_noalloc: mode 2 (double-double) needs more partials than "
+                                     "the static array holds; use lsq_fused_pass");
+  if (mode != 0 && mode != 1) return fail(LSQ_ERR_INVALID_ARG, "mode must be 0 or 1");
+  if (f32_math && p->a_dtype != LSQ_F32) return fail(LSQ_ERR_INVALID_ARG, "f32_math needs an FP32 matrix");
+  if (!c->noalloc) return fail(LSQ_ERR_HIP, "static partials array not available on this device");
+  // partials (one row of d + 1 per workgroup), the REDUCE_SPLIT rows of the first reduction stage and
+  // the reduced row, all inside the array: the workgroup count is capped to what fits
+  const int64_t width = p->d + 1;
+  const int64_t rows_fit = (int64_t)NOALLOC_DOUBLES / width - (REDUCE_SPLIT + 1);
+  if (rows_fit < 1) return fail(LSQ_ERR_UNSUPPORTED, "lsq_fused_pass_noalloc: d too large for the static array");
+  const int nwg = (int)std::min<int64_t>(fused_nwg(p->n, p->d), rows_fit);
+  double* part = c->noalloc;
+  double* part2 = part + (size_t)nwg * width;
+  double* red = part2 + (size_t)REDUCE_SPLIT * width;
+  const int ng_ = fused_pass(c->st, p->A, p->a_dtype == LSQ_F32, f32_math, p->n, p->d, p->lda, mode, v, p->y, part,
+                             nwg, nullptr);
+  reduce_partials(c->st, part, part2, ng_, p->d, red, nullptr);
+  vec_copy(c->st, w, red, p->d);
+  vec_copy(c->st, scal, red + p->d, 1);
+  HIPCHK(hipGetLastError());
   return LSQ_OK;
 }
 

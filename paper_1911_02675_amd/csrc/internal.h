@@ -171,6 +171,13 @@ void ihs_update(hipStream_t st, int64_t d, double* x, double* xprev, const doubl
 // out = sqrt(a[0] / b) style scalar helpers evaluated on the device
 void error_from_resid(hipStream_t st, const double* scal, double denom, double* out);
 
+// ---- noalloc.hip ------------------------------------------------------------------------------
+// A file-scope device array of NOALLOC_DOUBLES doubles (8 MiB) per device for lsq_fused_pass_noalloc;
+// noalloc_scratch returns its address on device dev (the current device), looked up once per device.
+constexpr size_t NOALLOC_DOUBLES = (size_t)1 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(int dev, double** out);
+
 // ---- resid.hip ----------------------------------------------------------------------------------
 // r = A^T (y - A x) in double-double, rounded once; scal (optional) = ||y - A x||^2.  part:
 // resid_dd_part_len(d) doubles.  Returns false when d is beyond the kernel's chunk limit (d <= 1024).

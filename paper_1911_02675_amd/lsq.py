@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_timing", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -84,6 +84,7 @@ def load():
         "lsq_sketch": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), P, I64, I32], I32),
         "lsq_factor": ([P, P, I64, I64, I64, P, P], I32),
         "lsq_fused_pass": ([P, C.POINTER(Problem), I32, I32, P, P, P], I32),
+        "lsq_fused_pass_noalloc": ([P, C.POINTER(Problem), I32, I32, P, P, P], I32),
         "lsq_pcg_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(PcgOpts), P, P,
                            C.POINTER(Info)], I32),
         "lsq_ihs_solve": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), C.POINTER(IhsOpts), P, P,
@@ -202,6 +203,12 @@ class Context:
         p = problem(A, y)
         _check(self.lib.lsq_fused_pass(self.h, C.byref(p), mode, int(f32_math), _ptr(v), _ptr(w),
                                        _ptr(scal)))
+
+    def fused_pass_noalloc(self, A, y, v, w, scal, mode=0, f32_math=False):
+        """Queued on the context's stream; the caller synchronises."""
+        p = problem(A, y)
+        _check(self.lib.lsq_fused_pass_noalloc(self.h, C.byref(p), mode, int(f32_math), _ptr(v), _ptr(w),
+                                               _ptr(scal)))
 
     def pcg_solve(self, A, y, desc, x, tol=1e-10, max_iter=200, stop_rule=0, mixed=0, max_refine=8,
                   inner_f32=0, check_every=8, x_ref=None, err_trace=None, raise_on_error=True):
