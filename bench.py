@@ -76,11 +76,13 @@ def parse():
     ap.add_argument("--calibration-copy", action="store_true",
                     help="before the solves, convert 2^28 FP32 values to FP64 once (1 GiB read, 2 GiB "
                          "written): a kernel of known traffic for scaling rocprofv3 byte counters")
-    ap.add_argument("--sweep", choices=["c2", "c4", "c5", "msize"], default=None,
+    ap.add_argument("--sweep", choices=["c2", "c4", "c5", "msize", "gauss"], default=None,
                     help="c2: n=2^20 d=512 kappa=1e4, {SRHT, SJLT s=1,2,4,8, Gaussian} x m={2d,4d,8d}; "
                          "c4: 512 uneven problems, batched form vs a per-problem loop; "
                          "c5: refreshed IHS / Polyak-IHS statistics over 32 sketch seeds vs closed forms; "
+                         "gauss: the Gaussian sketch alone at the c2, c5 and c3 shapes; "
                          "one JSON line per run")
+    ap.add_argument("--gauss-cases", default="", help="gauss: comma list of case indices to run (default all)")
     ap.add_argument("--count", type=int, default=512, help="c4: number of problems")
     ap.add_argument("--slots", default="0", help="c4: comma list of batched workgroup counts to time "
                                                  "(0 = one per compute unit)")
@@ -128,6 +130,51 @@ def sweep_c2(a):
                               "iters": info.iters, "fused_ms": round(fms, 4),
                               "fused_gbs": round(n * d * 8 / (fms * 1e-3) / 1e9, 1) if fms > 0 else None,
                               "rel_a_norm_error": e}), flush=True)
+    ctx.close()
+
+
+def sweep_gauss(a):
+    """The Gaussian sketch alone (counter-based normals fused into the matrix-core GEMM) at the shapes of
+    the workloads that use it: n = 2^20, d = 512, m in {2d, 4d, 8d} (FP64, plain form), n = 2^21, d = 256,
+    m = 4d (FP64, refreshed IHS), n = 2^22, d = 1024, m = 4d (BF16 S times a three-term BF16 split of
+    FP32 A, the precision form).  Time per sketch from torch events on the library's stream (median of
+    `steps` after `warmup`), matrix-core work 2 m n d (x 3 split terms for BF16) against the dense peak
+    (FP64 78.6 TF/s, BF16 2.5 PF/s)."""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    cases = [(1 << 20, 512, 1024, "f64"), (1 << 20, 512, 2048, "f64"), (1 << 20, 512, 4096, "f64"),
+             (1 << 21, 256, 1024, "f64"), (1 << 22, 1024, 4096, "bf16")]
+    if a.gauss_cases:
+        keep = {int(c) for c in a.gauss_cases.split(",")}
+        cases = [c for i, c in enumerate(cases) if i in keep]
+    ctx = lsq.Context()
+    g = torch.Generator(device="cuda").manual_seed(5)
+    for n, d, m, comp in cases:
+        dt = torch.float32 if comp == "bf16" else torch.float64
+        A = torch.randn((n, d), dtype=dt, device="cuda", generator=g)
+        y = torch.zeros(n, dtype=torch.float64, device="cuda")
+        SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+        desc = lsq.sketch_desc("gaussian", m, seed=7, compute=comp)
+        for _ in range(max(a.warmup, 1)):
+            ctx.sketch(A, y, desc, SA)
+        times = []
+        for _ in range(max(a.steps, 1)):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ctx.sketch(A, y, desc, SA)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.median(times))
+        terms = 3 if comp == "bf16" else 1
+        peak = 2500.0 if comp == "bf16" else 78.6
+        tf = terms * 2.0 * m * n * d / (ms * 1e-3) / 1e12
+        print(json.dumps({"sweep": "gauss", "n": n, "d": d, "m": m, "compute": comp, "ms": round(ms, 3),
+                          "mfma_tflops": round(tf, 1), "peak_tflops": peak, "frac": round(tf / peak, 4),
+                          "product_tflops": round(2.0 * m * n * d / (ms * 1e-3) / 1e12, 1)}), flush=True)
+        del A, y, SA
+        torch.cuda.empty_cache()
     ctx.close()
 
 
@@ -509,6 +556,9 @@ def main():
         return
     if a.sweep == "msize":
         sweep_msize(a)
+        return
+    if a.sweep == "gauss":
+        sweep_gauss(a)
         return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); multi-GPU sharding is not "

@@ -32,8 +32,10 @@
  *              targets per row; entries +-1/sqrt(s).
  *       GAUSS: S_ij (i < m, j < n) = g / sqrt(m), g from block (j >> 3, 3, t, i), word p = (j & 7) >> 1,
  *              a = low 32 bits, b = high 32 bits, u1 = (a + 1) 2^-32, u2 = b 2^-32,
- *              g = sqrt(-2 ln u1) cos(2 pi u2) for even j, sin(...) for odd j (Box-Muller, evaluated in
- *              single precision on the GPU).
+ *              g = sqrt(-2 ln u1) cos(2 pi u2) for even j, sin(...) for odd j (Box-Muller; the GPU
+ *              evaluates it in FP64 with 2 pi u2 rounded once, as the oracle does, for the FP64 sketch,
+ *              and in single precision with the hardware transcendentals for the BF16 form, whose
+ *              entries are rounded to BF16).
  */
 #ifndef LSQ_H
 #define LSQ_H
@@ -192,7 +194,7 @@ typedef struct {
  * (SJLT), a compute other than LSQ_F64 for Haar, lda < d, null pointers; UNSUPPORTED for d > 1024 or,
  * for Haar, m > min(1024, n/4) (the m x m Gram of the draws is factored once on the device, which keeps
  * the rows orthonormal to rounding while the n x m draws are well conditioned; the workspace holds the
- * draws in FP32); RANK if that Gram is not positive definite. */
+ * n x m draws in FP64); RANK if that Gram is not positive definite. */
 lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc, void* SA,
                       int64_t ldsa, int32_t sa_dtype);
 
@@ -291,14 +293,14 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* ctx, int32_t count, const lsq_problem*
  *                  increasing).  N must be a power of two.
  *   lsq_draw_sjlt: targets (device int32, n*s, row-major by row of A, in draw order) and signs
  *                  (device int8, n*s).
- *   lsq_draw_gaussian: g(i, j0 + c) for i < m, c < ncols into G (device FP32, m x ncols row-major),
- *                  unscaled standard normals. */
+ *   lsq_draw_gaussian: g(i, j0 + c) for i < m, c < ncols into G (device FP64, m x ncols row-major),
+ *                  unscaled standard normals as the FP64 sketch uses them. */
 lsq_status lsq_draw_srht(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t N, int64_t m, int8_t* signs,
                          int64_t* rows);
 lsq_status lsq_draw_sjlt(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t n, int64_t m, int32_t s,
                          int32_t* targets, int8_t* signs);
 lsq_status lsq_draw_gaussian(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
-                             int64_t ncols, float* G);
+                             int64_t ncols, double* G);
 
 /* Wall time (ms, HIP events on the context stream) of the last fused pass launched by the library,
  * and the average over all fused-pass launches since the last reset (for roofline reporting). */

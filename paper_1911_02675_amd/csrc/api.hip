@@ -259,7 +259,7 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     // Y = G_s A and Z = G_s g^T (the Gaussian sketch of the drawn n x m matrix g^T), so g A = sqrt(m) Y
     // and g g^T = sqrt(m) Z.
     const int64_t m = s->m, n = p->n, d = p->d, mp = cholqr_padded(m);
-    float* Gt;
+    double* Gt;
     double *Y, *Z, *W, *scr, *tscr, *part;
     CHK(wsT(c, "haar_gt", (size_t)n * m, &Gt));
     CHK(wsT(c, "haar_y", (size_t)m * d, &Y));
@@ -271,7 +271,7 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     CHK(wsT(c, "gauss_part", pb / sizeof(double) + 1, &part));
     launch_gauss_draw_t(st, s->seed, t, n, m, Gt);
     gauss_apply(st, s->seed, t, p->A, a_f32, n, d, p->lda, m, 0, part, Y, d);
-    gauss_apply(st, s->seed, t, Gt, 1, n, m, m, m, 0, part, Z, m);
+    gauss_apply(st, s->seed, t, Gt, 0, n, m, m, m, 0, part, Z, m);
     HIPCHK(hipMemsetAsync(c->dflags + 6, 0, sizeof(int), st));
     const double rm = sqrt((double)m);
     spd_chol_inverse(st, Z, m, rm, scr, W, c->dflags + 6, tscr);
@@ -1132,7 +1132,7 @@ lsq_status lsq_draw_sjlt(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t n, int64
 }
 
 lsq_status lsq_draw_gaussian(lsq_ctx* c, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
-                             int64_t ncols, float* G) {
+                             int64_t ncols, double* G) {
   if (!c || !G) return fail(LSQ_ERR_INVALID_ARG, "null argument");
   if (m < 1 || ncols < 1 || j0 < 0) return fail(LSQ_ERR_INVALID_ARG, "bad sizes");
   launch_gauss_draw(c->st, seed, t, m, j0, ncols, G);

@@ -18,11 +18,20 @@ struct u64x4 {
   uint64_t x, y, z, w;
 };
 
-__host__ __device__ __forceinline__ uint64_t mulhi64(uint64_t a, uint64_t b) {
+// The 128-bit product a b as (lo, hi).  On the device from four 32 x 32 + 64-bit multiply-adds on the
+// 32-bit halves (schoolbook), which yields both halves together.
+__host__ __device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t& lo, uint64_t& hi) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  return __umul64hi(a, b);
+  const uint64_t a0 = (uint32_t)a, a1 = a >> 32, b0 = (uint32_t)b, b1 = b >> 32;
+  const uint64_t t = a0 * b0;
+  const uint64_t u = a1 * b0 + (t >> 32);
+  const uint64_t v = a0 * b1 + (uint32_t)u;
+  hi = a1 * b1 + ((u >> 32) + (v >> 32));
+  lo = (v << 32) | (uint32_t)t;
 #else
-  return (uint64_t)(((unsigned __int128)a * b) >> 64);
+  const unsigned __int128 p = (unsigned __int128)a * b;
+  lo = (uint64_t)p;
+  hi = (uint64_t)(p >> 64);
 #endif
 }
 
@@ -36,8 +45,9 @@ __host__ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1
       k0 += W0;
       k1 += W1;
     }
-    const uint64_t lo0 = M0 * c0, hi0 = mulhi64(M0, c0);
-    const uint64_t lo1 = M1 * c2, hi1 = mulhi64(M1, c2);
+    uint64_t lo0, hi0, lo1, hi1;
+    mul128(M0, c0, lo0, hi0);
+    mul128(M1, c2, lo1, hi1);
     const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
     c0 = n0;
     c1 = lo1;
@@ -58,19 +68,52 @@ __device__ __forceinline__ bool sjlt_propose(uint64_t w, uint32_t m, uint32_t th
   return (uint32_t)P >= thr;
 }
 
-// Standard normal from one 64-bit word by Box-Muller in single precision: a = low 32 bits,
-// b = high 32 bits, u1 = (a + 1) 2^-32 in (0, 1], u2 = b 2^-32; cos branch for even columns, sin for odd.
-__device__ __forceinline__ float box_muller_f32(uint64_t w, int odd) {
+// sin x and cos x for 0 <= x <= 2 pi (+ a few ulp) in FP64: Cody-Waite reduction x = k pi/2 + r with
+// pi/2 split into three parts (33 + 33 + 53 bits, so k P1 and k P2 are exact for k <= 4 and x - k P1 is
+// exact), then the Taylor series of sin and cos on |r| <= pi/4 to degree 17 and 18 (truncation below
+// 1e-19), placed by the quadrant k mod 4.
+__device__ __forceinline__ void sincos_0_2pi(double x, double& sn, double& cs) {
+  const double P1 = 0x1.921fb54400000p+0, P2 = 0x1.0b4611a600000p-34, P3 = 0x1.3198a2e037073p-69;
+  const double k = rint(x * 0.63661977236758134);  // 2 / pi
+  double r = fma(-k, P1, x);
+  r = fma(-k, P2, r);
+  r = fma(-k, P3, r);
+  const double z = r * r;
+  double ps = -1.0 / 1307674368000.0 + z * (1.0 / 355687428096000.0);  // -1/15!, 1/17!
+  ps = fma(z, ps, 1.0 / 6227020800.0);
+  ps = fma(z, ps, -1.0 / 39916800.0);
+  ps = fma(z, ps, 1.0 / 362880.0);
+  ps = fma(z, ps, -1.0 / 5040.0);
+  ps = fma(z, ps, 1.0 / 120.0);
+  ps = fma(z, ps, -1.0 / 6.0);
+  const double s = fma(r * z, ps, r);
+  double pc = 1.0 / 20922789888000.0 + z * (-1.0 / 6402373705728000.0);  // 1/16!, -1/18!
+  pc = fma(z, pc, -1.0 / 87178291200.0);
+  pc = fma(z, pc, 1.0 / 479001600.0);
+  pc = fma(z, pc, -1.0 / 3628800.0);
+  pc = fma(z, pc, 1.0 / 40320.0);
+  pc = fma(z, pc, -1.0 / 720.0);
+  pc = fma(z, pc, 1.0 / 24.0);
+  pc = fma(z, pc, -0.5);
+  const double c = fma(z, pc, 1.0);
+  const int q = (int)k & 3;
+  sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
+  cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+}
+
+// Both standard normals of one 64-bit word by Box-Muller in FP64 (a = low 32 bits, b = high 32 bits):
+// u1 = (a + 1) 2^-32 in (0, 1] and u2 = b 2^-32 are exact, r = sqrt(-2 ln u1), the angle 2 pi u2 is
+// rounded to FP64 once, c = r cos(angle) (even columns), s = r sin(angle) (odd columns); log and sqrt are
+// the device library's FP64 functions, sin and cos the reduction above.
+__device__ __forceinline__ void box_muller_pair_f64(uint64_t w, double& c, double& s) {
   const uint32_t a = (uint32_t)w, b = (uint32_t)(w >> 32);
-  // ln u1 with u1 = (a + 1) 2^-32: for u1 >= 1/2 use log1p(-(1 - u1)) with 1 - u1 = (~a) 2^-32
-  // exact as an integer, so small radii keep their absolute accuracy.
-  const float lnu1 = (a >= 0x80000000u) ? log1pf(-(float)(~a) * 2.3283064365386963e-10f)
-                                        : logf(((float)a + 1.0f) * 2.3283064365386963e-10f);
-  const float u2 = (float)b * 2.3283064365386963e-10f;
-  const float r = sqrtf(-2.0f * lnu1);
-  float sn, cs;
-  sincospif(2.0f * u2, &sn, &cs);
-  return odd ? r * sn : r * cs;
+  const double u1 = ((double)a + 1.0) * 0x1p-32;
+  const double u2 = (double)b * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u1));
+  double sn, cs;
+  sincos_0_2pi(2.0 * 3.141592653589793 * u2, sn, cs);
+  c = r * cs;
+  s = r * sn;
 }
 
 // ---------------------------------------------------------------------------------------------------

@@ -257,45 +257,49 @@ void launch_sjlt_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int6
 }
 
 // ------------------------------------------------------------------------------------------------
-// Gaussian entries (unscaled standard normals), one thread per entry: for the bit-level checks.
+// Gaussian entries (unscaled standard normals, FP64, the values of the FP64 sketch), one thread per
+// entry: for the parity checks of the draws.
 // ------------------------------------------------------------------------------------------------
 __global__ void k_gauss_draw(uint64_t seed, uint64_t t, int64_t m, int64_t j0, int64_t ncols,
-                             float* __restrict__ G) {
+                             double* __restrict__ G) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= m * ncols) return;
   const int64_t i = idx / ncols, c = idx % ncols, j = j0 + c;
   const u64x4 w = philox4x64_10((uint64_t)(j >> 3), TAG_GAUSS, t, (uint64_t)i, seed, 0);
   const int q = (int)(j & 7), p = q >> 1;
   const uint64_t word = p == 0 ? w.x : p == 1 ? w.y : p == 2 ? w.z : w.w;
-  G[idx] = box_muller_f32(word, q & 1);
+  double cs, sn;
+  box_muller_pair_f64(word, cs, sn);
+  G[idx] = (q & 1) ? sn : cs;
 }
 
 // The Gaussian embedding's standard normals transposed: Gt[j m + i] = g(i, j), j < n, i < m (the n x m
-// matrix whose columns are the rows of the unscaled embedding).  One thread per (i, 8 consecutive j):
-// one Philox block gives the 8 values; consecutive threads write consecutive i.
-__global__ void k_gauss_draw_t(uint64_t seed, uint64_t t, int64_t n, int64_t m, float* __restrict__ Gt) {
+// matrix whose columns are the rows of the unscaled embedding), FP64 as in the FP64 sketch.  One thread
+// per (i, 8 consecutive j): one Philox block gives the 8 values; consecutive threads write consecutive i.
+__global__ void k_gauss_draw_t(uint64_t seed, uint64_t t, int64_t n, int64_t m, double* __restrict__ Gt) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t nb = (n + 7) / 8;
   if (idx >= nb * m) return;
   const int64_t i = idx % m, jb = idx / m;
   const u64x4 w = philox4x64_10((uint64_t)jb, TAG_GAUSS, t, (uint64_t)i, seed, 0);
+  const uint64_t ws[4] = {w.x, w.y, w.z, w.w};
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int64_t j = 8 * jb + q;
-    if (j >= n) break;
-    const int p = q >> 1;
-    const uint64_t word = p == 0 ? w.x : p == 1 ? w.y : p == 2 ? w.z : w.w;
-    Gt[j * m + i] = box_muller_f32(word, q & 1);
+  for (int p = 0; p < 4; ++p) {
+    double cs, sn;
+    box_muller_pair_f64(ws[p], cs, sn);
+    const int64_t j = 8 * jb + 2 * p;
+    if (j < n) Gt[j * m + i] = cs;
+    if (j + 1 < n) Gt[(j + 1) * m + i] = sn;
   }
 }
 
-void launch_gauss_draw_t(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, float* Gt) {
+void launch_gauss_draw_t(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, double* Gt) {
   const int64_t tot = (n + 7) / 8 * m;
   hipLaunchKernelGGL(k_gauss_draw_t, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, seed, t, n, m, Gt);
 }
 
 void launch_gauss_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
-                       int64_t ncols, float* G) {
+                       int64_t ncols, double* G) {
   const int64_t tot = m * ncols;
   hipLaunchKernelGGL(k_gauss_draw, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, seed, t,
                      m, j0, ncols, G);

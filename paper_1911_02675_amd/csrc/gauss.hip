@@ -1,67 +1,11 @@
 // Gaussian sketch S A with S_ij = g(i, j) / sqrt(m), g standard normal from the counter-based
 // specification (Section 2: i.i.d. N(0, 1/m) entries).  S is never stored: every workgroup generates
-// its block of S in LDS from Philox words and multiplies it with a tile of A.  The reduction over the
-// long dimension n is split across workgroups (partials), then summed in a fixed order.
+// its block of S in registers from Philox words and multiplies it with a tile of A on the matrix cores.
+// The reduction over the long dimension n is split across workgroups (partials), then summed in a fixed
+// order.
 #include "internal.h"
 
 namespace lsq {
-
-constexpr int GT_M = 64, GT_D = 64, GT_K = 32;
-
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gauss_tile(uint64_t seed, uint64_t t, const TA* __restrict__ A,
-                                                    int64_t n, int64_t d, int64_t lda, int64_t m,
-                                                    int64_t kchunk, double* __restrict__ part) {
-  __shared__ double Gs[GT_M][GT_K + 1];
-  __shared__ double As[GT_K][GT_D + 1];
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int64_t i0 = (int64_t)blockIdx.x * GT_M, c0 = (int64_t)blockIdx.y * GT_D;
-  const int64_t k0 = (int64_t)blockIdx.z * kchunk, k1 = min(n, k0 + kchunk);
-  double acc[4][4] = {};
-  for (int64_t kb = k0; kb < k1; kb += GT_K) {
-    __syncthreads();
-    {
-      // 64 rows x 32 columns of S: one Philox block (8 normals) per thread
-      const int gi = tid >> 2, gq = (tid & 3) * 8;
-      const int64_t i = i0 + gi, jb = kb + gq;
-      const u64x4 w = philox4x64_10((uint64_t)(jb >> 3), TAG_GAUSS, t, (uint64_t)i, seed, 0);
-      const uint64_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int64_t j = jb + q;
-        Gs[gi][gq + q] = (i < m && j < k1) ? (double)box_muller_f32(ws[q >> 1], q & 1) : 0.0;
-      }
-    }
-    for (int idx = tid; idx < GT_K * GT_D; idx += 256) {
-      const int kk = idx / GT_D, cc = idx % GT_D;
-      const int64_t j = kb + kk, col = c0 + cc;
-      As[kk][cc] = (j < k1 && col < d) ? (double)A[j * lda + col] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int kk = 0; kk < GT_K; ++kk) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        a[u] = Gs[ty * 4 + u][kk];
-        b[u] = As[kk][tx * 4 + u];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(a[u], b[v], acc[u][v]);
-    }
-  }
-  double* out = part + (int64_t)blockIdx.z * m * d;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t i = i0 + ty * 4 + u, col = c0 + tx * 4 + v;
-      if (i < m && col < d) out[i * d + col] = acc[u][v];
-    }
-}
 
 __global__ void k_gauss_reduce(const double* __restrict__ part, int64_t nks, int64_t m, int64_t d,
                                double scale, double* __restrict__ SA, int64_t ldsa) {
@@ -74,17 +18,75 @@ __global__ void k_gauss_reduce(const double* __restrict__ part, int64_t nks, int
 }
 
 // --------------------------------------------------------------------------------------------------
-// Matrix-core version (v_mfma_f64_16x16x4f64).  Workgroup: 8 wavefronts, 128 rows of S A (16 per
-// wavefront) x 256 columns (16 blocks of 16), over a range of rows of A split across workgroups.
-// Per step of 8 rows of A: the 8 x 256 tile of A is staged in LDS (shared by all wavefronts) and
-// each lane (row i = l % 16 of its wavefront, k offset kk = l / 16) evaluates one Philox block
-// (8 consecutive entries of row i of S) and keeps the two entries it feeds to the matrix cores,
-// j0 + kk and j0 + kk + 4.  Operand layouts: A operand lane l = S[l % 16][kk], B operand lane l =
-// A[kk][l % 16]; result lane l, register v = (row l / 16 + 4 v, column l % 16).
+// FP64 form on the matrix cores (v_mfma_f64_16x16x4f64).  Workgroup: 8 wavefronts, 128 rows of S A (16
+// per wavefront) x 256 columns (16 blocks of 16), over a range of rows of A split across workgroups.
+// Per step of 32 rows of A (columns kb .. kb + 31 of S): the 32 x 256 tile of A is staged in LDS (double
+// buffered: the next tile is loaded and stored into the other buffer after this step's MFMAs have
+// issued) and shared by all wavefronts.  Lane l (row il = l % 16
+// of its wavefront's S rows, group h = l / 16) evaluates the one Philox block of columns kb + 8 h .. + 7 of
+// row il and its four Box-Muller pairs (FP64): e[p] = S[il][kb + 8 h + p].  Two 4 x 4 transposes across
+// the four 16-lane rows of the wavefront (two rounds of row swaps each), of e[0..3] and of e[4..7], leave
+// in lane (il, kk) the A operands of the eight substeps: S[il][kb + 8 q + kk] (substep 2 q) and
+// S[il][kb + 8 q + 4 + kk] (substep 2 q + 1).  B operand lane l = A[kb + 4 s + l / 16][l % 16]; result
+// lane l, register v = (row l / 16 + 4 v, column l % 16).  The next step's normals are formed while this
+// step's MFMAs issue.
 // --------------------------------------------------------------------------------------------------
 typedef double g_d4 __attribute__((ext_vector_type(4)));
-constexpr int GM_WAVES = 8, GM_ROWS = GM_WAVES * 16, GM_BLK = 16, GM_COLS = GM_BLK * 16, GM_K = 8;
-constexpr int GM_LDS_STRIDE = GM_COLS + 16;  // 272 doubles: the 4 k-rows of one read hit different banks
+constexpr int GM_WAVES = 8, GM_ROWS = GM_WAVES * 16, GM_BLK = 16, GM_COLS = GM_BLK * 16, GM_K = 32;
+constexpr int GM_LDS_STRIDE = GM_COLS + 16;  // 272 doubles: the 4 k-rows of one read fall in different banks
+constexpr int GM_LROWS = GM_K / GM_WAVES;  // rows of the tile per loading thread (4)
+
+// Exchange of one double between the 16-lane rows of a wavefront: rows (0, 1) and (2, 3) swap
+// (x's odd rows with y's even rows) for XOR = 1; the wave halves swap (x's upper half with y's lower
+// half) for XOR = 2.
+template <int XOR>
+__device__ __forceinline__ void row_swap(double& x, double& y) {
+  const uint32_t xl = (uint32_t)__double2loint(x), xh = (uint32_t)__double2hiint(x);
+  const uint32_t yl = (uint32_t)__double2loint(y), yh = (uint32_t)__double2hiint(y);
+  if constexpr (XOR == 1) {
+    const auto l = __builtin_amdgcn_permlane16_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(xh, yh, false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(xl, yl, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(xh, yh, false, false);
+    x = __hiloint2double((int)h[0], (int)l[0]);
+    y = __hiloint2double((int)h[1], (int)l[1]);
+  }
+}
+
+// 4 x 4 transpose over (16-lane row h, element j) of e[0..3]: afterwards e[j] holds row j's former e[h].
+// Swaps the low bits of row and element, then the high bits.  All 64 lanes must be active.
+__device__ __forceinline__ void rows_transpose4(double& e0, double& e1, double& e2, double& e3) {
+  row_swap<1>(e0, e1);
+  row_swap<1>(e2, e3);
+  row_swap<2>(e0, e2);
+  row_swap<2>(e1, e3);
+}
+
+// The eight A operands of one step for lane (il, kk): g[s] = S[il][kb + 4 s + kk], s < 8 (see above).
+__device__ __forceinline__ void gauss_step_operands(uint64_t seed, uint64_t t, int64_t irow, bool iok, int64_t kb,
+                                                    int h, double (&g)[8]) {
+  double e[8];
+  if (iok) {
+    const u64x4 w = philox4x64_10((uint64_t)((kb >> 3) + h), TAG_GAUSS, t, (uint64_t)irow, seed, 0);
+    box_muller_pair_f64(w.x, e[0], e[1]);
+    box_muller_pair_f64(w.y, e[2], e[3]);
+    box_muller_pair_f64(w.z, e[4], e[5]);
+    box_muller_pair_f64(w.w, e[6], e[7]);
+  } else {
+#pragma unroll
+    for (int p = 0; p < 8; ++p) e[p] = 0.0;
+  }
+  rows_transpose4(e[0], e[1], e[2], e[3]);  // e[q] = S[il][kb + 8 q + kk]
+  rows_transpose4(e[4], e[5], e[6], e[7]);  // e[4 + q] = S[il][kb + 8 q + 4 + kk]
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    g[2 * q] = e[q];
+    g[2 * q + 1] = e[4 + q];
+  }
+}
 
 template <typename TA>
 __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uint64_t t,
@@ -97,46 +99,64 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uin
   const int64_t i0 = (int64_t)blockIdx.x * GM_ROWS;
   const int64_t c0 = (int64_t)blockIdx.y * GM_COLS;
   const int64_t k0 = (int64_t)blockIdx.z * kchunk, k1 = min(n, k0 + kchunk);
-  const int64_t irow = i0 + wv * 16 + il;       // row of S this lane generates
+  const int64_t irow = i0 + wv * 16 + il;  // row of S whose entries this lane generates
   const bool iok = irow < m;
   g_d4 acc[GM_BLK];
 #pragma unroll
   for (int b = 0; b < GM_BLK; ++b) acc[b] = (g_d4){0.0, 0.0, 0.0, 0.0};
-  // tile loader: thread -> (row tid / 64, 4 consecutive columns)
+  // tile loader: thread -> rows tid / 64 + 8 q (q < 4), 4 consecutive columns (64 x 4 = 256)
   const int lr = tid >> 6, lc = (tid & 63) * 4;
-  auto load_tile = [&](int64_t kb, double (&v)[4]) {
-    const int64_t row = kb + lr;
+  auto load_tile = [&](int64_t kb, double (&v)[GM_LROWS][4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int64_t col = c0 + lc + u;
-      v[u] = (row < k1 && col < d) ? (double)A[row * lda + col] : 0.0;
+    for (int q = 0; q < GM_LROWS; ++q) {
+      const int64_t row = kb + lr + 8 * q;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t col = c0 + lc + u;
+        v[q][u] = (row < k1 && col < d) ? (double)A[row * lda + col] : 0.0;
+      }
     }
   };
-  double nv[4];
-  if (k0 < k1) load_tile(k0, nv);
-  int buf = 0;
-  for (int64_t kb = k0; kb < k1; kb += GM_K) {
+  auto store_tile = [&](int buf, const double (&v)[GM_LROWS][4]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) As[buf][lr * GM_LDS_STRIDE + lc + u] = nv[u];
-    __syncthreads();
-    if (kb + GM_K < k1) load_tile(kb + GM_K, nv);  // next tile in flight during this step
-    // the two entries of row irow of S used by this lane in this step
-    double g0 = 0.0, g1 = 0.0;
-    if (iok) {
-      const u64x4 w = philox4x64_10((uint64_t)(kb >> 3), TAG_GAUSS, t, (uint64_t)irow, seed, 0);
-      const uint64_t w0 = (kk >> 1) == 0 ? w.x : w.y;          // word of entry kk
-      const uint64_t w1 = (kk >> 1) == 0 ? w.z : w.w;          // word of entry kk + 4
-      const double sc = 1.0;
-      g0 = (kb + kk < k1) ? sc * (double)box_muller_f32(w0, kk & 1) : 0.0;
-      g1 = (kb + kk + 4 < k1) ? sc * (double)box_muller_f32(w1, kk & 1) : 0.0;
+    for (int q = 0; q < GM_LROWS; ++q)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) As[buf][(lr + 8 * q) * GM_LDS_STRIDE + lc + u] = v[q][u];
+  };
+  if (k0 < k1) {
+    {
+      double nv[GM_LROWS][4];
+      load_tile(k0, nv);
+      store_tile(0, nv);
     }
-    const double* T0 = &As[buf][kk * GM_LDS_STRIDE];
-    const double* T1 = &As[buf][(kk + 4) * GM_LDS_STRIDE];
+    double g[8];
+    gauss_step_operands(seed, t, irow, iok, k0, kk, g);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t kb = k0; kb < k1; kb += GM_K) {
+      const bool more = kb + GM_K < k1;
+      // the next step's operands (past the range at the last step: computed and dropped), in the same
+      // block as this step's MFMAs so that the two interleave
+      double gn[8];
+      gauss_step_operands(seed, t, irow, iok, kb + GM_K, kk, gn);
 #pragma unroll
-    for (int b = 0; b < GM_BLK; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g0, T0[b * 16 + il], acc[b], 0, 0, 0);
+      for (int s = 0; s < 8; ++s) {
+        const double* T = &As[buf][(4 * s + kk) * GM_LDS_STRIDE + il];
 #pragma unroll
-    for (int b = 0; b < GM_BLK; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g1, T1[b * 16 + il], acc[b], 0, 0, 0);
-    buf ^= 1;
+        for (int b = 0; b < GM_BLK; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[s], T[b * 16], acc[b], 0, 0, 0);
+      }
+#pragma unroll
+      for (int s = 0; s < 8; ++s) g[s] = gn[s];
+      if (more) {
+        // the next tile into the other buffer (its last readers passed the previous barrier); the other
+        // wavefront of the SIMD keeps the matrix core busy while these loads are in flight
+        double nv[GM_LROWS][4];
+        load_tile(kb + GM_K, nv);
+        store_tile(buf ^ 1, nv);
+      }
+      __syncthreads();
+      buf ^= 1;
+    }
   }
   double* out = part + (int64_t)blockIdx.z * m * d;
 #pragma unroll
@@ -337,7 +357,7 @@ void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a
                        nks, m, d, 1.0 / sqrt((double)m), SA, ldsa);
     return;
   }
-  kchunk = (kchunk + GM_K - 1) / GM_K * GM_K;  // multiple of 8: Philox blocks never straddle chunks
+  kchunk = (kchunk + GM_K - 1) / GM_K * GM_K;  // multiple of 32: whole steps, Philox blocks never straddle chunks
   if (a_f32)
     hipLaunchKernelGGL(k_gauss_mfma<float>, g, dim3(GM_WAVES * 64), 0, st, seed, t, (const float*)A, n, d,
                        lda, m, kchunk, partials);

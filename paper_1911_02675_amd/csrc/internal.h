@@ -25,9 +25,9 @@ void srht_select(hipStream_t st, const uint64_t* keys, int64_t N, int64_t m, int
 void launch_sjlt_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, int s,
                       int32_t* targets, int8_t* signs, int* err);
 void launch_gauss_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t m, int64_t j0,
-                       int64_t ncols, float* G);
+                       int64_t ncols, double* G);
 // Gt (n x m, row-major FP32) = the unscaled normals transposed, Gt[j m + i] = g(i, j).
-void launch_gauss_draw_t(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, float* Gt);
+void launch_gauss_draw_t(hipStream_t st, uint64_t seed, uint64_t t, int64_t n, int64_t m, double* Gt);
 // Exclusive prefix sum of len int32 values; tmp needs scan_tmp_len(len) ints.
 size_t scan_tmp_len(int64_t len);
 void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, int* tmp);

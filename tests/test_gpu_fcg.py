@@ -2,10 +2,9 @@
 library through its C ABI against the CPU oracle on the same draws, iterate by iterate through the
 exact-error trace, plus edge cases and properties that hold at any size.
 
-Tolerances: the SRHT and SJLT sketches are FP64 on both sides, so iterates agree to the rounding of
-the factorizations and passes (relative A-norm difference 1e-10 of ||A x*||); the Gaussian entries
-are single-precision values on the GPU (about 1e-6 absolute), which perturbs each preconditioner at
-that level (1e-5)."""
+Tolerances: every sketch is FP64 on both sides (the Gaussian normals within a few ulp of the
+oracle's), so iterates agree to the rounding of the factorizations and passes (relative A-norm
+difference 1e-10 of ||A x*||)."""
 import sys
 
 import numpy as np
@@ -71,7 +70,7 @@ def test_fcg_iterates(ctx, kind, n, d, m, window, refresh, T):
     assert info.iters == T
     scale = np.linalg.norm(A @ xs)
     diff = np.linalg.norm(A @ (host(x) - its[-1])) / scale
-    tol = 1e-5 if kind == "gaussian" else 1e-10
+    tol = 1e-10
     e_or = np.array([np.linalg.norm(A @ (xt - xs)) / scale for xt in its])
     e_gpu = host(trace)
     say("  diff", diff, "final error", e_or[-1], "gpu", e_gpu[-1])

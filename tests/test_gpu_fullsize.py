@@ -95,8 +95,8 @@ def test_fullsize_gaussian_rows(big, compute):
         prod = (np.abs(g) @ np.abs(A[:, COLS])) / np.sqrt(M)
         maxterm = np.abs(g).max() * np.abs(A[:, COLS]).max(axis=0) / np.sqrt(M)
         if compute == "f64":
-            # single-precision normals (<= 8e-6 absolute each) and FP64 sums
-            bound = 8e-6 * (np.abs(A[:, COLS]).sum(axis=0) / np.sqrt(M)) + 64 * EPS64 * prod
+            # FP64 normals within a few ulp of the oracle's and FP64 sums in any order
+            bound = 80 * EPS64 * prod
         else:
             # FP32 chains of 256 rows folded into FP64, the three-term split, and a few BF16 rounding
             # flips of normals whose single- and double-precision values straddle a rounding boundary

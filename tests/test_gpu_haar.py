@@ -1,9 +1,10 @@
 """Haar embedding on the GPU (S = Q^T of the positive-diagonal QR of the Gaussian draws, formed as
 R^{-T} (g A)) against the oracle (numpy QR of the same counter-based draws).
 
-The device's normals are single-precision values, so S differs from the oracle's at that level; the
-orthonormality of the rows is checked on the device result directly (A = I gives S A = S), independently
-of the draws."""
+The device's normals are FP64 values within a few ulp of the oracle's, so S differs from the oracle's by
+the rounding of the two factorizations (Cholesky of g g^T on the device, Householder QR of g^T in the
+oracle), about m u kappa(g)^2 with kappa(g) <= 3 here; the orthonormality of the rows is checked on the
+device result directly (A = I gives S A = S), independently of the draws."""
 import math
 import sys
 
@@ -58,9 +59,9 @@ def test_haar_sketch_parity(ctx, n, d, m):
     A = np.random.default_rng(n + d).standard_normal((n, d))
     got = _sa(ctx, A, m, seed=21, t=2)
     ref = sketch.haar_sketch(A, m, 21, 2)
-    # the device normals are single-precision values (within a few units of 2^-24 of the oracle's), and
-    # S ~ g / sqrt(n); the second term is the FP64 rounding of the products and of the factorization
-    bound = 1e-7 / math.sqrt(n) * np.abs(A).sum(axis=0)[None, :] + 1e-12 * np.linalg.norm(A, axis=0)[None, :]
+    # S ~ g / sqrt(n): the FP64 rounding of the products and of the factorizations, m u kappa(g)^2 per
+    # entry of S, summed over the column of A
+    bound = 64 * m * EPS * (np.abs(A).sum(axis=0)[None, :] / math.sqrt(n) + np.linalg.norm(A, axis=0)[None, :])
     r = np.max(np.abs(got - ref) / bound)
     say("  max err / bound", r)
     assert r <= 1.0
@@ -109,4 +110,4 @@ def test_haar_pcg_and_refreshed_ihs(ctx):
     xo = its[-1]
     diff = a_norm_error(A, x.cpu().numpy(), xo) * np.linalg.norm(A @ xo) / np.linalg.norm(A @ xs)
     say("  haar ihs: diff", diff, "err", a_norm_error(A, xo, xs))
-    assert diff <= 1e-7
+    assert diff <= 1e-10
