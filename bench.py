@@ -137,14 +137,14 @@ def sweep_gauss(a):
     """The Gaussian sketch alone (counter-based normals fused into the matrix-core GEMM) at the shapes of
     the workloads that use it: n = 2^20, d = 512, m in {2d, 4d, 8d} (FP64, plain form), n = 2^21, d = 256,
     m = 4d (FP64, refreshed IHS), n = 2^22, d = 1024, m = 4d (BF16 S times a three-term BF16 split of
-    FP32 A, the precision form).  Time per sketch from torch events on the library's stream (median of
+    FP32 A, the precision form; and the FP64 form on FP64 A at that shape).  Time per sketch from torch events on the library's stream (median of
     `steps` after `warmup`), matrix-core work 2 m n d (x 3 split terms for BF16) against the dense peak
     (FP64 78.6 TF/s, BF16 2.5 PF/s)."""
     import torch
 
     from paper_1911_02675_amd import lsq
     cases = [(1 << 20, 512, 1024, "f64"), (1 << 20, 512, 2048, "f64"), (1 << 20, 512, 4096, "f64"),
-             (1 << 21, 256, 1024, "f64"), (1 << 22, 1024, 4096, "bf16")]
+             (1 << 21, 256, 1024, "f64"), (1 << 22, 1024, 4096, "bf16"), (1 << 22, 1024, 4096, "f64")]
     if a.gauss_cases:
         keep = {int(c) for c in a.gauss_cases.split(",")}
         cases = [c for i, c in enumerate(cases) if i in keep]
@@ -510,36 +510,90 @@ def host_np(t):
     return t.cpu().numpy()
 
 
-def cpu_baseline(A64, y64, m, kind, s, seed, iters, rows=1 << 16):
-    """The CPU oracle as it stands, on a bounded sample of the same workload: its sketch of the first
-    `rows` rows (scaled linearly to n), its Householder QR of the m x d sketch, and one of its PCG
-    iterations on the full matrix (times the GPU's iteration count)."""
-    from threadpoolctl import threadpool_info
+def host_description():
+    """CPU model, logical CPUs visible to this process, and RAM of the host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    ram = None
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal:"):
+                ram = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": len(os.sched_getaffinity(0)), "ram_gib": ram}
+
+
+def cpu_baseline(A64, m, kind, s, seed, iters, sketch_rows=1 << 16, qr_rows=4096, pass_rows=1 << 19):
+    """The CPU oracle as it stands, timed on bounded samples of the workload and scaled by each step's own
+    cost law, once with one BLAS thread and once with all of them:
+      sketch  the oracle's SRHT of the first `sketch_rows` rows (a full transform of that length, then
+              the m selected rows), scaled by N log2 N (N = the padded length);
+      factor  the oracle's Householder QR of the first `qr_rows` rows of that sketch, scaled by the flop
+              count 2 m d^2 - 2 d^3 / 3;
+      pass    one oracle PCG step (A p, A^T q, the triangular solves) on the first `pass_rows` rows,
+              scaled linearly to n, times the GPU solve's passes (its iterations + the first gradient).
+    Gaussian and SJLT sketches are scaled linearly in n."""
+    from threadpoolctl import threadpool_info, threadpool_limits
 
     from oracle import householder, sketch
     from oracle.pcg import apply_hs_inv
 
     n, d = A64.shape
-    rows = min(n, rows)
-    t0 = time.perf_counter()
-    SA = sketch.sketch(A64[:rows], kind, m, seed, 0, s)
-    t_sk = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    R = householder.householder_qr(SA)
-    t_qr = time.perf_counter() - t0
+    N = 1
+    while N < n:
+        N *= 2
+    rs = min(n, sketch_rows)
+    Ns = 1
+    while Ns < rs:
+        Ns *= 2
+    ms = min(m, Ns)
+    sk_scale = (N * np.log2(N)) / (Ns * np.log2(Ns)) if kind == "srht" else n / rs
+    sk_scale *= m / ms
+    qr_m = min(qr_rows, ms)
+    flops = lambda mm: 2.0 * mm * d * d - 2.0 * d ** 3 / 3.0
+    qr_scale = flops(m) / flops(qr_m)
+    pr = min(n, pass_rows)
     p = np.random.default_rng(0).standard_normal(d)
-    t0 = time.perf_counter()
-    q = A64 @ p
-    Hp = A64.T @ q
-    rhat = apply_hs_inv(R, Hp)
-    t_it = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        SA = sketch.sketch(A64[:rs], kind, ms, seed, 0, s)
+        t_sk = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        R = householder.householder_qr(SA[:qr_m])
+        t_qr = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        q = A64[:pr] @ p
+        Hp = A64[:pr].T @ q
+        apply_hs_inv(R, Hp)
+        t_it = time.perf_counter() - t0
+        comp = {"sketch_s": t_sk * sk_scale, "factor_s": t_qr * qr_scale, "pass_s": t_it * n / pr}
+        total = comp["sketch_s"] + comp["factor_s"] + (iters + 1) * comp["pass_s"]
+        return total, comp, t_sk + t_qr + t_it
+
     threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    total = t_sk * (n / rows) + t_qr + iters * t_it
+    with threadpool_limits(limits=1):
+        one, comp1, spent1 = run()
+    allc, compa, spenta = run()
+    rnd = lambda c: {k: round(v, 3) for k, v in c.items()}
     return {
-        "value": round(total, 3), "unit": "s", "cores": threads, "kind": "oracle",
-        "sample": (f"oracle {kind} sketch of the first {rows} rows ({t_sk:.2f} s, scaled x{n / rows:.0f}), "
-                   f"its Householder QR of the {m}x{d} sketch ({t_qr:.2f} s), one oracle PCG iteration "
-                   f"on the full {n}x{d} FP64 matrix ({t_it:.2f} s) x {iters} iterations"),
+        "value": round(allc, 3), "unit": "s", "cores": threads, "kind": "oracle",
+        "sample": (f"oracle {kind} sketch of the first {rs} rows with m={ms} (scaled x{sk_scale:.0f}: "
+                   f"{'N log N' if kind == 'srht' else 'n'}{' and m' if ms < m else ''}), its Householder QR of the first {qr_m} "
+                   f"rows of that sketch (scaled x{qr_scale:.1f} by 2md^2 - 2d^3/3 to m={m}), one oracle PCG "
+                   f"step on the first {pr} rows (scaled x{n / pr:.0f}) times {iters + 1} passes; "
+                   f"{spenta:.1f} s of CPU time on {threads} threads, {spent1:.1f} s on one"),
+        "components_s": rnd(compa),
+        "single_thread": {"value": round(one, 3), "cores": 1, "components_s": rnd(comp1)},
+        "host": host_description(),
     }
 
 
@@ -654,6 +708,9 @@ def main():
             f"refine={info.refinements} sketch={info.t_sketch_ms:.1f} factor={info.t_factor_ms:.1f} "
             f"iter={info.t_iter_ms:.1f} ms  fused {fused_ms:.3f} ms/launch "
             f"({res[form]['fused_gbs']:.0f} GB/s)")
+    # the measured read ceiling over the largest operand (the bare streaming read of lsq_read_bandwidth)
+    read_peak = ctx.read_bandwidth(A32 if A32 is not None else A64, reps=3)
+    log(f"[bench] measured read ceiling {read_peak:.0f} GB/s")
     ctx.close()
 
     head = "mixed" if "mixed" in res else forms[0]
@@ -661,8 +718,8 @@ def main():
     cpu = None
     if not a.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
-        cpu = cpu_baseline(P["A64"], P["y64"], m_form[head], a.sketch, a.s, a.seed, h["info"]["iters"],
-                           a.cpu_sample_rows)
+        cpu = cpu_baseline(P["A64"], m_form[head], a.sketch, a.s, a.seed, h["info"]["iters"],
+                           sketch_rows=a.cpu_sample_rows)
     out = {
         "metric": "time-to-solve (s) + HBM GB/s, n=2^22 d=1024 to 1e-10; mixed vs FP64",
         "value": round(h["s"], 5),
@@ -702,6 +759,8 @@ def main():
                      "unit": "GB/s", "frac": round(h["fused_gbs"] / HBM_PEAK_GBS, 4),
                      "traffic": counter_traffic(a.n, a.d, head,
                                                 tuned.get(head, {}).get("fused_groups_per_cu", 8)),
+                     "measured_read_peak": round(read_peak, 1),
+                     "frac_of_measured": round(h["fused_gbs"] / read_peak, 4),
                      "kernel": "k_fused (A^T(A p), one pass)",
                      "bytes_per_launch": h["bytes_per_pass"], "avg_launch_ms": round(h["fused_ms"], 4),
                      "launches": h["launches"]},

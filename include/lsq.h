@@ -307,6 +307,15 @@ lsq_status lsq_draw_gaussian(lsq_ctx* ctx, uint64_t seed, uint64_t t, int64_t m,
 lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, double* avg_ms,
                                  int64_t* launches);
 
+/* Measured read ceiling of the device memory, the reference the streaming kernels' achieved bandwidth is
+ * compared with beside the datasheet peak: the whole 16-byte vectors of buf (device, 16-byte aligned,
+ * `bytes` long) are read `reps` times by a bare streaming-read kernel (the fused pass's 16-byte
+ * non-temporal loads, no arithmetic beyond a running sum) at 4, 8 and 16 workgroups per compute unit;
+ * *gbs (host) receives the best rate in GB/s (1e9 bytes per second), timed with HIP events on the
+ * context's stream.  Synchronous.  INVALID_ARG for null pointers, bytes < 16, reps < 1 or a misaligned
+ * buffer. */
+lsq_status lsq_read_bandwidth(lsq_ctx* ctx, const void* buf, int64_t bytes, int32_t reps, double* gbs);
+
 /* Process-wide launch parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
  * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
  * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);

@@ -55,6 +55,13 @@ def build(jobs=None, verbose=False):
                        capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr[-20000:]}")
+    # a kernel whose host stub was not emitted links but cannot be loaded: refuse such a library
+    nm = shutil.which("nm") or "/usr/bin/nm"
+    r = subprocess.run([nm, "-u", tmp], capture_output=True, text=True)
+    missing = [ln.split()[-1] for ln in r.stdout.splitlines() if "__device_stub__" in ln]
+    if missing:
+        os.remove(tmp)
+        raise RuntimeError("kernel host stubs missing from the link: " + ", ".join(missing[:8]))
     os.replace(tmp, LIB)
     return LIB
 

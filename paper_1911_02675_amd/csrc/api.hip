@@ -638,6 +638,32 @@ lsq_status lsq_fused_pass_noalloc(lsq_ctx* c, const lsq_problem* p, int32_t mode
   return LSQ_OK;
 }
 
+lsq_status lsq_read_bandwidth(lsq_ctx* c, const void* buf, int64_t bytes, int32_t reps, double* gbs) {
+  if (!c || !buf || !gbs) return fail(LSQ_ERR_INVALID_ARG, "null context, buffer or output");
+  if (bytes < 16 || reps < 1) return fail(LSQ_ERR_INVALID_ARG, "need bytes >= 16 and reps >= 1");
+  if ((uintptr_t)buf % 16) return fail(LSQ_ERR_INVALID_ARG, "buffer must be 16-byte aligned");
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev));
+  double best = 0.0;
+  for (int gpc : {4, 8, 16}) {
+    const int groups = std::max(cus, 1) * gpc;
+    float* out;
+    CHK(wsT(c, "read_probe", (size_t)groups, &out));
+    stream_read(c->st, buf, bytes, groups, out);  // warm-up
+    HIPCHK(hipEventRecord(c->ev[4], c->st));
+    for (int r = 0; r < reps; ++r) stream_read(c->st, buf, bytes, groups, out);
+    HIPCHK(hipEventRecord(c->ev[5], c->st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(c->ev[5]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+    const double rate = (double)(bytes / 16 * 16) * reps / (ms * 1e-3) / 1e9;
+    best = std::max(best, rate);
+  }
+  *gbs = best;
+  return LSQ_OK;
+}
+
 lsq_status lsq_fused_pass_timing(lsq_ctx* c, int32_t reset, double* last_ms, double* avg_ms,
                                  int64_t* launches) {
   if (!c) return fail(LSQ_ERR_INVALID_ARG, "null context");

@@ -96,20 +96,49 @@ __device__ __forceinline__ void sincos_0_2pi(double x, double& sn, double& cs) {
   pc = fma(z, pc, 1.0 / 24.0);
   pc = fma(z, pc, -0.5);
   const double c = fma(z, pc, 1.0);
+  // quadrant q: (sin, cos) = (s, c), (c, -s), (-s, -c), (-c, s) for q = 0, 1, 2, 3
   const int q = (int)k & 3;
-  sn = q == 0 ? s : (q == 1 ? c : (q == 2 ? -s : -c));
-  cs = q == 0 ? c : (q == 1 ? -s : (q == 2 ? -c : s));
+  const double a = (q & 1) ? c : s, b = (q & 1) ? s : c;
+  sn = a * ((q & 2) ? -1.0 : 1.0);
+  cs = b * (((q + 1) & 2) ? -1.0 : 1.0);
+}
+
+// ln u for 2^-32 <= u <= 1 in FP64, without branches (u is never zero, negative, subnormal or special
+// here): u = f 2^e with f in [sqrt(1/2), sqrt(2)) by frexp, ln u = e ln 2 + ln f with ln 2 split into 42 +
+// 53 bits (e ln2_hi exact), and ln f = 2 atanh(s) = 2 (s + s^3/3 + ... + s^23/23), s = (f - 1)/(f + 1),
+// |s| <= 0.172 (truncation below 1e-19).
+__device__ __forceinline__ double log_unit(double u) {
+  int e;
+  double f = frexp(u, &e);  // [1/2, 1)
+  const bool lo = f < 0.70710678118654752;
+  f = lo ? 2.0 * f : f;
+  e = lo ? e - 1 : e;
+  const double sv = (f - 1.0) / (f + 1.0);
+  const double z = sv * sv;
+  double p = fma(z, 1.0 / 23.0, 1.0 / 21.0);
+  p = fma(z, p, 1.0 / 19.0);
+  p = fma(z, p, 1.0 / 17.0);
+  p = fma(z, p, 1.0 / 15.0);
+  p = fma(z, p, 1.0 / 13.0);
+  p = fma(z, p, 1.0 / 11.0);
+  p = fma(z, p, 1.0 / 9.0);
+  p = fma(z, p, 1.0 / 7.0);
+  p = fma(z, p, 1.0 / 5.0);
+  p = fma(z, p, 1.0 / 3.0);
+  const double lf = fma(2.0 * sv * z, p, 2.0 * sv);
+  const double LN2_HI = 0x1.62e42fefa3800p-1, LN2_LO = 0x1.ef35793c76730p-45;
+  return fma((double)e, LN2_HI, fma((double)e, LN2_LO, lf));
 }
 
 // Both standard normals of one 64-bit word by Box-Muller in FP64 (a = low 32 bits, b = high 32 bits):
 // u1 = (a + 1) 2^-32 in (0, 1] and u2 = b 2^-32 are exact, r = sqrt(-2 ln u1), the angle 2 pi u2 is
-// rounded to FP64 once, c = r cos(angle) (even columns), s = r sin(angle) (odd columns); log and sqrt are
-// the device library's FP64 functions, sin and cos the reduction above.
+// rounded to FP64 once, c = r cos(angle) (even columns), s = r sin(angle) (odd columns); ln by the
+// reduction above, sqrt the device library's, sin and cos by sincos_0_2pi.
 __device__ __forceinline__ void box_muller_pair_f64(uint64_t w, double& c, double& s) {
   const uint32_t a = (uint32_t)w, b = (uint32_t)(w >> 32);
   const double u1 = ((double)a + 1.0) * 0x1p-32;
   const double u2 = (double)b * 0x1p-32;
-  const double r = sqrt(-2.0 * log(u1));
+  const double r = sqrt(-2.0 * log_unit(u1));
   double sn, cs;
   sincos_0_2pi(2.0 * 3.141592653589793 * u2, sn, cs);
   c = r * cs;

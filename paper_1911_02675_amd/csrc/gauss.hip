@@ -21,8 +21,8 @@ __global__ void k_gauss_reduce(const double* __restrict__ part, int64_t nks, int
 // FP64 form on the matrix cores (v_mfma_f64_16x16x4f64).  Workgroup: 8 wavefronts, 128 rows of S A (16
 // per wavefront) x 256 columns (16 blocks of 16), over a range of rows of A split across workgroups.
 // Per step of 32 rows of A (columns kb .. kb + 31 of S): the 32 x 256 tile of A is staged in LDS (double
-// buffered: the next tile is loaded and stored into the other buffer after this step's MFMAs have
-// issued) and shared by all wavefronts.  Lane l (row il = l % 16
+// buffered; whole FP64 tiles are loaded straight into the other buffer while this step computes, other
+// tiles through registers after this step's MFMAs have issued) and shared by all wavefronts.  Lane l (row il = l % 16
 // of its wavefront's S rows, group h = l / 16) evaluates the one Philox block of columns kb + 8 h .. + 7 of
 // row il and its four Box-Muller pairs (FP64): e[p] = S[il][kb + 8 h + p].  Two 4 x 4 transposes across
 // the four 16-lane rows of the wavefront (two rounds of row swaps each), of e[0..3] and of e[4..7], leave
@@ -66,19 +66,18 @@ __device__ __forceinline__ void rows_transpose4(double& e0, double& e1, double& 
 }
 
 // The eight A operands of one step for lane (il, kk): g[s] = S[il][kb + 4 s + kk], s < 8 (see above).
+// Every lane evaluates its block (rows past m take zeros afterwards), so the code has no branches and
+// can be interleaved with the matrix-core instructions.
 __device__ __forceinline__ void gauss_step_operands(uint64_t seed, uint64_t t, int64_t irow, bool iok, int64_t kb,
                                                     int h, double (&g)[8]) {
   double e[8];
-  if (iok) {
-    const u64x4 w = philox4x64_10((uint64_t)((kb >> 3) + h), TAG_GAUSS, t, (uint64_t)irow, seed, 0);
-    box_muller_pair_f64(w.x, e[0], e[1]);
-    box_muller_pair_f64(w.y, e[2], e[3]);
-    box_muller_pair_f64(w.z, e[4], e[5]);
-    box_muller_pair_f64(w.w, e[6], e[7]);
-  } else {
+  const u64x4 w = philox4x64_10((uint64_t)((kb >> 3) + h), TAG_GAUSS, t, (uint64_t)irow, seed, 0);
+  box_muller_pair_f64(w.x, e[0], e[1]);
+  box_muller_pair_f64(w.y, e[2], e[3]);
+  box_muller_pair_f64(w.z, e[4], e[5]);
+  box_muller_pair_f64(w.w, e[6], e[7]);
 #pragma unroll
-    for (int p = 0; p < 8; ++p) e[p] = 0.0;
-  }
+  for (int p = 0; p < 8; ++p) e[p] = iok ? e[p] : 0.0;
   rows_transpose4(e[0], e[1], e[2], e[3]);  // e[q] = S[il][kb + 8 q + kk]
   rows_transpose4(e[4], e[5], e[6], e[7]);  // e[4 + q] = S[il][kb + 8 q + 4 + kk]
 #pragma unroll
@@ -88,7 +87,53 @@ __device__ __forceinline__ void gauss_step_operands(uint64_t seed, uint64_t t, i
   }
 }
 
-template <typename TA>
+// 16 bytes per lane from global memory straight into LDS: lane l's bytes land at dst + 16 l (dst must be
+// the same for the whole wavefront).
+__device__ __forceinline__ void lds_load16(const void* src, double* dst) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+}
+
+// Rows kb + lr + 8 q (q < 4), columns c0 + lc .. + 3 of A into v, zero outside rows [k0, k1) and columns
+// [0, d).  VEC: 16-byte rows (A aligned, lda and d multiples of 4 elements; FP64 also 2): vector loads.
+// Out-of-range entries read a clamped in-range address and are replaced by zero, so there are no
+// branches.  Ordinary (cached) loads: the tile is read again by the workgroups of the other rows of S.
+template <typename TA, bool VEC>
+__device__ __forceinline__ void gm_load_tile(const TA* __restrict__ A, int64_t kb, int64_t k0, int64_t k1, int64_t c0,
+                                             int64_t d, int64_t lda, int lr, int lc, double (&v)[GM_LROWS][4]) {
+  const int64_t col = c0 + lc;
+#pragma unroll
+  for (int q = 0; q < GM_LROWS; ++q) {
+    const int64_t row = kb + lr + 8 * q;
+    const bool rok = row < k1;
+    const TA* base = A + (rok ? row : k0) * lda;
+    if constexpr (VEC) {
+      const bool ok = rok && col < d;
+      const TA* pv = base + (col < d ? col : 0);
+      if constexpr (sizeof(TA) == 4) {
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 x = *(const f4*)pv;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[q][u] = ok ? (double)x[u] : 0.0;
+      } else {
+        typedef double d2 __attribute__((ext_vector_type(2)));
+        const d2 x0 = *(const d2*)pv, x1 = *(const d2*)(pv + 2);
+        v[q][0] = ok ? x0[0] : 0.0;
+        v[q][1] = ok ? x0[1] : 0.0;
+        v[q][2] = ok ? x1[0] : 0.0;
+        v[q][3] = ok ? x1[1] : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t cu = col + u;
+        const bool ok = rok && cu < d;
+        v[q][u] = ok ? (double)base[cu < d ? cu : d - 1] : 0.0;
+      }
+    }
+  }
+}
+
+template <typename TA, bool VEC>
 __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uint64_t t,
                                                              const TA* __restrict__ A, int64_t n,
                                                              int64_t d, int64_t lda, int64_t m,
@@ -106,27 +151,30 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uin
   for (int b = 0; b < GM_BLK; ++b) acc[b] = (g_d4){0.0, 0.0, 0.0, 0.0};
   // tile loader: thread -> rows tid / 64 + 8 q (q < 4), 4 consecutive columns (64 x 4 = 256)
   const int lr = tid >> 6, lc = (tid & 63) * 4;
-  auto load_tile = [&](int64_t kb, double (&v)[GM_LROWS][4]) {
-#pragma unroll
-    for (int q = 0; q < GM_LROWS; ++q) {
-      const int64_t row = kb + lr + 8 * q;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int64_t col = c0 + lc + u;
-        v[q][u] = (row < k1 && col < d) ? (double)A[row * lda + col] : 0.0;
-      }
-    }
-  };
   auto store_tile = [&](int buf, const double (&v)[GM_LROWS][4]) {
 #pragma unroll
     for (int q = 0; q < GM_LROWS; ++q)
 #pragma unroll
       for (int u = 0; u < 4; ++u) As[buf][(lr + 8 * q) * GM_LDS_STRIDE + lc + u] = v[q][u];
   };
+  // FP64 rows of 16 bytes and a column block inside [0, d): whole tiles go from global memory straight
+  // into LDS (global_load_lds, 16 bytes per lane: one instruction fills half a tile row; wavefront w fills
+  // rows w, w + 8, w + 16, w + 24), issued at the start of the step before it so that the loads fly
+  // under the MFMAs and occupy no registers
+  const bool direct_cols = sizeof(TA) == 8 && VEC && c0 + GM_COLS <= d;
+  auto direct_tile = [&](int buf, int64_t kb) {
+#pragma unroll
+    for (int q = 0; q < GM_LROWS; ++q) {
+      const int r = wv + 8 * q;
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+        lds_load16(A + (kb + r) * lda + c0 + 128 * hh + 2 * lane, &As[buf][r * GM_LDS_STRIDE + 128 * hh]);
+    }
+  };
   if (k0 < k1) {
     {
       double nv[GM_LROWS][4];
-      load_tile(k0, nv);
+      gm_load_tile<TA, VEC>(A, k0, k0, k1, c0, d, lda, lr, lc, nv);
       store_tile(0, nv);
     }
     double g[8];
@@ -135,8 +183,11 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uin
     int buf = 0;
     for (int64_t kb = k0; kb < k1; kb += GM_K) {
       const bool more = kb + GM_K < k1;
-      // the next step's operands (past the range at the last step: computed and dropped), in the same
-      // block as this step's MFMAs so that the two interleave
+      const bool direct = direct_cols && kb + 2 * GM_K <= k1;  // the next tile is whole (uniform)
+      if (direct) direct_tile(buf ^ 1, kb + GM_K);
+      // the next step's operands (past the range at the last step: computed and dropped), interleaved
+      // with this step's MFMAs: per MFMA about five VALU instructions of the normals, and the LDS
+      // reads of the B operands ahead of their MFMAs
       double gn[8];
       gauss_step_operands(seed, t, irow, iok, kb + GM_K, kk, gn);
 #pragma unroll
@@ -146,12 +197,20 @@ __global__ __launch_bounds__(GM_WAVES * 64) void k_gauss_mfma(uint64_t seed, uin
         for (int b = 0; b < GM_BLK; ++b) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[s], T[b * 16], acc[b], 0, 0, 0);
       }
 #pragma unroll
+      for (int i = 0; i < 8 * GM_BLK; ++i) {
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // one LDS read
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA
+        __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // five VALU
+      }
+#pragma unroll
       for (int s = 0; s < 8; ++s) g[s] = gn[s];
-      if (more) {
+      if (direct) {
+        __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wavefront's LDS loads have landed
+      } else if (more) {
         // the next tile into the other buffer (its last readers passed the previous barrier); the other
         // wavefront of the SIMD keeps the matrix core busy while these loads are in flight
         double nv[GM_LROWS][4];
-        load_tile(kb + GM_K, nv);
+        gm_load_tile<TA, VEC>(A, kb + GM_K, k0, k1, c0, d, lda, lr, lc, nv);
         store_tile(buf ^ 1, nv);
       }
       __syncthreads();
@@ -358,12 +417,18 @@ void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a
     return;
   }
   kchunk = (kchunk + GM_K - 1) / GM_K * GM_K;  // multiple of 32: whole steps, Philox blocks never straddle chunks
-  if (a_f32)
-    hipLaunchKernelGGL(k_gauss_mfma<float>, g, dim3(GM_WAVES * 64), 0, st, seed, t, (const float*)A, n, d,
-                       lda, m, kchunk, partials);
-  else
-    hipLaunchKernelGGL(k_gauss_mfma<double>, g, dim3(GM_WAVES * 64), 0, st, seed, t, (const double*)A, n,
-                       d, lda, m, kchunk, partials);
+  const bool v16 = ((uintptr_t)A % 16 == 0) && lda % 4 == 0 && d % 4 == 0;
+#define LSQ_GM(TA, V)                                                                                       \
+  hipLaunchKernelGGL((k_gauss_mfma<TA, V>), g, dim3(GM_WAVES * 64), 0, st, seed, t, (const TA*)A, n, d, lda, m, \
+                     kchunk, partials)
+  if (a_f32) {
+    if (v16) LSQ_GM(float, true);
+    else LSQ_GM(float, false);
+  } else {
+    if (v16) LSQ_GM(double, true);
+    else LSQ_GM(double, false);
+  }
+#undef LSQ_GM
   hipLaunchKernelGGL(k_gauss_reduce, dim3((unsigned)((m * d + 255) / 256)), dim3(256), 0, st, partials,
                      nks, m, d, 1.0 / sqrt((double)m), SA, ldsa);
 }

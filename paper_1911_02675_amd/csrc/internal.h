@@ -136,6 +136,9 @@ constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 int fused_nwg(int64_t n, int64_t d);
 extern int g_fused_groups_per_cu;   // tuning: fused-pass workgroups per CU
 extern int g_batched_slots;         // tuning: batched-kernel workgroups (0 = one per CU)
+// Bare streaming read of the first bytes / 16 whole 16-byte vectors of buf (device, 16-byte aligned) by
+// `groups` workgroups, each writing its sum to out[group] (for measuring the read ceiling).
+void stream_read(hipStream_t st, const void* buf, int64_t bytes, int groups, float* out);
 // Partial sums are reduced in two fixed-order stages: nwg rows -> REDUCE_SPLIT rows -> 1.
 constexpr int REDUCE_SPLIT = 32;
 void reduce_stage1(hipStream_t st, const double* part, int nwg, int64_t d, double* part2,

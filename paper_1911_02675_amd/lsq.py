@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_read_bandwidth", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -98,6 +98,7 @@ def load():
         "lsq_draw_sjlt": ([P, U64, U64, I64, I64, I32, P, P], I32),
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
         "lsq_fused_pass_timing": ([P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)], I32),
+        "lsq_read_bandwidth": ([P, P, I64, I32, C.POINTER(D)], I32),
         "lsq_tune": ([C.c_char_p, I64], I32),
         "lsq_set_option": ([P, C.c_char_p, I64], I32),
         "lsq_status_string": ([I32], C.c_char_p),
@@ -266,6 +267,13 @@ class Context:
 
     def draw_gaussian(self, seed, t, m, j0, ncols, G):
         _check(self.lib.lsq_draw_gaussian(self.h, seed, t, m, j0, ncols, _ptr(G)))
+
+    def read_bandwidth(self, buf, reps=5):
+        """Measured read ceiling (GB/s) over the device tensor buf (see lsq_read_bandwidth)."""
+        g = C.c_double()
+        _check(self.lib.lsq_read_bandwidth(self.h, _ptr(buf), buf.numel() * buf.element_size(), reps,
+                                           C.byref(g)))
+        return g.value
 
     def fused_pass_timing(self, reset=False):
         last, avg, cnt = C.c_double(), C.c_double(), C.c_int64()
