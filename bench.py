@@ -470,9 +470,10 @@ def sweep_msize(a):
         autotune.apply("f64" if form == "fp64" else "f32", a.d)
         A, y = (A64, y64) if form == "fp64" else (A32, y32)
         comp = "f64" if form == "fp64" or a.sketch != "srht" else "f32"
-        meas, t_pass = msize.calibrate(ctx, A, y, a.sketch, compute=comp, s=a.s, seed=a.seed)
-        extra = 0.0 if form == "fp64" else 3.0  # refinement residual passes of the mixed form
-        pick, pred = msize.choose(meas, t_pass, a.d, a.tol, extra)
+        extra = 2.0 if form == "fp64" else 3.0  # verification / refinement residual passes
+        meas, t_pass, pick, _ = msize.calibrate(ctx, A, y, a.sketch, compute=comp, s=a.s, seed=a.seed, tol=a.tol,
+                                                extra_passes=extra)
+        _, pred = msize.choose(meas, t_pass, a.d, a.tol, extra)
         measured = {}
         for m in sorted(meas):
             best = None
@@ -648,18 +649,16 @@ def main():
     ctx = lsq.Context()
     ax = torch.linalg.norm(A64 @ xs)
 
-    m_form, m_model = {}, {}
+    m_form, m_model, comp_form = {}, {}, {}
 
     def solve(form):
         x = torch.zeros(a.d, dtype=torch.float64, device=dev)
-        # not converged is reported, not raised: at kappa ~ 1e8 the FP64 conditioning floor can sit
-        # above the tolerance
+        # not converged is reported, not raised
         if form == "fp64":
             desc = lsq.sketch_desc(a.sketch, m_form[form], seed=a.seed, s=a.s, compute="f64")
             st, info = ctx.pcg_solve(A64, y64, desc, x, tol=a.tol, max_iter=200, raise_on_error=False)
         else:
-            comp = "f32" if a.sketch == "srht" else "f64"
-            desc = lsq.sketch_desc(a.sketch, m_form[form], seed=a.seed, s=a.s, compute=comp)
+            desc = lsq.sketch_desc(a.sketch, m_form[form], seed=a.seed, s=a.s, compute=comp_form[form])
             st, info = ctx.pcg_solve(A32, y32, desc, x, tol=a.tol, max_iter=200, mixed=1, max_refine=8,
                                      raise_on_error=False)
         if st not in (lsq.LSQ_OK, lsq.LSQ_ERR_NOT_CONVERGED):
@@ -671,17 +670,28 @@ def main():
     for form in forms:
         # launch parameters from the autotuner's table for this GPU (defaults when it has no entry)
         tuned[form] = autotune.apply("f64" if form == "fp64" else "f32", a.d)
+        comp_form[form] = "f64" if form == "fp64" or a.sketch != "srht" else "f32"
+        Af, yf = (A64, y64) if form == "fp64" else (A32, y32)
         if a.m == "auto":
-            # sketch size from the Section 6 cost model with costs measured here (outside the timed region)
-            comp = "f64" if form == "fp64" or a.sketch != "srht" else "f32"
-            meas, t_pass = msize.calibrate(ctx, A64 if form == "fp64" else A32, y64 if form == "fp64" else y32,
-                                           a.sketch, compute=comp, s=a.s, seed=a.seed)
-            m_form[form], _ = msize.choose(meas, t_pass, a.d, a.tol, 0.0 if form == "fp64" else 3.0)
-            m_model[form] = [{"m": m, "sketch_ms": round(ts, 3), "factor_ms": round(tf, 3), "T": T,
-                              "predicted_ms": round(pr, 2)}
-                             for m, ts, tf, T, pr in msize.table(meas, t_pass, a.d, a.tol,
-                                                                 0.0 if form == "fp64" else 3.0)]
-            log(f"[bench] {form}: sketch size m={m_form[form]} chosen by the cost model (pass {t_pass:.3f} ms)")
+            # sketch size from the Section 6 cost model with costs measured here by the library's chooser
+            # (outside the timed region); the precision form's transform: FP32, unless the factor's diagonal
+            # spread (about kappa / 25) exceeds 1e6, where the FP32 transform weakens the preconditioner
+            # (the library would otherwise retake the sketch in FP64 inside the solve)
+            extra = 2.0 if form == "fp64" else 3.0
+            meas, t_pass, m_best, tab = msize.calibrate(ctx, Af, yf, a.sketch, compute=comp_form[form], s=a.s,
+                                                        seed=a.seed, tol=a.tol, extra_passes=extra)
+            spread = {r["m"]: r["r_spread"] for r in tab}[m_best]
+            if form != "fp64" and comp_form[form] == "f32" and spread > 1e6:
+                comp_form[form] = "f64"
+                meas, t_pass, m_best, tab = msize.calibrate(ctx, Af, yf, a.sketch, compute="f64", s=a.s,
+                                                            seed=a.seed, tol=a.tol, extra_passes=extra)
+            m_form[form] = m_best
+            m_model[form] = [{"m": r["m"], "sketch_ms": round(r["t_sketch_ms"], 3),
+                              "factor_ms": round(r["t_factor_ms"], 3), "T": r["iters"],
+                              "predicted_ms": round(r["predicted_ms"], 2), "r_spread": float(f"{r['r_spread']:.3g}")}
+                             for r in tab]
+            log(f"[bench] {form}: sketch size m={m_form[form]} ({comp_form[form]} transform) chosen by the cost model "
+                f"(pass {t_pass:.3f} ms, diag(R) spread {spread:.2e})")
         else:
             m_form[form] = int(a.m)
         for _ in range(a.warmup):
@@ -736,7 +746,9 @@ def main():
         "config": {"workload": f"least squares n={a.n} d={a.d} kappa={a.kappa:g} sigma={a.sigma} "
                                f"{a.sketch} m={m_form[head]} tol={a.tol:g}",
                    "n": a.n, "d": a.d, "m": m_form[head], "m_by_form": m_form,
-                   "m_rule": ("Section 6 cost model, measured costs" if a.m == "auto" else "fixed"),
+                   "m_rule": ("Section 6 cost model, measured costs (lsq_choose_sketch_size)" if a.m == "auto"
+                              else "fixed"),
+                   "transform_by_form": comp_form,
                    "m_model": m_model or None, "kappa": a.kappa, "sketch": a.sketch,
                    "parallelism": "single GPU", "tuned": tuned},
         "rel_a_norm_error": h["err"],

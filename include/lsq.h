@@ -241,6 +241,33 @@ lsq_status lsq_fused_pass(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, i
 lsq_status lsq_fused_pass_noalloc(lsq_ctx* ctx, const lsq_problem* prob, int32_t mode, int32_t f32_math,
                                   const double* v, double* w, double* scal);
 
+/* One row of the sketch-size chooser's table (lsq_choose_sketch_size). */
+typedef struct {
+  int64_t m;           /* candidate sketch size                                              */
+  int32_t iters;       /* T(m) = ceil(log(4 / tol^2) / log(m / d)), Section 6 with rho = d/m  */
+  int32_t pad_;
+  double t_sketch_ms;  /* measured: fastest of reps sketches on this problem                  */
+  double t_factor_ms;  /* measured: fastest of reps factorizations of that sketch             */
+  double predicted_ms; /* t_sketch + t_factor + (T(m) + extra_passes) t_pass                  */
+  double r_spread;     /* max |R_ii| / min |R_ii| of the factor (about kappa(A) / 25)        */
+} lsq_msize_entry;
+
+/* Sketch size m for PCG by Section 6's cost model C(m) = C_sketch(m) + C_factor(m) + T(m) C_pass with
+ * T(m) = ceil(log(4 / eps) / log(m / d)), eps = tol^2 (rho = d/m; Theorems 6.1 and 6.2 minimise the same
+ * model in flop counts, and Section 6 leaves a hardware-specific version as future work): here the sketch,
+ * the factorization and one fused pass are timed on this GPU on the caller's problem (desc's kind, s,
+ * compute, seed and t; desc->m is ignored), for m in {1.5, 2, 3, 4, 5, 6, 8, 10, 12, 16, 24, 32, 40, 48, 64}
+ * times d (multiples of 64 when d >= 64), above d and within the embedding's limits.  extra_passes: passes
+ * over A beyond T(m) that the caller's solve makes (e.g. a verification residual).  reps >= 1 timed rounds
+ * after one warm-up round per candidate.  table (host, optional, capacity >= the candidate count, at most
+ * 15) receives every candidate; *count (host, optional) their number, *m_best (host) the argmin of the
+ * predicted times (ties: the smaller m), *t_pass_ms (host, optional) the pass time.  Synchronous; the sketches
+ * use the context's workspace.  Errors as lsq_sketch and lsq_factor; INVALID_ARG for tol outside (0, 1),
+ * reps < 1, extra_passes < 0 or a table smaller than the candidate list. */
+lsq_status lsq_choose_sketch_size(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_desc* desc, double tol,
+                                  double extra_passes, int32_t reps, lsq_msize_entry* table, int32_t capacity,
+                                  int32_t* count, int64_t* m_best, double* t_pass_ms);
+
 /* PCG with a fixed sketch (Section 1.2): x (device, d) holds x_0 on entry (zeros are a valid start)
  * and the solution on exit.  The stop rule measures the error relative to that of x_0 (for x_0 = 0,
  * relative to ||A x*||): a warm start already near x* asks for a correspondingly smaller error and
@@ -337,6 +364,12 @@ lsq_status lsq_tune(const char* key, int64_t value);
  *     (FP32 intermediate; the FP64 one takes its general form); 2 = staged through LDS, eight
  *     wavefronts, 4-point fold; 3 = sixteen wavefronts, 4-point fold; 4 = sixteen wavefronts, 8-point
  *     fold.  Every form computes the same sums (exactly, for integer-valued A).
+ *   "sketch_upgrade" (the precision form, mixed = 1, with an SRHT in FP32): 1 = after the factorization
+ *     the spread max |R_ii| / min |R_ii| (about kappa(A) / 25 for tall A) is checked, and above 1e6 the
+ *     sketch and factor are taken again with an FP64 transform of the same FP32 A, because the FP32
+ *     transform's rounding then weakens the preconditioner (measured at n = 2^22, d = 1024, m = 40960:
+ *     37 PCG iterations at kappa = 1e8 with the FP32 transform, 17 with the FP64 one; 16 either way at
+ *     kappa = 1e7), the default; 0 = never.
  * INVALID_ARG for a null context, an unknown key or an out-of-range value. */
 lsq_status lsq_set_option(lsq_ctx* ctx, const char* key, int64_t value);
 

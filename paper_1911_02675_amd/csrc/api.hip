@@ -69,7 +69,9 @@ struct lsq_ctx {
   int factor_mode = 0;    // 0 CholeskyQR2 with fallbacks, 1 Householder, 2 SVD, 3 column-pivoted QR
   int srht_passb = 0;     // SRHT pass B form for large buckets
   double* noalloc = nullptr;  // this device's static array for lsq_fused_pass_noalloc
+  int sketch_upgrade = 1; // mixed form: an FP32 SRHT is retaken in FP64 when diag(R) spreads beyond 1e6
 };
+constexpr double SKETCH_UPGRADE_SPREAD = 1e6;
 
 // Per-call trace on stderr when the environment variable LSQ_LOG is set to a non-zero value.
 static bool log_on() {
@@ -732,6 +734,26 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   CHK(do_sketch(c, p, s, s->t, SA, d, x0_zero || o->x_ref ? &grad : nullptr, &grad_rows));
   HIPCHK(hipEventRecord(c->ev[1], st));
   CHK(do_factor(c, SA, m, d, d, R, W, WT));
+  if (o->mixed && s->kind == LSQ_SRHT && s->compute == LSQ_F32 && c->sketch_upgrade) {
+    // An FP32 transform perturbs S A by about its single-precision rounding; once kappa(A) approaches
+    // 1/u32 that visibly weakens the preconditioner (at kappa = 1e8, 37 PCG iterations instead of 17).
+    // The spread of diag(R), about kappa / 25, decides: above 1e6 the sketch is taken again with an FP64
+    // transform of the same FP32 A.
+    double* spr;
+    CHK(wsT(c, "diag_spread", 1, &spr));
+    diag_spread(st, R, d, spr);
+    HIPCHK(hipMemcpyAsync(c->hx, spr, sizeof(double), hipMemcpyDeviceToHost, st));  // (x_0 was read above)
+    HIPCHK(hipStreamSynchronize(st));
+    const double spread = c->hx[0];
+    if (spread > SKETCH_UPGRADE_SPREAD) {
+      LSQ_TRACE("diag(R) spread %.3e > %.1e: FP32 transform replaced by an FP64 one", spread, SKETCH_UPGRADE_SPREAD);
+      lsq_sketch_desc s64 = *s;
+      s64.compute = LSQ_F64;
+      CHK(do_sketch(c, p, &s64, s64.t, SA, d, x0_zero || o->x_ref ? &grad : nullptr, &grad_rows));
+      HIPCHK(hipEventRecord(c->ev[1], st));
+      CHK(do_factor(c, SA, m, d, d, R, W, WT));
+    }
+  }
   HIPCHK(hipEventRecord(c->ev[2], st));
 
   const int a_f32 = p->a_dtype == LSQ_F32;
@@ -885,6 +907,113 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
     ret = fail(LSQ_ERR_NOT_CONVERGED, "the measured residual did not meet the tolerance within the budget");
   if (info) info->status = ret;
   return ret;
+}
+
+// Section 6's iteration model: T(m) = ceil(log(4 / eps) / log(m / d)), eps = tol^2 (rho = d/m).
+static int msize_iterations(int64_t m, int64_t d, double tol) {
+  if (m <= d) return 1 << 30;
+  return (int)ceil(log(4.0 / (tol * tol)) / log((double)m / (double)d));
+}
+
+// Candidate sketch sizes: 1.5 d .. 64 d (multiples of 64 for d >= 64), above d, within the
+// factorization's limit and the embedding's own (m <= N for the SRHT, 16384 for the SJLT, min(1024, n/4)
+// for Haar).
+static std::vector<int64_t> msize_candidates(int64_t n, int64_t d, int kind) {
+  int64_t hi = FACTOR_M_MAX;
+  if (kind == LSQ_SRHT) hi = std::min(hi, next_pow2(n));
+  if (kind == LSQ_SJLT) hi = std::min<int64_t>(hi, 16384);
+  if (kind == LSQ_HAAR) hi = std::min<int64_t>(std::min<int64_t>(hi, 1024), n / 4);
+  std::vector<int64_t> out;
+  for (double f : {1.5, 2.0, 3.0, 4.0, 5.0, 6.0, 8.0, 10.0, 12.0, 16.0, 24.0, 32.0, 40.0, 48.0, 64.0}) {
+    const int64_t m = d >= 64 ? (int64_t)llround(f * d / 64.0) * 64 : (int64_t)llround(f * d);
+    if (m > d && m <= hi && std::find(out.begin(), out.end(), m) == out.end()) out.push_back(m);
+  }
+  return out;
+}
+
+lsq_status lsq_choose_sketch_size(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s, double tol,
+                                  double extra_passes, int32_t reps, lsq_msize_entry* table, int32_t capacity,
+                                  int32_t* count, int64_t* m_best, double* t_pass_ms) {
+  CHK(check_problem(c, p));
+  if (!s || !m_best) return fail(LSQ_ERR_INVALID_ARG, "null descriptor or output");
+  if (!(tol > 0.0 && tol < 1.0)) return fail(LSQ_ERR_INVALID_ARG, "tol must lie in (0, 1)");
+  if (reps < 1 || extra_passes < 0.0) return fail(LSQ_ERR_INVALID_ARG, "need reps >= 1, extra_passes >= 0");
+  if (table && capacity < 1) return fail(LSQ_ERR_INVALID_ARG, "table without capacity");
+  const int64_t n = p->n, d = p->d;
+  const std::vector<int64_t> cand = msize_candidates(n, d, s->kind);
+  if (cand.empty()) return fail(LSQ_ERR_UNSUPPORTED, "no sketch size between d and the embedding's limit");
+  if (table && capacity < (int32_t)cand.size()) return fail(LSQ_ERR_INVALID_ARG, "table capacity below the candidate count");
+  const hipStream_t st = c->st;
+  double *SA, *R, *W, *WT, *spr;
+  CHK(wsT(c, "SA", (size_t)cand.back() * d, &SA));
+  CHK(wsT(c, "f_R", (size_t)d * d, &R));
+  CHK(wsT(c, "f_W", (size_t)d * d, &W));
+  CHK(wsT(c, "f_WT", (size_t)d * d, &WT));
+  CHK(wsT(c, "diag_spread", 1, &spr));
+  // one fused pass (H v), the unit of the iteration term
+  SolveBufs b;
+  CHK(solve_bufs(c, n, d, &b));
+  vec_zero(st, b.p, d);
+  double t_pass = 1e300;
+  for (int r = 0; r <= 3; ++r) {
+    HIPCHK(hipEventRecord(c->ev[4], st));
+    const int ng_ = fused_pass(st, p->A, p->a_dtype == LSQ_F32, 0, n, d, p->lda, 0, b.p, nullptr, b.part, b.nwg, nullptr);
+    HIPCHK(hipEventRecord(c->ev[5], st));
+    reduce_partials(st, b.part, b.part2, ng_, d, b.red, nullptr);
+    HIPCHK(hipEventSynchronize(c->ev[5]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+    if (r > 0) t_pass = std::min(t_pass, (double)ms);  // the first launch is a warm-up
+  }
+  int64_t best = -1;
+  double best_pred = 1e300;
+  for (size_t i = 0; i < cand.size(); ++i) {
+    lsq_sketch_desc sd = *s;
+    sd.m = cand[i];
+    CHK(check_sketch(c, p, &sd, true));
+    double ts = 1e300, tf = 1e300;
+    for (int r = 0; r <= reps; ++r) {
+      HIPCHK(hipEventRecord(c->ev[0], st));
+      CHK(do_sketch(c, p, &sd, sd.t, SA, d));
+      HIPCHK(hipEventRecord(c->ev[1], st));
+      CHK(do_factor(c, SA, sd.m, d, d, R, W, WT));
+      HIPCHK(hipEventRecord(c->ev[2], st));
+      HIPCHK(hipEventSynchronize(c->ev[2]));
+      float a = 0.f, f = 0.f;
+      HIPCHK(hipEventElapsedTime(&a, c->ev[0], c->ev[1]));
+      HIPCHK(hipEventElapsedTime(&f, c->ev[1], c->ev[2]));
+      if (r > 0 || reps == 0) {  // the first round also loads code and grows the workspace
+        ts = std::min(ts, (double)a);
+        tf = std::min(tf, (double)f);
+      }
+    }
+    diag_spread(st, R, d, spr);
+    HIPCHK(hipMemcpyAsync(c->hflags, spr, sizeof(double), hipMemcpyDeviceToHost, st));  // (8 pinned ints)
+    HIPCHK(hipStreamSynchronize(st));
+    double spread;
+    memcpy(&spread, c->hflags, sizeof(double));
+    const int T = msize_iterations(sd.m, d, tol);
+    const double pred = ts + tf + (T + extra_passes) * t_pass;
+    LSQ_TRACE("sketch size %lld: sketch %.3f ms factor %.3f ms T %d predicted %.2f ms (diag spread %.2e)",
+              (long long)sd.m, ts, tf, T, pred, spread);
+    if (table) {
+      table[i].m = sd.m;
+      table[i].iters = T;
+      table[i].pad_ = 0;
+      table[i].t_sketch_ms = ts;
+      table[i].t_factor_ms = tf;
+      table[i].predicted_ms = pred;
+      table[i].r_spread = spread;
+    }
+    if (pred < best_pred) {  // ties keep the smaller m
+      best_pred = pred;
+      best = sd.m;
+    }
+  }
+  if (count) *count = (int32_t)cand.size();
+  if (t_pass_ms) *t_pass_ms = t_pass;
+  *m_best = best;
+  return LSQ_OK;
 }
 
 lsq_status lsq_ihs_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc* s,
@@ -1199,6 +1328,11 @@ lsq_status lsq_set_option(lsq_ctx* c, const char* key, int64_t value) {
                   "srht_passb: 0 (LDS-staged, fold width by bucket size, the default), 1 (register-direct), "
                   "2 (LDS-staged, 8 wavefronts), 3 (16 wavefronts, 4-point fold) or 4 (16 wavefronts, 8-point fold)");
     c->srht_passb = (int)value;
+    return LSQ_OK;
+  }
+  if (k == "sketch_upgrade") {
+    if (value < 0 || value > 1) return fail(LSQ_ERR_INVALID_ARG, "sketch_upgrade: 0 or 1");
+    c->sketch_upgrade = (int)value;
     return LSQ_OK;
   }
   return fail(LSQ_ERR_INVALID_ARG, "unknown option: " + k);

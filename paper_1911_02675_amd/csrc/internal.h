@@ -86,6 +86,8 @@ void tri_inverse_padded(hipStream_t st, const double* R, int64_t n, double* W, d
 // status |= 1 when some |R_kk| <= 8 d eps max |R_jj|.
 // flag (device int, cleared by the caller) = 1 when X (m x d, row stride ld) holds a NaN or an infinity.
 void nonfinite_scan(hipStream_t st, const double* X, int64_t m, int64_t d, int64_t ld, int* flag);
+// out[0] (device) = max |R_ii| / min |R_ii| of the d x d row-major R (a lower estimate of kappa(R)).
+void diag_spread(hipStream_t st, const double* R, int64_t d, double* out);
 void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status);
 
 // ---- chol.hip -----------------------------------------------------------------------------------

@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_read_bandwidth", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_read_bandwidth", "lsq_choose_sketch_size", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -58,6 +58,11 @@ class Info(C.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MsizeEntry(C.Structure):
+    _fields_ = [("m", C.c_int64), ("iters", C.c_int32), ("pad_", C.c_int32), ("t_sketch_ms", C.c_double),
+                ("t_factor_ms", C.c_double), ("predicted_ms", C.c_double), ("r_spread", C.c_double)]
 
 
 class LsqError(RuntimeError):
@@ -99,6 +104,8 @@ def load():
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
         "lsq_fused_pass_timing": ([P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)], I32),
         "lsq_read_bandwidth": ([P, P, I64, I32, C.POINTER(D)], I32),
+        "lsq_choose_sketch_size": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), D, D, I32, C.POINTER(MsizeEntry),
+                                    I32, C.POINTER(I32), C.POINTER(I64), C.POINTER(D)], I32),
         "lsq_tune": ([C.c_char_p, I64], I32),
         "lsq_set_option": ([P, C.c_char_p, I64], I32),
         "lsq_status_string": ([I32], C.c_char_p),
@@ -267,6 +274,18 @@ class Context:
 
     def draw_gaussian(self, seed, t, m, j0, ncols, G):
         _check(self.lib.lsq_draw_gaussian(self.h, seed, t, m, j0, ncols, _ptr(G)))
+
+    def choose_sketch_size(self, A, y, desc, tol=1e-10, extra_passes=0.0, reps=2):
+        """Section 6's chooser with this GPU's measured costs (lsq_choose_sketch_size).  Returns
+        (m_best, table, t_pass_ms) with table a list of dicts (m, iters, t_sketch_ms, t_factor_ms,
+        predicted_ms, r_spread)."""
+        p = problem(A, y)
+        tab = (MsizeEntry * 16)()
+        cnt, mb, tp = C.c_int32(), C.c_int64(), C.c_double()
+        _check(self.lib.lsq_choose_sketch_size(self.h, C.byref(p), C.byref(desc), tol, extra_passes, reps, tab, 16,
+                                               C.byref(cnt), C.byref(mb), C.byref(tp)))
+        rows = [{k: getattr(tab[i], k) for k, _ in MsizeEntry._fields_ if k != "pad_"} for i in range(cnt.value)]
+        return mb.value, rows, tp.value
 
     def read_bandwidth(self, buf, reps=5):
         """Measured read ceiling (GB/s) over the device tensor buf (see lsq_read_bandwidth)."""

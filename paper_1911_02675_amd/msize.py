@@ -111,50 +111,18 @@ def choose(meas, t_pass, d, tol, extra_passes=0.0):
     return min(pred, key=lambda m: (pred[m], m)), pred
 
 
-def calibrate(ctx, A, y, kind, compute="f64", s=4, seed=1, ms=None, reps=2):
-    """Measure the library's sketch and factor times (ms) at each candidate m and the time of one fused
-    pass, on the caller's matrix (torch CUDA tensors A, y).  Returns (meas, t_pass_ms)."""
-    import torch
-
+def calibrate(ctx, A, y, kind, compute="f64", s=4, seed=1, tol=1e-10, extra_passes=0.0, reps=2):
+    """The library's chooser (lsq_choose_sketch_size: the sketch, factor and one fused pass timed on this GPU
+    at every candidate m, on the caller's torch CUDA tensors A, y).  Returns (meas, t_pass_ms, m_best, table)
+    with meas = {m: (t_sketch_ms, t_factor_ms)} for `choose` / `predict` and table the library's rows."""
     from . import lsq
-    n, d = A.shape
-    ms = ms or candidates(n, d, kind)
-    ev0, ev1, ev2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
-    stream = torch.cuda.current_stream()
-    meas = {}
-    for m in ms:
-        SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
-        R = torch.empty((d, d), dtype=torch.float64, device="cuda")
-        W = torch.empty((d, d), dtype=torch.float64, device="cuda")
-        best = None
-        for _ in range(reps + 1):
-            desc = lsq.sketch_desc(kind, m, seed=seed, s=s, compute=compute)
-            ev0.record(stream)
-            ctx.sketch(A, y, desc, SA)
-            ev1.record(stream)
-            ctx.factor(SA, R, W)
-            ev2.record(stream)
-            ev2.synchronize()
-            cur = (ev0.elapsed_time(ev1), ev1.elapsed_time(ev2))
-            best = cur if best is None else (min(best[0], cur[0]), min(best[1], cur[1]))
-        meas[m] = best
-        del SA, R, W
-    v = torch.randn(d, dtype=torch.float64, device="cuda")
-    w = torch.empty(d, dtype=torch.float64, device="cuda")
-    sc = torch.empty(1, dtype=torch.float64, device="cuda")
-    ctx.fused_pass(A, y, v, w, sc)
-    ctx.fused_pass_timing(reset=True)
-    for _ in range(3):
-        ctx.fused_pass(A, y, v, w, sc)
-    _, t_pass, _ = ctx.fused_pass_timing()
-    return meas, float(t_pass)
+    desc = lsq.sketch_desc(kind, 0, seed=seed, s=s, compute=compute)
+    m_best, table, t_pass = ctx.choose_sketch_size(A, y, desc, tol=tol, extra_passes=extra_passes, reps=reps)
+    meas = {r["m"]: (r["t_sketch_ms"], r["t_factor_ms"]) for r in table}
+    return meas, float(t_pass), m_best, table
 
 
 def table(meas, t_pass, d, tol, extra_passes=0.0):
-    """Rows (m, sketch ms, factor ms, T(m), predicted ms) for reports."""
+    """Rows (m, sketch ms, factor ms, T(m), predicted ms) of the cost model, by increasing m."""
     pred = predict(meas, t_pass, d, tol, extra_passes)
     return [(m, meas[m][0], meas[m][1], pcg_iterations(m, d, tol), pred[m]) for m in sorted(meas)]
-
-
-__all__ = ["lambert_w0", "pcg_iterations", "m_star_gaussian", "m_opt_gaussian", "m_star_srht", "paper_m_star", "candidates",
-           "predict", "choose", "calibrate", "table"]

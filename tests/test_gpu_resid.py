@@ -109,3 +109,34 @@ def test_mixed_refinement_from_nonzero_start(ctx):
             info.refinements, "iters", info.iters, "e_A", e)
         assert st == lsq.LSQ_OK
         assert e <= 1e-10
+
+
+def test_mixed_fp32_transform_upgrade_at_kappa_1e8(ctx):
+    """The precision form with an FP32 SRHT at kappa = 1e8: the FP32 transform's rounding weakens the
+    preconditioner, the factor's diagonal spread (about kappa / 25) exceeds 1e6, and the solve retakes the
+    sketch with an FP64 transform (lsq_set_option "sketch_upgrade", on by default).  Both settings reach the
+    tolerance; the upgraded one needs fewer PCG iterations."""
+    import torch
+
+    from paper_1911_02675_amd import lsq
+    from synth import make_planted
+    n, d, m = 1 << 16, 128, 1024
+    P = make_planted(n, d, 1e8, sigma=0.01, seed=94, want64=False, want32=True)
+    A32 = torch.from_numpy(P["A32"]).cuda()
+    y32 = torch.from_numpy(P["y32"]).cuda()
+    xs = torch.from_numpy(P["x_star"]).cuda()
+    Ad = A32.double()
+    res = {}
+    try:
+        for up in (0, 1):
+            ctx.set_option("sketch_upgrade", up)
+            x = torch.zeros(d, dtype=torch.float64, device="cuda")
+            st, info = ctx.pcg_solve(A32, y32, lsq.sketch_desc("srht", m, seed=4, compute="f32"), x, tol=1e-10,
+                                     max_iter=300, mixed=1, max_refine=10, raise_on_error=False)
+            e = float(torch.linalg.norm(Ad @ (x - xs)) / torch.linalg.norm(Ad @ xs))
+            say("  sketch_upgrade", up, "status", st, "iters", info.iters, "e_A", e)
+            assert st == lsq.LSQ_OK and e <= 1e-10
+            res[up] = info.iters
+    finally:
+        ctx.set_option("sketch_upgrade", 1)
+    assert res[1] < res[0]
