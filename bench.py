@@ -754,7 +754,8 @@ def main():
         "rel_a_norm_error": h["err"],
         "fp64": ({"time_s": round(res["fp64"]["s"], 5), "rel_a_norm_error": res["fp64"]["err"],
                   "status": res["fp64"]["info"]["status"],
-                  "iters": res["fp64"]["info"]["iters"], "fused_gbs": round(res["fp64"]["fused_gbs"], 1),
+                  "iters": res["fp64"]["info"]["iters"], "refinements": res["fp64"]["info"]["refinements"],
+                  "fused_gbs": round(res["fp64"]["fused_gbs"], 1),
                   "phases_ms": {k: round(res["fp64"]["info"][k], 3) for k in
                                 ("t_sketch_ms", "t_factor_ms", "t_iter_ms")}}
                  if "fp64" in res else None),

@@ -347,7 +347,14 @@ lsq_status lsq_read_bandwidth(lsq_ctx* ctx, const void* buf, int64_t bytes, int3
  * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
  * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);
  * "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute unit, else
- * 1..65536).  INVALID_ARG for an unknown key or an out-of-range value. */
+ * 1..65536); "srht_fold8_rows_f32" / "srht_fold8_rows_f64" (the SRHT's LDS-staged second pass folds by
+ * the 8-point transform, rather than the 4-point one, from this many selected rows per 256-row bucket on
+ * average, FP32 / FP64 intermediate; defaults 64 / 128); "srht_passa_wgs" (workgroups the SRHT's first
+ * pass aims at, 0 = 2^17 for an FP32 transform and 2^15 for FP64, the default); "srht_passb_wgs"
+ * (workgroups the LDS-staged second pass aims at when splitting its sums over j_hi, default 8192);
+ * "gauss_wgs" (workgroups the Gaussian sketch aims at when splitting the rows of A, default 1024);
+ * "gram_wgs" (workgroups the CholeskyQR Gram kernel aims at when splitting the rows of S A, default 2048).
+ * INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
 
 /* Numerics options of one context (each context starts with the defaults; calls on other contexts are

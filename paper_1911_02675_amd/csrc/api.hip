@@ -1309,6 +1309,24 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     g_batched_slots = (int)value;
     return LSQ_OK;
   }
+  struct Knob {
+    const char* key;
+    int* var;
+    int64_t lo, hi;
+  };
+  const Knob knobs[] = {{"srht_fold8_rows_f32", &g_srht_fold8_rows_f32, 1, 1 << 20},
+                        {"srht_fold8_rows_f64", &g_srht_fold8_rows_f64, 1, 1 << 20},
+                        {"srht_passa_wgs", &g_srht_passa_wgs, 0, 1 << 22},
+                        {"srht_passb_wgs", &g_srht_passb_wgs, 256, 1 << 20},
+                        {"gauss_wgs", &g_gauss_wgs, 64, 1 << 16},
+                        {"gram_wgs", &g_gram_wgs, 64, 1 << 16}};
+  for (const Knob& kn : knobs)
+    if (k == kn.key) {
+      if (value < kn.lo || value > kn.hi)
+        return fail(LSQ_ERR_INVALID_ARG, k + " in [" + std::to_string(kn.lo) + ", " + std::to_string(kn.hi) + "]");
+      *kn.var = (int)value;
+      return LSQ_OK;
+    }
   return fail(LSQ_ERR_INVALID_ARG, "unknown tuning key: " + k);
 }
 

@@ -427,11 +427,13 @@ __global__ __launch_bounds__(1024) void k_chol_diagratio(const double* __restric
 // --------------------------------------------------------------------------------------------------
 int64_t cholqr_padded(int64_t d) { return (d + CQ_T - 1) / CQ_T * CQ_T; }
 
+int g_gram_wgs = 2048;
+
 static int gram_splits(int64_t m, int64_t dp) {
   const int64_t tiles = (dp / CQ_T) * (dp / CQ_T + 1) / 2;
-  // about 2048 workgroups: two rounds of four per compute unit (33 KB of LDS each), so that the last
-  // round is nearly full
-  int64_t s = (2048 + tiles / 2) / tiles;
+  // about g_gram_wgs (2048) workgroups: two rounds of four per compute unit (33 KB of LDS each), so that
+  // the last round is nearly full
+  int64_t s = (g_gram_wgs + tiles / 2) / tiles;
   const int64_t smax = (m + 255) / 256;  // at least 256 rows per split
   s = s > smax ? smax : s;
   return (int)(s < 1 ? 1 : (s > 32 ? 32 : s));

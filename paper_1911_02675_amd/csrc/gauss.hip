@@ -379,10 +379,12 @@ __global__ __launch_bounds__(GB_WAVES * 64) void k_gauss_bf16(uint64_t seed, uin
   }
 }
 
+int g_gauss_wgs = 1024;
+
 static int64_t gauss_nks(int64_t m, int64_t d, int64_t n) {
-  // GM_ROWS x GM_COLS and GB_ROWS x GB_COLS tiles are the same size
+  // GM_ROWS x GM_COLS and GB_ROWS x GB_COLS tiles are the same size; about g_gauss_wgs workgroups in all
   const int64_t tiles = ((m + GM_ROWS - 1) / GM_ROWS) * ((d + GM_COLS - 1) / GM_COLS);
-  int64_t nks = (1024 + tiles - 1) / tiles;
+  int64_t nks = (g_gauss_wgs + tiles - 1) / tiles;
   const int64_t maxks = (n + 255) / 256;
   if (nks > maxks) nks = maxks;
   if (nks > 512) nks = 512;

@@ -136,6 +136,14 @@ constexpr int64_t FACTOR_M_MAX = 65536;  // any factorization
 
 // ---- iter.hip -----------------------------------------------------------------------------------
 int fused_nwg(int64_t n, int64_t d);
+// Launch-shape tuning (lsq_tune; set from the autotuner's table).  None changes the method: each selects
+// a grid or a kernel form that computes the same sums (in another fixed order at most).
+extern int g_srht_fold8_rows_f32;   // SRHT pass B: 8-point fold from this many selected rows per bucket (FP32 T)
+extern int g_srht_fold8_rows_f64;   // the same for an FP64 intermediate
+extern int g_srht_passa_wgs;        // SRHT pass A: workgroups aimed at (0: by the transform precision)
+extern int g_srht_passb_wgs;        // LDS-staged SRHT pass B: workgroups aimed at when splitting j_hi
+extern int g_gauss_wgs;             // Gaussian sketch: workgroups aimed at when splitting n
+extern int g_gram_wgs;              // CholeskyQR Gram kernel: workgroups aimed at when splitting m
 extern int g_fused_groups_per_cu;   // tuning: fused-pass workgroups per CU
 extern int g_batched_slots;         // tuning: batched-kernel workgroups (0 = one per CU)
 // Bare streaming read of the first bytes / 16 whole 16-byte vectors of buf (device, 16-byte aligned) by

@@ -21,6 +21,10 @@
 namespace lsq {
 
 constexpr int SRHT_N1_MAX = 512;
+int g_srht_fold8_rows_f32 = 64;
+int g_srht_fold8_rows_f64 = 128;
+int g_srht_passa_wgs = 0;
+int g_srht_passb_wgs = 8192;
 
 // --------------------------------------------------------------------------------------------------
 // Grouping of the selected rows by k_lo (single workgroup): bucket counts, their scan, a scatter.
@@ -1103,11 +1107,11 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   }
 }
 
-// j_hi ranges of the LDS-staged pass B: about 8192 workgroups in all, at most the partial buffer's
-// ranges, at least two stages (256 rows of T for FP32, 128 for FP64) per range.
+// j_hi ranges of the LDS-staged pass B: about g_srht_passb_wgs (8192) workgroups in all, at most the
+// partial buffer's ranges, at least two stages (256 rows of T for FP32, 128 for FP64) per range.
 static int srht_js_lds(int64_t N1, int64_t N2, int64_t ncb) {
   int js = 1;
-  while (js < 8 && N1 * ncb * js < 8192 && N2 / (2 * js) >= 256 && 2 * js <= srht_js_cap(N2)) js *= 2;
+  while (js < 8 && N1 * ncb * js < g_srht_passb_wgs && N2 / (2 * js) >= 256 && 2 * js <= srht_js_cap(N2)) js *= 2;
   return js;
 }
 
@@ -1147,7 +1151,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       // slice groups: about 2^17 (FP32 T) or 2^15 (FP64 T) workgroups in all, measured best on gfx950
       constexpr int64_t DC = 16 * VW;
       const int64_t nslices = (d + DC - 1) / DC;
-      const int64_t target = sizeof(TC) == 4 ? (1 << 17) : (1 << 15);
+      const int64_t target = g_srht_passa_wgs > 0 ? g_srht_passa_wgs : (sizeof(TC) == 4 ? (1 << 17) : (1 << 15));
       int64_t sg = (target + p.N2 - 1) / p.N2;
       sg = sg > nslices ? nslices : (sg < 1 ? 1 : sg);
       // (the gradient needs A's values exactly: not with an FP32 transform of FP64 A)
@@ -1185,7 +1189,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       // on average (measured at n = 2^22, d = 1024: sketches 3-8 % faster from 64 to 256 rows, where its
       // tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen, 4-point;
       // 4 sixteen, 8-point.
-      const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= 64 * p.N1);
+      const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= (int64_t)g_srht_fold8_rows_f32 * p.N1);
       if (p.passb == 2)
         hipLaunchKernelGGL((k_srht_passB_u<float, 8, 2>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
@@ -1210,7 +1214,7 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
     // as for FP32 T; the FP64 8-point form's 64 KB stages leave one workgroup per CU (measured at n = 2^22,
     // d = 1024: sketches 5-9 % faster from 128 to 256 rows per bucket, even at 96)
-    const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= 128 * p.N1);
+    const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= (int64_t)g_srht_fold8_rows_f64 * p.N1);
     if (p.passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
