@@ -3,18 +3,33 @@
     python -m paper_1911_02675_amd.autotune [--quick] [--out PATH]   measure on this GPU, write the table
     from paper_1911_02675_amd import autotune; autotune.apply()        set the library's knobs from it
 
-Two knobs are measured (see lsq_tune in include/lsq.h):
+Knobs measured (see lsq_tune in include/lsq.h), each as the fastest of a few candidates:
   fused_groups_per_cu  workgroups per compute unit of the fused A^T(A p) pass, per storage dtype and
                        bucket of d (the pass is HBM-bound; the best oversubscription depends on the
                        row width and on how many rows a workgroup streams);
   batched_slots        workgroups of the persistent batched kernel (each streams one problem; fewer
-                       than one per compute unit can win when the largest problems set the makespan).
+                       than one per compute unit can win when the largest problems set the makespan);
+  srht_passa_wgs       workgroups of the SRHT's first pass, per transform precision and d bucket (timed
+                       at m = 4d, where the second pass is small);
+  srht_passb_wgs       workgroups of the LDS-staged second pass (timed at m = 40 d);
+  srht_fold8_rows_*    from how many selected rows per 256-row bucket the second pass folds by the
+                       8-point transform instead of the 4-point one (both forms timed at 32..192 rows per
+                       bucket; the threshold is the smallest count from which the 8-point form stays
+                       faster);
+  gauss_wgs            workgroups of the Gaussian sketch (FP64 form, n = 2^20, d = 512, m = 2048);
+  gram_wgs             workgroups of the CholeskyQR Gram kernel, per d bucket (the factor of an m = 40 d
+                       sketch).
 
 The table is JSON keyed by the GPU's architecture name (gcnArchName), so a table measured on one
 chip is never applied to another:
   {"gfx950:sramecc+:xnack-": {"fused_groups_per_cu": {"f32": {"64": 8, ...}, "f64": {...}},
-                              "batched_slots": 192, "measured": {...raw timings...}}}
-apply(dtype, d) picks the entry of the bucket that contains d (the largest bucket not above d).
+                              "batched_slots": 192,
+                              "srht": {"f32": {"256": {"srht_passa_wgs": ..., "srht_passb_wgs": ...,
+                                                       "fold8_rows": ...}, "1024": {...}}, "f64": {...}},
+                              "gauss_wgs": 1024, "gram_wgs": {"256": ..., "1024": ...},
+                              "measured": {...raw timings...}}}
+apply(dtype, d) picks the entry of the bucket that contains d (the largest bucket not above d; the
+nearest measured bucket for the SRHT and Gram knobs, which are measured at fewer widths).
 The default table path is tune_table.json next to this file; LSQ_TUNE_TABLE overrides it.
 """
 import argparse
@@ -29,6 +44,14 @@ DEFAULT_TABLE = os.path.join(HERE, "tune_table.json")
 D_BUCKETS = (64, 256, 1024)
 GPC_CANDIDATES = (2, 4, 8, 16)
 SLOT_CANDIDATES = (128, 192, 256)
+PASSA_CANDIDATES = (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
+PASSB_CANDIDATES = (4096, 8192, 16384)
+FOLD_ROWS = (32, 48, 64, 96, 128, 160, 192)
+GAUSS_CANDIDATES = (512, 1024, 2048, 4096)
+GRAM_CANDIDATES = (1024, 2048, 4096)
+# library defaults, restored after measuring
+DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
+            "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128, "gauss_wgs": 1024, "gram_wgs": 2048}
 
 
 def table_path():
@@ -57,14 +80,40 @@ def bucket(d):
     return str(b)
 
 
+def _by_bucket(tab, d):
+    """The entry of a {bucket: value} map for d: its bucket, else the nearest bucket measured."""
+    if not tab:
+        return None
+    b = bucket(d)
+    if b in tab:
+        return tab[b]
+    return tab[min(tab, key=lambda k: abs(int(k) - int(b)))]
+
+
 def choose(entry, dtype="f32", d=1024):
-    """Knob values for (dtype, d) from one architecture's entry of the table."""
+    """Knob values for (dtype, d) from one architecture's entry of the table: dtype is the storage type of A
+    and the precision of the SRHT transform ("f32" for the precision form, "f64" for the plain one)."""
     out = {}
     g = entry.get("fused_groups_per_cu", {}).get(dtype, {})
     if g:
         out["fused_groups_per_cu"] = int(g.get(bucket(d), next(iter(g.values()))))
     if "batched_slots" in entry:
         out["batched_slots"] = int(entry["batched_slots"])
+    srht = entry.get("srht", {})
+    sr = _by_bucket(srht.get(dtype, {}), d)
+    if sr:
+        out["srht_passa_wgs"] = int(sr["srht_passa_wgs"])
+        out["srht_passb_wgs"] = int(sr["srht_passb_wgs"])
+    # the fold threshold is held per transform precision: both, since a solve may change its transform
+    for prec in ("f32", "f64"):
+        sp = _by_bucket(srht.get(prec, {}), d)
+        if sp:
+            out["srht_fold8_rows_" + prec] = int(sp["fold8_rows"])
+    if "gauss_wgs" in entry:
+        out["gauss_wgs"] = int(entry["gauss_wgs"])
+    gw = _by_bucket(entry.get("gram_wgs", {}), d)
+    if gw:
+        out["gram_wgs"] = int(gw)
     return out
 
 
@@ -155,18 +204,141 @@ def measure_batched(ctx, quick=False):
     return res
 
 
+def _time_ms(fn, reps):
+    """Fastest of `reps` runs of fn (after one warm-up), from torch events on the current stream."""
+    import torch
+    fn()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        e1.synchronize()
+        t = e0.elapsed_time(e1)
+        best = t if best is None else min(best, t)
+    return best
+
+
+def _fold_threshold(t4, t8):
+    """The smallest rows-per-bucket count from which the 8-point form is faster at every larger count
+    measured (one past the largest when it never wins)."""
+    rows = sorted(t4)
+    thr = rows[-1] + 1
+    for r in reversed(rows):
+        if t8[r] < t4[r]:
+            thr = r
+        else:
+            break
+    return thr
+
+
+def measure_srht(ctx, quick=False):
+    """Sketch times (ms) for the SRHT knobs, per transform precision and d bucket."""
+    import torch
+    shapes = {"1024": ((1 << 19) if quick else (1 << 22), 1024), "256": ((1 << 18) if quick else (1 << 21), 256)}
+    reps = 2 if quick else 3
+    res = {}
+    for dt, tdt in (("f32", torch.float32), ("f64", torch.float64)):
+        res[dt] = {}
+        for b, (n, d) in shapes.items():
+            A = torch.randn(n, d, dtype=tdt, device="cuda")
+            y = torch.zeros(n, dtype=torch.float64, device="cuda")
+            N = 1 << (n - 1).bit_length()
+            rec = {"n": n, "d": d, "passa": {}, "passb": {}, "fold4": {}, "fold8": {}}
+
+            def sk(m):
+                SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+                desc = lsq.sketch_desc("srht", m, seed=3, compute=dt)
+                return lambda: ctx.sketch(A, y, desc, SA)
+            m_small = 4 * d
+            for w in PASSA_CANDIDATES:
+                lsq.tune("srht_passa_wgs", w)
+                rec["passa"][str(w)] = round(_time_ms(sk(m_small), reps), 4)
+            lsq.tune("srht_passa_wgs", 0)
+            m_big = min(40 * d, N // 2)
+            for w in PASSB_CANDIDATES:
+                lsq.tune("srht_passb_wgs", w)
+                rec["passb"][str(w)] = round(_time_ms(sk(m_big), reps), 4)
+            lsq.tune("srht_passb_wgs", 8192)
+            try:
+                for rows in FOLD_ROWS:
+                    m = rows * 256
+                    if m > N or m > 65536:
+                        continue
+                    for mode, key in ((3, "fold4"), (4, "fold8")):
+                        ctx.set_option("srht_passb", mode)
+                        rec[key][str(rows)] = round(_time_ms(sk(m), reps), 4)
+            finally:
+                ctx.set_option("srht_passb", 0)
+            res[dt][b] = rec
+            del A, y
+            torch.cuda.empty_cache()
+    return res
+
+
+def measure_gauss(ctx, quick=False):
+    """FP64 Gaussian sketch time (ms) per workgroup target."""
+    import torch
+    n, d, m = ((1 << 17) if quick else (1 << 20)), 512, 2048
+    A = torch.randn(n, d, dtype=torch.float64, device="cuda")
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc("gaussian", m, seed=3)
+    res = {}
+    for w in GAUSS_CANDIDATES:
+        lsq.tune("gauss_wgs", w)
+        res[str(w)] = round(_time_ms(lambda: ctx.sketch(A, y, desc, SA), 2), 4)
+    lsq.tune("gauss_wgs", 1024)
+    return res
+
+
+def measure_gram(ctx, quick=False):
+    """Factor time (ms) of an m = 40 d sketch per Gram workgroup target, per d bucket."""
+    import torch
+    res = {}
+    for d in ((256,) if quick else (256, 1024)):
+        m = 40 * d
+        SA = torch.randn(m, d, dtype=torch.float64, device="cuda")
+        R = torch.empty((d, d), dtype=torch.float64, device="cuda")
+        W = torch.empty((d, d), dtype=torch.float64, device="cuda")
+        row = {}
+        for w in GRAM_CANDIDATES:
+            lsq.tune("gram_wgs", w)
+            row[str(w)] = round(_time_ms(lambda: ctx.factor(SA, R, W), 3), 4)
+        res[str(d)] = row
+    lsq.tune("gram_wgs", 2048)
+    return res
+
+
+def _argmin(row):
+    return int(min(row, key=lambda k: (row[k], int(k))))
+
+
 def tune(quick=False, path=None):
     """Measure, write the architecture's entry of the table, return it."""
     ctx = lsq.Context()
     try:
         fused = measure_fused(ctx, quick)
         batched = measure_batched(ctx, quick)
+        srht = measure_srht(ctx, quick)
+        gauss = measure_gauss(ctx, quick)
+        gram = measure_gram(ctx, quick)
     finally:
         ctx.close()
+        for k, v in DEFAULTS.items():
+            lsq.tune(k, v)
     entry = {"fused_groups_per_cu": {dt: {b: int(max(row, key=row.get)) for b, row in per.items()}
                                      for dt, per in fused.items()},
              "batched_slots": int(max(batched, key=batched.get)),
-             "measured": {"fused_gbs": fused, "batched_solves_per_s": batched, "quick": quick}}
+             "srht": {dt: {b: {"srht_passa_wgs": _argmin(rec["passa"]), "srht_passb_wgs": _argmin(rec["passb"]),
+                               "fold8_rows": _fold_threshold({int(k): v for k, v in rec["fold4"].items()},
+                                                             {int(k): v for k, v in rec["fold8"].items()})}
+                          for b, rec in per.items()} for dt, per in srht.items()},
+             "gauss_wgs": _argmin(gauss),
+             "gram_wgs": {b: _argmin(row) for b, row in gram.items()},
+             "measured": {"fused_gbs": fused, "batched_solves_per_s": batched, "srht_ms": srht,
+                          "gauss_ms": gauss, "gram_ms": gram, "quick": quick}}
     path = path or table_path()
     tab = load_table(path)
     tab[arch_name()] = entry
