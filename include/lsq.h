@@ -201,14 +201,19 @@ lsq_status lsq_sketch(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch_de
 /* Upper-triangular R (d x d, row-major, positive diagonal) with R^T R = (SA)^T (SA) of SA (m x d,
  * row-major, ld lds, m >= d), and W = R^{-1} (d x d, row-major).  Section 1.2 (the paper names QR of S A
  * or a Cholesky factor of H_S = (SA)^T (SA)).  Default: CholeskyQR2, R = chol(Q1^T Q1) chol(X^T X) with
- * Q1 = X chol(X^T X)^{-1}, backward stable like QR; when the first Cholesky breaks down or the spread of
- * its diagonal exceeds 1e7 (kappa(SA) beyond about 1e7), Householder QR for m <= 8192 and shifted
- * CholeskyQR3 above.  lsq_tune("factor", 1) selects Householder QR alone.  lsq_tune("factor", 2)
+ * X = SA and Q1 = X chol(X^T X)^{-1}, backward stable like QR (lsq_pcg_solve and lsq_choose_sketch_size
+ * instead stop at R = chol(X^T X), the Cholesky factor of H_S itself, when the spread max|R_jj| / min|R_jj|
+ * of that factor is at most 2e5: its error, about eps kappa(SA)^2 relative, perturbs the preconditioned
+ * operator by a factor 1 + O(eps kappa^2), which leaves the PCG iteration count unchanged there and never
+ * the verified answer); when the first Cholesky breaks down or its spread exceeds 1e7 (kappa(SA) beyond
+ * about 1e7), Householder QR for m <= 8192 and shifted CholeskyQR3 above.  Option "factor" 4 forces
+ * CholeskyQR2 and 5 the one-pass factor, everywhere (both with the same fallbacks).  Option "factor" 1
+ * selects Householder QR alone; 2
  * selects the SVD (LSRN) form: R by Householder QR (m <= 8192, rank deficiency allowed) or CholeskyQR2,
  * then one-sided Jacobi on R gives S A = U Sigma V^T; R is returned as Sigma V^T and W = V Sigma^+
  * (both dense; singular values at or below 1e-12 sigma_max dropped, their rows of R and columns of W
  * zero), and every solver then applies H_S^+ = W W^T, so that PCG from x_0 = 0 converges to the
- * minimum-norm solution of a rank-deficient problem.  lsq_tune("factor", 3) selects column-pivoted
+ * minimum-norm solution of a rank-deficient problem.  Option "factor" 3 selects column-pivoted
  * Householder QR: R11 the leading block with |R_kk| > 1e-12 |R_00|, W = P [R11^{-1}; 0] (dense), R returned
  * as R_pivoted P^T; PCG then returns the basic solution on the kept columns (the others exactly zero).
  * R or W may be NULL.  NONFINITE when SA holds a NaN or an infinity (checked before factoring).  RANK
@@ -360,9 +365,10 @@ lsq_status lsq_tune(const char* key, int64_t value);
 /* Numerics options of one context (each context starts with the defaults; calls on other contexts are
  * unaffected).  Keys:
  *   "factor" (Section 1.2 names QR of S A or a Cholesky factor of H_S; Section 6 the same; pivoted QR and
- *     the SVD are the alternatives it cites): 0 = CholeskyQR2 with its fallbacks, the default; 1 =
- *     Householder QR only; 2 = the SVD form; 3 = column-pivoted QR (see lsq_factor).  The batched form
- *     keeps its own Householder QR.
+ *     the SVD are the alternatives it cites): 0 = CholeskyQR2 with its fallbacks, the default (PCG takes
+ *     one pass or two by the spread of the first factor's diagonal); 1 = Householder QR only; 2 = the SVD
+ *     form; 3 = column-pivoted QR; 4 = CholeskyQR2 everywhere; 5 = one-pass CholeskyQR everywhere (see
+ *     lsq_factor).  The batched form keeps its own Householder QR.
  *   "srht_passb" (Section 2, SRHT; which kernel evaluates the high-bit sum for buckets of more than 24
  *     selected rows on average): 0 = staged through LDS, sixteen wavefronts of one row tile each, so
  *     that up to 16 tiles of a bucket share one pass over its block of the intermediate, folding by the

@@ -66,7 +66,8 @@ struct lsq_ctx {
   int w_dense = 0;        // the last factorization's W is dense (SVD form) rather than triangular
   int svd_rank = 0, svd_sweeps = 0;
   // numerics options of this context (lsq_set_option)
-  int factor_mode = 0;    // 0 CholeskyQR2 with fallbacks, 1 Householder, 2 SVD, 3 column-pivoted QR
+  int factor_mode = 0;    // 0 CholeskyQR, second pass when needed, with fallbacks; 1 Householder; 2 SVD;
+                          // 3 column-pivoted QR; 4 CholeskyQR2 always; 5 one pass always (fallbacks of 0)
   int srht_passb = 0;     // SRHT pass B form for large buckets
   double* noalloc = nullptr;  // this device's static array for lsq_fused_pass_noalloc
   int sketch_upgrade = 1; // mixed form: an FP32 SRHT is retaken in FP64 when diag(R) spreads beyond 1e6
@@ -291,11 +292,12 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
   return LSQ_OK;
 }
 
-// Factor S A -> R, W = R^{-1}, W^T.  CholeskyQR2 (Gram matrices on the matrix cores) when the first
-// Cholesky is usable, otherwise Householder QR (m <= 8192) or shifted CholeskyQR3 (larger m); the
-// Householder form alone with lsq_tune("factor", 1).
+// Factor S A -> R, W = R^{-1}, W^T.  CholeskyQR (Gram matrices on the matrix cores): the Cholesky factor
+// of H_S when the spread of its diagonal is small, CholeskyQR2 when it is larger, Householder QR (m <= 8192)
+// or shifted CholeskyQR3 (larger m) when the first Cholesky is not usable; the other forms by the context's
+// option "factor".
 static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, int64_t lds,
-                            double* R, double* W, double* WT) {
+                            double* R, double* W, double* WT, bool pcg = false) {
   const hipStream_t st = c->st;
   double* tscr;
   CHK(wsT(c, "trinv", trinv_scratch_len(cholqr_padded(d)), &tscr));
@@ -339,10 +341,13 @@ static lsq_status do_factor(lsq_ctx* c, const double* SA, int64_t m, int64_t d, 
     return LSQ_OK;
   }
   bool done = false;
-  if (c->factor_mode == 0) {
+  if (c->factor_mode == 0 || c->factor_mode == 4 || c->factor_mode == 5) {
     double* cs;
     CHK(wsT(c, "cholqr", cholqr_scratch_len(m, d), &cs));
-    if (cholqr_factor(st, SA, m, d, lds, cs, R, c->dflags + 4, c->hflags + 4, tscr) == 0) {
+    // one pass or two by the first factor's spread for PCG, whose answer the preconditioner's last digits do
+    // not change; two for the others (IHS and FCG iterates are defined by H_S^{-1} itself)
+    const int passes = c->factor_mode == 4 ? 2 : (c->factor_mode == 5 ? 1 : (pcg ? 0 : 2));
+    if (cholqr_factor(st, SA, m, d, lds, cs, R, c->dflags + 4, c->hflags + 4, tscr, passes) == 0) {
       done = true;
     } else if (m > QR_M_MAX) {
       // the shift regularises the first pass; a breakdown in the later passes means rank deficiency
@@ -733,7 +738,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
   HIPCHK(hipEventRecord(c->ev[0], st));
   CHK(do_sketch(c, p, s, s->t, SA, d, x0_zero || o->x_ref ? &grad : nullptr, &grad_rows));
   HIPCHK(hipEventRecord(c->ev[1], st));
-  CHK(do_factor(c, SA, m, d, d, R, W, WT));
+  CHK(do_factor(c, SA, m, d, d, R, W, WT, true));
   if (o->mixed && s->kind == LSQ_SRHT && s->compute == LSQ_F32 && c->sketch_upgrade) {
     // An FP32 transform perturbs S A by about its single-precision rounding; once kappa(A) approaches
     // 1/u32 that visibly weakens the preconditioner (at kappa = 1e8, 37 PCG iterations instead of 17).
@@ -751,7 +756,7 @@ lsq_status lsq_pcg_solve(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_desc
       s64.compute = LSQ_F64;
       CHK(do_sketch(c, p, &s64, s64.t, SA, d, x0_zero || o->x_ref ? &grad : nullptr, &grad_rows));
       HIPCHK(hipEventRecord(c->ev[1], st));
-      CHK(do_factor(c, SA, m, d, d, R, W, WT));
+      CHK(do_factor(c, SA, m, d, d, R, W, WT, true));
     }
   }
   HIPCHK(hipEventRecord(c->ev[2], st));
@@ -976,7 +981,7 @@ lsq_status lsq_choose_sketch_size(lsq_ctx* c, const lsq_problem* p, const lsq_sk
       HIPCHK(hipEventRecord(c->ev[0], st));
       CHK(do_sketch(c, p, &sd, sd.t, SA, d));
       HIPCHK(hipEventRecord(c->ev[1], st));
-      CHK(do_factor(c, SA, sd.m, d, d, R, W, WT));
+      CHK(do_factor(c, SA, sd.m, d, d, R, W, WT, true));
       HIPCHK(hipEventRecord(c->ev[2], st));
       HIPCHK(hipEventSynchronize(c->ev[2]));
       float a = 0.f, f = 0.f;
@@ -1334,9 +1339,10 @@ lsq_status lsq_set_option(lsq_ctx* c, const char* key, int64_t value) {
   if (!c || !key) return fail(LSQ_ERR_INVALID_ARG, "null context or key");
   const std::string k(key);
   if (k == "factor") {
-    if (value < 0 || value > 3)
+    if (value < 0 || value > 5)
       return fail(LSQ_ERR_INVALID_ARG,
-                  "factor: 0 (CholeskyQR2), 1 (Householder), 2 (SVD) or 3 (column-pivoted QR)");
+                  "factor: 0 (CholeskyQR, second pass when needed), 1 (Householder), 2 (SVD), 3 (column-pivoted "
+                  "QR), 4 (CholeskyQR2) or 5 (one-pass CholeskyQR)");
     c->factor_mode = (int)value;
     return LSQ_OK;
   }

@@ -1,8 +1,10 @@
 // Factor step through the Gram matrix (the paper's alternative to QR of S A: a Cholesky factor of
-// H_S = (S A)^T (S A), Section 1.2 and Section 6), made backward stable by a second pass:
-// CholeskyQR2.  With X = S A (m x d):
-//     R1 = chol(X^T X),  Q1 = X R1^{-1},  R2 = chol(Q1^T Q1),  R = R2 R1,
-// and, when the first factorization breaks down, the shifted form with a third pass
+// H_S = (S A)^T (S A), Section 1.2 and Section 6).  With X = S A (m x d), R1 = chol(X^T X) is the factor
+// itself; its error (about u kappa(X)^2 relative) only matters to the preconditioner once kappa(X)^2 u is
+// no longer small, so a second pass, CholeskyQR2,
+//     Q1 = X R1^{-1},  R2 = chol(Q1^T Q1),  R = R2 R1,
+// runs only when the spread of diag(R1) exceeds CHOLQR_ONE_PASS_SPREAD (or when asked for); when the
+// first factorization breaks down, the shifted form with a third pass
 // (R1 = chol(X^T X + s I), s = 11 (m d + d (d + 1)) u ||X||_F^2).  Every product runs on the FP64
 // matrix cores (v_mfma_f64_16x16x4); the Cholesky is blocked by 64 columns (one wavefront factors the
 // diagonal block in registers and inverts it, then the block row and the trailing matrix are updated
@@ -394,9 +396,10 @@ __global__ void k_chol_extract(const double* __restrict__ Rp, int64_t dp, int64_
   R[idx] = j >= i ? Rp[i * dp + j] : 0.0;
 }
 
-// max |R_jj| / min |R_jj| > lim sets *flag (the first factor is too inaccurate for two passes).
+// The spread max |R_jj| / min |R_jj| of the first factor: above lim, *flag = 1 (too inaccurate for two passes);
+// else above lim2, *flag = 2 (the second pass is needed); else *flag stays 0.
 __global__ __launch_bounds__(1024) void k_chol_diagratio(const double* __restrict__ Rp, int64_t dp, int64_t d,
-                                                         double lim, int* __restrict__ flag) {
+                                                         double lim, double lim2, int* __restrict__ flag) {
   __shared__ double smx[16], smn[16];
   double mx = 0.0, mn = INFINITY;
   for (int64_t i = threadIdx.x; i < d; i += 1024) {
@@ -418,7 +421,10 @@ __global__ __launch_bounds__(1024) void k_chol_diagratio(const double* __restric
       mx = fmax(mx, smx[w]);
       mn = fmin(mn, smn[w]);
     }
-    if (!(mx <= lim * mn)) *flag = 1;
+    if (!(mx <= lim * mn))
+      *flag = 1;
+    else if (!(mx <= lim2 * mn))
+      *flag = 2;
   }
 }
 
@@ -481,7 +487,7 @@ static void cq_pass(hipStream_t st, const double* X, int64_t m, int64_t d, int64
 }
 
 int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
-                  double* R, int* flags, int* hflags, double* trinv_scratch) {
+                  double* R, int* flags, int* hflags, double* trinv_scratch, int passes) {
   const int64_t dp = cholqr_padded(d);
   const int S = gram_splits(m, dp);
   double* part = scratch;
@@ -495,13 +501,21 @@ int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_
   double* Q2 = Q + (size_t)m * dp;
   double* shift = Q2 + (size_t)m * dp;
   const dim3 gx((unsigned)((m + CQ_T - 1) / CQ_T), (unsigned)(dp / CQ_T));
-  // pass 1, then a check that it is usable for two passes
+  // pass 1, then a check that it is usable for two passes, and whether it is accurate enough alone
   hipMemsetAsync(flags, 0, 2 * sizeof(int), st);
   cq_pass(st, SA, m, d, lds, dp, part, G, nullptr, Ra, Dinv, flags);
-  hipLaunchKernelGGL(k_chol_diagratio, dim3(1), dim3(1024), 0, st, Ra, dp, d, 1e7, flags + 1);
+  hipLaunchKernelGGL(k_chol_diagratio, dim3(1), dim3(1024), 0, st, Ra, dp, d, 1e7, CHOLQR_ONE_PASS_SPREAD,
+                     flags + 1);
   hipMemcpyAsync(hflags, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st);
   hipStreamSynchronize(st);
-  if (hflags[0] || hflags[1]) return 1;  // caller chooses the robust path
+  if (hflags[0] || hflags[1] == 1) return 1;  // caller chooses the robust path
+  if (passes == 1 || (passes == 0 && hflags[1] == 0)) {
+    // R = chol(X^T X), the Cholesky factor of H_S itself.  Its error (about u kappa^2 relative, against
+    // u kappa after the second pass) only perturbs the preconditioned operator R^{-T} A^T A R^{-1} by a
+    // factor 1 + O(u kappa^2): invisible in the PCG iteration count while the spread is small.
+    hipLaunchKernelGGL(k_chol_extract, dim3((unsigned)((d * d + 255) / 256)), dim3(256), 0, st, Ra, dp, d, R);
+    return 0;
+  }
   // Q1 = X R1^{-1}; pass 2 on Q1; R = R2 R1
   tri_inverse_padded(st, Ra, dp, Wt, trinv_scratch);
   launch_xw(st, gx, SA, m, d, lds, Wt, dp, Q);

@@ -97,7 +97,9 @@ void qr_rank_check(hipStream_t st, const double* R, int64_t d, int* status);
 int64_t cholqr_padded(int64_t d);
 size_t cholqr_scratch_len(int64_t m, int64_t d);
 int cholqr_factor(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
-                  double* R, int* flags, int* hflags, double* trinv_scratch);
+                  double* R, int* flags, int* hflags, double* trinv_scratch, int passes = 2);
+// Spread of diag(R) of the first CholeskyQR pass up to which the automatic form stops after that pass.
+constexpr double CHOLQR_ONE_PASS_SPREAD = 2e5;
 // Shifted CholeskyQR3 (any full-rank SA up to kappa ~ 1/u).  flags: 1 device int.
 int cholqr3_shifted(hipStream_t st, const double* SA, int64_t m, int64_t d, int64_t lds, double* scratch,
                     double* R, int* flags, double* trinv_scratch);

@@ -253,28 +253,43 @@ def test_gaussian_sketch(ctx, n, d, m):
 # ----------------------------------------------------------------------------------------------
 # factor
 # ----------------------------------------------------------------------------------------------
+def factor_amplification(Ro, kappa, mode):
+    """How the factor's forward error grows with kappa: kappa for a backward-stable R (Householder,
+    CholeskyQR2, shifted CholeskyQR3: lsq_factor's default), kappa^2 for the one-pass Cholesky factor of
+    X^T X (option 5)."""
+    one_pass = mode == 5
+    return kappa * kappa if one_pass else kappa
+
+
+@pytest.mark.parametrize("mode", [0, 5])
 @pytest.mark.parametrize("m,d,kappa", [(16, 3, 10.0), (256, 64, 1e3), (700, 129, 1e6), (1500, 300, 1e4),
                                        (2048, 512, 1e8), (4100, 1024, 1e4)])
-def test_factor(ctx, m, d, kappa):
+def test_factor(ctx, m, d, kappa, mode):
     from oracle.householder import householder_qr
     from synth import make_problem
     torch = _torch()
-    say("factor", m, d, kappa)
+    say("factor", m, d, kappa, mode)
     X = make_problem(m, d, kappa, seed=m)["A"]
     R = torch.empty((d, d), dtype=torch.float64, device="cuda")
     W = torch.empty((d, d), dtype=torch.float64, device="cuda")
-    ctx.factor(dev(X), R, W)
+    ctx.set_option("factor", mode)
+    try:
+        ctx.factor(dev(X), R, W)
+    finally:
+        ctx.set_option("factor", 0)
     Rg, Wg = host(R), host(W)
     Ro = householder_qr(X)
+    amp = factor_amplification(Ro, kappa, mode)
     assert np.all(np.diag(Rg) > 0) and np.allclose(np.tril(Rg, -1), 0)
-    # backward-stable QR: R^T R reproduces X^T X to O(eps) relative to ||X||^2
+    # R^T R reproduces X^T X to O(eps) relative to ||X||^2 (the Gram rounding and the Cholesky's backward
+    # error; QR's backward error for the two-pass forms)
     nx2 = np.linalg.norm(X, 2) ** 2
     assert np.abs(Rg.T @ Rg - X.T @ X).max() <= 50 * m * EPS * nx2
-    # R itself is unique; rows agree to O(eps kappa)
-    assert np.abs(Rg - Ro).max() <= 50 * m * EPS * kappa * np.abs(Ro).max()
-    # X R^{-1} has orthonormal columns
+    # R itself is unique; rows agree to O(eps kappa) (O(eps kappa^2) for the Cholesky factor of X^T X)
+    assert np.abs(Rg - Ro).max() <= 50 * m * EPS * amp * np.abs(Ro).max()
+    # X R^{-1} has orthonormal columns to the same order
     Q = X @ Wg
-    assert np.abs(Q.T @ Q - np.eye(d)).max() <= 1e3 * m * EPS * kappa
+    assert np.abs(Q.T @ Q - np.eye(d)).max() <= 1e3 * m * EPS * amp
 
 
 def test_factor_rank_deficient(ctx):
