@@ -720,8 +720,26 @@ def main():
             f"({res[form]['fused_gbs']:.0f} GB/s)")
     # the measured read ceiling over the largest operand (the bare streaming read of lsq_read_bandwidth)
     read_peak = ctx.read_bandwidth(A32 if A32 is not None else A64, reps=3)
-    log(f"[bench] measured read ceiling {read_peak:.0f} GB/s")
+    # and the read + write ceiling (bare streaming copy of 4 GiB of the same matrix)
+    src = (A32 if A32 is not None else A64).view(-1)[: (1 << 30) // (A32 if A32 is not None else A64).element_size() * 4]
+    dst = torch.empty_like(src)
+    copy_peak = ctx.copy_bandwidth(src, dst, reps=3)
+    del src, dst
+    log(f"[bench] measured read ceiling {read_peak:.0f} GB/s, read + write ceiling {copy_peak:.0f} GB/s")
     ctx.close()
+    # the SRHT's two passes at those ceilings: pass A reads A and writes the intermediate T (N rows of the
+    # transform's precision), pass B reads T once
+    sketch_floor = None
+    if a.sketch == "srht":
+        sketch_floor = {}
+        nN = 1 << (a.n - 1).bit_length()
+        for form in res:
+            ab = a.n * a.d * (8 if form == "fp64" else 4)
+            tb = nN * a.d * (8 if comp_form[form] == "f64" else 4)
+            floor = ((ab + tb) / copy_peak + tb / read_peak) / 1e6
+            meas = res[form]["info"]["t_sketch_ms"]
+            sketch_floor[form] = {"pass_a_bytes": ab + tb, "pass_b_bytes": tb, "floor_ms": round(floor, 3),
+                                  "measured_ms": round(meas, 3), "frac": round(floor / meas, 4)}
 
     head = "mixed" if "mixed" in res else forms[0]
     h = res[head]
@@ -773,10 +791,12 @@ def main():
                      "traffic": counter_traffic(a.n, a.d, head,
                                                 tuned.get(head, {}).get("fused_groups_per_cu", 8)),
                      "measured_read_peak": round(read_peak, 1),
+                     "measured_copy_peak": round(copy_peak, 1),
                      "frac_of_measured": round(h["fused_gbs"] / read_peak, 4),
                      "kernel": "k_fused (A^T(A p), one pass)",
                      "bytes_per_launch": h["bytes_per_pass"], "avg_launch_ms": round(h["fused_ms"], 4),
                      "launches": h["launches"]},
+        "sketch_floor": sketch_floor,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -348,6 +348,15 @@ lsq_status lsq_fused_pass_timing(lsq_ctx* ctx, int32_t reset, double* last_ms, d
  * buffer. */
 lsq_status lsq_read_bandwidth(lsq_ctx* ctx, const void* buf, int64_t bytes, int32_t reps, double* gbs);
 
+/* Measured read + write ceiling, the reference for kernels that stream one buffer in and another out
+ * (the SRHT's first pass): the whole 16-byte vectors of src (device, `bytes` long) are copied to dst
+ * (device, same length, not overlapping src; both 16-byte aligned) `reps` times by a bare streaming-copy
+ * kernel (16-byte non-temporal loads and stores) at 4, 8 and 16 workgroups per compute unit; *gbs (host)
+ * receives the best rate in GB/s counting both directions (2 bytes moved per byte copied).  Synchronous.
+ * INVALID_ARG for null pointers, bytes < 16, reps < 1, misaligned or overlapping buffers. */
+lsq_status lsq_copy_bandwidth(lsq_ctx* ctx, const void* src, void* dst, int64_t bytes, int32_t reps,
+                              double* gbs);
+
 /* Process-wide launch parameters, set by the autotuner (paper_1911_02675_amd/autotune.py) from its
  * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
  * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);

@@ -43,7 +43,7 @@ struct lsq_ctx {
   std::map<std::string, std::pair<void*, size_t>> bufs;
   DevState* ds = nullptr;   // device
   DevState* hds = nullptr;  // pinned host mirror
-  int* dflags = nullptr;    // device ints: [0] factor status, [1] SJLT draw error, [2] nneeded,
+  int* dflags = nullptr;    // device ints: [0] factor status, [1] SJLT draw error, [2] SRHT buckets used,
                             // [4], [5] CholeskyQR breakdown / spread flags
   int* hflags = nullptr;    // pinned host mirror (8 ints)
   hipEvent_t ev[6] = {};
@@ -224,9 +224,9 @@ static lsq_status do_sketch(lsq_ctx* c, const lsq_problem* p, const lsq_sketch_d
     CHK(wsT(c, "srht_order", s->m, &order));
     CHK(wsT(c, "srht_bstart", plan.N1 + 1, &bstart));
     srht_plan_groups(st, rows, s->m, plan.N1, slot, order, bstart, c->dflags + 2);
-    HIPCHK(hipMemcpyAsync(c->hflags + 2, c->dflags + 2, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
-    plan.nneeded = c->hflags[2];
+    // T is sized for every bucket a selected row can fall in (the count of distinct buckets stays on the
+    // device, so the sketch needs no host round trip)
+    plan.nneeded = (int)std::min<int64_t>(plan.N1, s->m);
     const int cf32 = s->compute == LSQ_F32;
     void* tbuf;
     CHK(ws(c, "srht_tbuf", srht_tbuf_bytes(plan.N2, plan.nneeded, p->d, cf32), &tbuf));
@@ -642,6 +642,33 @@ lsq_status lsq_fused_pass_noalloc(lsq_ctx* c, const lsq_problem* p, int32_t mode
   vec_copy(c->st, w, red, p->d);
   vec_copy(c->st, scal, red + p->d, 1);
   HIPCHK(hipGetLastError());
+  return LSQ_OK;
+}
+
+lsq_status lsq_copy_bandwidth(lsq_ctx* c, const void* src, void* dst, int64_t bytes, int32_t reps, double* gbs) {
+  if (!c || !src || !dst || !gbs) return fail(LSQ_ERR_INVALID_ARG, "null context, buffer or output");
+  if (bytes < 16 || reps < 1) return fail(LSQ_ERR_INVALID_ARG, "need bytes >= 16 and reps >= 1");
+  if ((uintptr_t)src % 16 || (uintptr_t)dst % 16) return fail(LSQ_ERR_INVALID_ARG, "buffers must be 16-byte aligned");
+  const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+  if (s0 < d0 + (uintptr_t)bytes && d0 < s0 + (uintptr_t)bytes)
+    return fail(LSQ_ERR_INVALID_ARG, "source and destination overlap");
+  int cus = 0;
+  HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev));
+  double best = 0.0;
+  for (int gpc : {4, 8, 16}) {
+    const int groups = std::max(cus, 1) * gpc;
+    stream_copy(c->st, src, dst, bytes, groups);  // warm-up
+    HIPCHK(hipEventRecord(c->ev[4], c->st));
+    for (int r = 0; r < reps; ++r) stream_copy(c->st, src, dst, bytes, groups);
+    HIPCHK(hipEventRecord(c->ev[5], c->st));
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipEventSynchronize(c->ev[5]));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, c->ev[4], c->ev[5]));
+    const double rate = 2.0 * (double)(bytes / 16 * 16) * reps / (ms * 1e-3) / 1e9;
+    best = std::max(best, rate);
+  }
+  *gbs = best;
   return LSQ_OK;
 }
 

@@ -37,12 +37,12 @@ void exclusive_scan_i32(hipStream_t st, const int* in, int* out, int64_t len, in
 // remaining high bits are summed directly for the selected rows only.
 struct SrhtPlan {
   int64_t N, N1, N2, m;
-  int nneeded;             // distinct k_lo among the selected rows
+  int nneeded;             // buckets T is sized for: min(N1, m), at least the distinct k_lo selected
   int passb = 0;           // form of pass B for large buckets (lsq_set_option "srht_passb")
 };
 size_t srht_tbuf_bytes(int64_t N2, int64_t nneeded, int64_t d, int compute_f32);
 // Groups the selected rows by k_lo: slot (N1 ints, -1 if unused), order (m ints), bstart (N1+1 ints).
-// Host-side planning needs nneeded: computed on device and copied back (one sync).
+// The count of distinct k_lo is left on the device (nneeded_dev); the host sizes T for min(N1, m) buckets.
 void srht_plan_groups(hipStream_t st, const int64_t* rows, int64_t m, int64_t N1, int* slot,
                       int* order, int* bstart, int* nneeded_dev);
 size_t srht_partial_bytes(int64_t N2, int64_t m, int64_t d);
@@ -151,6 +151,7 @@ extern int g_batched_slots;         // tuning: batched-kernel workgroups (0 = on
 // Bare streaming read of the first bytes / 16 whole 16-byte vectors of buf (device, 16-byte aligned) by
 // `groups` workgroups, each writing its sum to out[group] (for measuring the read ceiling).
 void stream_read(hipStream_t st, const void* buf, int64_t bytes, int groups, float* out);
+void stream_copy(hipStream_t st, const void* src, void* dst, int64_t bytes, int groups);
 // Partial sums are reduced in two fixed-order stages: nwg rows -> REDUCE_SPLIT rows -> 1.
 constexpr int REDUCE_SPLIT = 32;
 void reduce_stage1(hipStream_t st, const double* part, int nwg, int64_t d, double* part2,

@@ -29,6 +29,28 @@ __global__ __launch_bounds__(READ_NT) void k_stream_read(const probe_f4* __restr
   if (threadIdx.x == 0) out[blockIdx.x] = ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
+// Bare streaming copy: the measured ceiling of a kernel that reads one buffer and writes another of the
+// same size (the SRHT's first pass reads A and writes its intermediate).  Each workgroup copies the
+// 16-byte vectors of a contiguous slice with non-temporal loads and stores, two vectors in flight per lane.
+__global__ __launch_bounds__(READ_NT) void k_stream_copy(const probe_f4* __restrict__ src, probe_f4* __restrict__ dst,
+                                                         int64_t nvec) {
+  const int64_t per = (nvec + gridDim.x - 1) / gridDim.x;
+  const int64_t v0 = (int64_t)blockIdx.x * per, v1 = min(nvec, v0 + per);
+  int64_t i = v0 + threadIdx.x;
+  for (; i + READ_NT < v1; i += 2 * READ_NT) {
+    const probe_f4 a = __builtin_nontemporal_load(src + i);
+    const probe_f4 b = __builtin_nontemporal_load(src + i + READ_NT);
+    __builtin_nontemporal_store(a, dst + i);
+    __builtin_nontemporal_store(b, dst + i + READ_NT);
+  }
+  if (i < v1) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+}
+
+void stream_copy(hipStream_t st, const void* src, void* dst, int64_t bytes, int groups) {
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)groups), dim3(READ_NT), 0, st, (const probe_f4*)src,
+                     (probe_f4*)dst, bytes / 16);
+}
+
 void stream_read(hipStream_t st, const void* buf, int64_t bytes, int groups, float* out) {
   hipLaunchKernelGGL(k_stream_read, dim3((unsigned)groups), dim3(READ_NT), 0, st, (const probe_f4*)buf, bytes / 16,
                      out);

@@ -20,7 +20,7 @@ DTYPES = {"f64": LSQ_F64, "f32": LSQ_F32, "bf16": LSQ_BF16}
 EXPORTED = [
     "lsq_create", "lsq_destroy", "lsq_sketch", "lsq_factor", "lsq_fused_pass", "lsq_pcg_solve",
     "lsq_ihs_solve", "lsq_fcg_solve", "lsq_pcg_solve_batched", "lsq_draw_srht", "lsq_draw_sjlt", "lsq_draw_gaussian",
-    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_read_bandwidth", "lsq_choose_sketch_size", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
+    "lsq_fused_pass_noalloc", "lsq_fused_pass_timing", "lsq_read_bandwidth", "lsq_copy_bandwidth", "lsq_choose_sketch_size", "lsq_tune", "lsq_set_option", "lsq_status_string", "lsq_last_error", "lsq_version",
 ]
 
 
@@ -104,6 +104,7 @@ def load():
         "lsq_draw_gaussian": ([P, U64, U64, I64, I64, I64, P], I32),
         "lsq_fused_pass_timing": ([P, I32, C.POINTER(D), C.POINTER(D), C.POINTER(I64)], I32),
         "lsq_read_bandwidth": ([P, P, I64, I32, C.POINTER(D)], I32),
+        "lsq_copy_bandwidth": ([P, P, P, I64, I32, C.POINTER(D)], I32),
         "lsq_choose_sketch_size": ([P, C.POINTER(Problem), C.POINTER(SketchDesc), D, D, I32, C.POINTER(MsizeEntry),
                                     I32, C.POINTER(I32), C.POINTER(I64), C.POINTER(D)], I32),
         "lsq_tune": ([C.c_char_p, I64], I32),
@@ -286,6 +287,13 @@ class Context:
                                                C.byref(cnt), C.byref(mb), C.byref(tp)))
         rows = [{k: getattr(tab[i], k) for k, _ in MsizeEntry._fields_ if k != "pad_"} for i in range(cnt.value)]
         return mb.value, rows, tp.value
+
+    def copy_bandwidth(self, src, dst, reps=5):
+        """Measured read + write ceiling (GB/s, both directions) copying src to dst (see lsq_copy_bandwidth)."""
+        g = C.c_double()
+        nb = min(src.numel() * src.element_size(), dst.numel() * dst.element_size())
+        _check(self.lib.lsq_copy_bandwidth(self.h, _ptr(src), _ptr(dst), nb, reps, C.byref(g)))
+        return g.value
 
     def read_bandwidth(self, buf, reps=5):
         """Measured read ceiling (GB/s) over the device tensor buf (see lsq_read_bandwidth)."""
