@@ -361,9 +361,11 @@ lsq_status lsq_copy_bandwidth(lsq_ctx* ctx, const void* src, void* dst, int64_t 
  * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
  * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);
  * "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute unit, else
- * 1..65536); "srht_fold8_rows_f32" / "srht_fold8_rows_f64" (the SRHT's LDS-staged second pass folds by
+ * 1..65536); "srht_fold8_rows_f32" / "srht_fold8_rows_f64" (the SRHT's staged second pass folds by
  * the 8-point transform, rather than the 4-point one, from this many selected rows per 256-row bucket on
- * average, FP32 / FP64 intermediate; defaults 64 / 128); "srht_passa_wgs" (workgroups the SRHT's first
+ * average, FP32 / FP64 intermediate; defaults 64 / 128); "srht_stream_rows_f32" / "srht_stream_rows_f64"
+ * (from this many rows per bucket the streamed form with the 16-point fold; default 192 for both);
+ * "srht_passa_wgs" (workgroups the SRHT's first
  * pass aims at, 0 = 2^17 for an FP32 transform and 2^15 for FP64, the default); "srht_passb_wgs"
  * (workgroups the LDS-staged second pass aims at when splitting its sums over j_hi, default 8192);
  * "gauss_wgs" (workgroups the Gaussian sketch aims at when splitting the rows of A, default 1024);
@@ -379,13 +381,17 @@ lsq_status lsq_tune(const char* key, int64_t value);
  *     form; 3 = column-pivoted QR; 4 = CholeskyQR2 everywhere; 5 = one-pass CholeskyQR everywhere (see
  *     lsq_factor).  The batched form keeps its own Householder QR.
  *   "srht_passb" (Section 2, SRHT; which kernel evaluates the high-bit sum for buckets of more than 24
- *     selected rows on average): 0 = staged through LDS, sixteen wavefronts of one row tile each, so
- *     that up to 16 tiles of a bucket share one pass over its block of the intermediate, folding by the
- *     8-point transform when a bucket averages 64 rows or more (FP32 intermediate) or 128 rows or more
- *     (FP64) and by the 4-point one otherwise, the default; 1 = operands loaded straight into registers
- *     (FP32 intermediate; the FP64 one takes its general form); 2 = staged through LDS, eight
- *     wavefronts, 4-point fold; 3 = sixteen wavefronts, 4-point fold; 4 = sixteen wavefronts, 8-point
- *     fold.  Every form computes the same sums (exactly, for integer-valued A).
+ *     selected rows on average): 0 = by the average bucket size, the default: staged through registers
+ *     into LDS, sixteen wavefronts of one row tile each (up to 16 tiles of a bucket share one pass over
+ *     its block of the intermediate), folding by the 8-point transform from "srht_fold8_rows_f32" /
+ *     "_f64" rows per bucket (lsq_tune; 64 / 128) and by the 4-point one below; from
+ *     "srht_stream_rows_f32" / "_f64" rows (192) the intermediate streamed into LDS by the memory system
+ *     (no staging registers) and folded there in place by the 16-point transform, eight wavefronts of up
+ *     to four tiles each (up to 32 tiles per pass); 1 = operands loaded straight into registers (FP32
+ *     intermediate; the FP64 one takes its general form); 2 = staged, eight wavefronts, 4-point fold;
+ *     3 = staged, sixteen wavefronts, 4-point fold; 4 = the same with the 8-point fold; 5 and 6 =
+ *     streamed with the 8- and the 16-point fold.  Every form computes the same sums (exactly, for
+ *     integer-valued A).
  *   "sketch_upgrade" (the precision form, mixed = 1, with an SRHT in FP32): 1 = after the factorization
  *     the spread max |R_ii| / min |R_ii| (about kappa(A) / 25 for tall A) is checked, and above 1e6 the
  *     sketch and factor are taken again with an FP64 transform of the same FP32 A, because the FP32

@@ -12,10 +12,12 @@ Knobs measured (see lsq_tune in include/lsq.h), each as the fastest of a few can
   srht_passa_wgs       workgroups of the SRHT's first pass, per transform precision and d bucket (timed
                        at m = 4d, where the second pass is small);
   srht_passb_wgs       workgroups of the LDS-staged second pass (timed at m = 40 d);
-  srht_fold8_rows_*    from how many selected rows per 256-row bucket the second pass folds by the
-                       8-point transform instead of the 4-point one (both forms timed at 32..192 rows per
+  srht_fold8_rows_*    from how many selected rows per 256-row bucket the staged second pass folds by
+                       the 8-point transform instead of the 4-point one (both timed at 32..256 rows per
                        bucket; the threshold is the smallest count from which the 8-point form stays
                        faster);
+  srht_stream_rows_*   from how many rows per bucket the streamed second pass (16-point fold) replaces
+                       the staged one (the 8-point staged form against the streamed one at 32..256 rows);
   gauss_wgs            workgroups of the Gaussian sketch (FP64 form, n = 2^20, d = 512, m = 2048);
   gram_wgs             workgroups of the CholeskyQR Gram kernel, per d bucket (the factor of an m = 40 d
                        sketch).
@@ -25,7 +27,7 @@ chip is never applied to another:
   {"gfx950:sramecc+:xnack-": {"fused_groups_per_cu": {"f32": {"64": 8, ...}, "f64": {...}},
                               "batched_slots": 192,
                               "srht": {"f32": {"256": {"srht_passa_wgs": ..., "srht_passb_wgs": ...,
-                                                       "fold8_rows": ...}, "1024": {...}}, "f64": {...}},
+                                                       "fold8_rows": ..., "stream_rows": ...}, "1024": {...}}, "f64": {...}},
                               "gauss_wgs": 1024, "gram_wgs": {"256": ..., "1024": ...},
                               "measured": {...raw timings...}}}
 apply(dtype, d) picks the entry of the bucket that contains d (the largest bucket not above d; the
@@ -46,12 +48,13 @@ GPC_CANDIDATES = (2, 4, 8, 16)
 SLOT_CANDIDATES = (128, 192, 256)
 PASSA_CANDIDATES = (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
 PASSB_CANDIDATES = (4096, 8192, 16384)
-FOLD_ROWS = (32, 48, 64, 96, 128, 160, 192)
+FOLD_ROWS = (32, 48, 64, 96, 128, 160, 192, 256)
 GAUSS_CANDIDATES = (512, 1024, 2048, 4096)
 GRAM_CANDIDATES = (1024, 2048, 4096)
 # library defaults, restored after measuring
 DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
-            "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128, "gauss_wgs": 1024, "gram_wgs": 2048}
+            "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128,
+            "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gram_wgs": 2048}
 
 
 def table_path():
@@ -107,8 +110,9 @@ def choose(entry, dtype="f32", d=1024):
     # the fold threshold is held per transform precision: both, since a solve may change its transform
     for prec in ("f32", "f64"):
         sp = _by_bucket(srht.get(prec, {}), d)
-        if sp:
-            out["srht_fold8_rows_" + prec] = int(sp["fold8_rows"])
+        for key in ("fold8_rows", "stream_rows"):
+            if sp and key in sp:
+                out["srht_" + key + "_" + prec] = int(sp[key])
     if "gauss_wgs" in entry:
         out["gauss_wgs"] = int(entry["gauss_wgs"])
     gw = _by_bucket(entry.get("gram_wgs", {}), d)
@@ -220,13 +224,13 @@ def _time_ms(fn, reps):
     return best
 
 
-def _fold_threshold(t4, t8):
-    """The smallest rows-per-bucket count from which the 8-point form is faster at every larger count
+def _fold_threshold(t_narrow, t_wide):
+    """The smallest rows-per-bucket count from which the wider fold is faster at every larger count
     measured (one past the largest when it never wins)."""
-    rows = sorted(t4)
+    rows = sorted(t_narrow)
     thr = rows[-1] + 1
     for r in reversed(rows):
-        if t8[r] < t4[r]:
+        if t_wide[r] < t_narrow[r]:
             thr = r
         else:
             break
@@ -245,7 +249,7 @@ def measure_srht(ctx, quick=False):
             A = torch.randn(n, d, dtype=tdt, device="cuda")
             y = torch.zeros(n, dtype=torch.float64, device="cuda")
             N = 1 << (n - 1).bit_length()
-            rec = {"n": n, "d": d, "passa": {}, "passb": {}, "fold4": {}, "fold8": {}}
+            rec = {"n": n, "d": d, "passa": {}, "passb": {}, "fold4": {}, "fold8": {}, "stream16": {}}
 
             def sk(m):
                 SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
@@ -266,7 +270,7 @@ def measure_srht(ctx, quick=False):
                     m = rows * 256
                     if m > N or m > 65536:
                         continue
-                    for mode, key in ((3, "fold4"), (4, "fold8")):
+                    for mode, key in ((3, "fold4"), (4, "fold8"), (6, "stream16")):
                         ctx.set_option("srht_passb", mode)
                         rec[key][str(rows)] = round(_time_ms(sk(m), reps), 4)
             finally:
@@ -333,7 +337,9 @@ def tune(quick=False, path=None):
              "batched_slots": int(max(batched, key=batched.get)),
              "srht": {dt: {b: {"srht_passa_wgs": _argmin(rec["passa"]), "srht_passb_wgs": _argmin(rec["passb"]),
                                "fold8_rows": _fold_threshold({int(k): v for k, v in rec["fold4"].items()},
-                                                             {int(k): v for k, v in rec["fold8"].items()})}
+                                                             {int(k): v for k, v in rec["fold8"].items()}),
+                               "stream_rows": _fold_threshold({int(k): v for k, v in rec["fold8"].items()},
+                                                              {int(k): v for k, v in rec["stream16"].items()})}
                           for b, rec in per.items()} for dt, per in srht.items()},
              "gauss_wgs": _argmin(gauss),
              "gram_wgs": {b: _argmin(row) for b, row in gram.items()},

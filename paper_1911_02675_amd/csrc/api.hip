@@ -1348,6 +1348,8 @@ lsq_status lsq_tune(const char* key, int64_t value) {
   };
   const Knob knobs[] = {{"srht_fold8_rows_f32", &g_srht_fold8_rows_f32, 1, 1 << 20},
                         {"srht_fold8_rows_f64", &g_srht_fold8_rows_f64, 1, 1 << 20},
+                        {"srht_stream_rows_f32", &g_srht_stream_rows_f32, 1, 1 << 20},
+                        {"srht_stream_rows_f64", &g_srht_stream_rows_f64, 1, 1 << 20},
                         {"srht_passa_wgs", &g_srht_passa_wgs, 0, 1 << 22},
                         {"srht_passb_wgs", &g_srht_passb_wgs, 256, 1 << 20},
                         {"gauss_wgs", &g_gauss_wgs, 64, 1 << 16},
@@ -1374,10 +1376,11 @@ lsq_status lsq_set_option(lsq_ctx* c, const char* key, int64_t value) {
     return LSQ_OK;
   }
   if (k == "srht_passb") {
-    if (value < 0 || value > 4)
+    if (value < 0 || value > 6)
       return fail(LSQ_ERR_INVALID_ARG,
-                  "srht_passb: 0 (LDS-staged, fold width by bucket size, the default), 1 (register-direct), "
-                  "2 (LDS-staged, 8 wavefronts), 3 (16 wavefronts, 4-point fold) or 4 (16 wavefronts, 8-point fold)");
+                  "srht_passb: 0 (form and fold width by bucket size, the default), 1 (register-direct), 2 "
+                  "(register-staged, 8 wavefronts), 3 (16 wavefronts, 4-point fold), 4 (16 wavefronts, 8-point "
+                  "fold), 5 (streamed into LDS, 8-point fold) or 6 (streamed, 16-point fold)");
     c->srht_passb = (int)value;
     return LSQ_OK;
   }

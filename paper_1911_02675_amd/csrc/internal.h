@@ -142,6 +142,8 @@ int fused_nwg(int64_t n, int64_t d);
 // a grid or a kernel form that computes the same sums (in another fixed order at most).
 extern int g_srht_fold8_rows_f32;   // SRHT pass B: 8-point fold from this many selected rows per bucket (FP32 T)
 extern int g_srht_fold8_rows_f64;   // the same for an FP64 intermediate
+extern int g_srht_stream_rows_f32;  // SRHT pass B: the streamed form from this many rows per bucket (FP32 T)
+extern int g_srht_stream_rows_f64;  // the same for an FP64 intermediate
 extern int g_srht_passa_wgs;        // SRHT pass A: workgroups aimed at (0: by the transform precision)
 extern int g_srht_passb_wgs;        // LDS-staged SRHT pass B: workgroups aimed at when splitting j_hi
 extern int g_gauss_wgs;             // Gaussian sketch: workgroups aimed at when splitting n

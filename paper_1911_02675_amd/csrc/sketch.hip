@@ -18,11 +18,15 @@
 // result is bitwise reproducible.
 #include "internal.h"
 
+#include <type_traits>
+
 namespace lsq {
 
 constexpr int SRHT_N1_MAX = 512;
 int g_srht_fold8_rows_f32 = 64;
 int g_srht_fold8_rows_f64 = 128;
+int g_srht_stream_rows_f32 = 192;
+int g_srht_stream_rows_f64 = 192;
 int g_srht_passa_wgs = 0;
 int g_srht_passb_wgs = 8192;
 
@@ -829,20 +833,24 @@ __device__ __forceinline__ void lds_barrier() {
 // e = k_hi mod F (F = 2^FB, the width of the fold) in tiles of 16 (the order of rows inside a tile does not
 // change any output row; empty slots stay -1): one thread per row places itself with an LDS counter per
 // group.  All threads of the workgroup call it; returns the tile count.
-struct SrhtTiles {
-  int tq[SRHT_LMAXT][16];        // order[] positions of the tile's rows (-1: empty)
-  uint32_t tka[SRHT_LMAXT][16];  // k_a = k_hi >> FB of each row
-  int te[SRHT_LMAXT];            // e of the tile
-  int cnt[8], tbase[8], nt;
+template <int MAXT>
+struct SrhtTilesT {
+  static constexpr int LMAXT = MAXT;
+  int tq[MAXT][16];        // order[] positions of the tile's rows (-1: empty)
+  uint32_t tka[MAXT][16];  // k_a = k_hi >> FB of each row
+  int te[MAXT];            // e of the tile
+  int cnt[16], tbase[16], nt;
 };
+typedef SrhtTilesT<SRHT_LMAXT> SrhtTiles;
 
-template <int FB>
-__device__ __forceinline__ int srht_tile_build(SrhtTiles& S, int cb, int ce, const int64_t* __restrict__ rows,
+template <int FB, typename TS>
+__device__ __forceinline__ int srht_tile_build(TS& S, int cb, int ce, const int64_t* __restrict__ rows,
                                                const int* __restrict__ order, int L1) {
   constexpr int F = 1 << FB;
+  static_assert(F <= 16, "fold width");
   const int tid = threadIdx.x;
   __syncthreads();  // the previous chunk's tiles are no longer read
-  for (int i = tid; i < SRHT_LMAXT * 16; i += blockDim.x) S.tq[i / 16][i % 16] = -1;
+  for (int i = tid; i < TS::LMAXT * 16; i += blockDim.x) S.tq[i / 16][i % 16] = -1;
   if (tid < F) S.cnt[tid] = 0;
   __syncthreads();
   int e_me = 0, slot_me = 0;
@@ -1107,6 +1115,282 @@ __global__ __launch_bounds__(64 * NW, 1) void k_srht_passB_u(const TC* __restric
   }
 }
 
+// Pass B over large buckets with the intermediate streamed into LDS by the memory system itself
+// (global_load_lds, 16 bytes per lane; no staging registers) and folded there in place.  A stage is
+// SR = F JA consecutive rows j_hi of the bucket's 64-column stripe of T (16 KB, or 32 KB for the FP64
+// 16-point fold; one contiguous range of the stripe layout), and NBUF = 128 KB / stage buffers rotate:
+// while the matrix cores consume stage s, stage s + 1 is folded in place and stages s + 2 .. s + NBUF - 1
+// are in flight (96 KB per CU with 16 KB stages, enough to cover the memory latency at this CU's share
+// of the bandwidth), so each wave waits (vmcnt) only for its own loads of stage s + 1 before the one
+// barrier per stage.  In place: the rows of stage buffer position (j_a, b) = row F j_a + b, column c,
+// become U_e[j_a] at position (j_a, e), the thread of unit (j_a, c) reading its F values, transforming
+// and writing them back.
+//   Eight wavefronts (two per SIMD, up to 256 registers each) carry up to QT tiles of 16 rows each, so one
+// sweep over the bucket's T block serves up to 8 QT tiles: with the 16-point fold, about 16 + (rows - 256)
+// / 16 tiles once a bucket passes 256 selected rows, which keeps sketches of m up to about 2^17 at one
+// read of T.  The tile of wavefront w, slot q is tile tg + w + 8 q of the chunk's list.  Signs, operand
+// layouts, chain lengths and the FP64 folding of the FP32 chains are those of k_srht_passB_u.
+constexpr int SRHT2_NW = 8;
+constexpr int SRHT2_LDS = 131072;                       // bytes of stage buffers
+constexpr int SRHT2_LROWS = 64 * SRHT2_NW;              // rows of a bucket per tile build (one thread each)
+typedef SrhtTilesT<SRHT2_LROWS / 16 + 16> SrhtTiles2;   // up to 16 fold groups
+
+template <typename TC, int FB>
+struct Srht2Shape {
+  static constexpr int STG = 32768;  // bytes per stage
+  static constexpr int NBUF = SRHT2_LDS / STG;
+};
+
+__device__ __forceinline__ void srht_dma16(const void* src, void* lds) {
+  __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+
+template <int N>
+__device__ __forceinline__ void srht_vm_wait() {
+  // vmcnt(N) (bits 3:0 and 15:14), expcnt and lgkmcnt unconstrained
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// vmcnt(k IPT) for a runtime k in [0, KMAX] (the waitcnt operand is an immediate)
+template <int IPT, int KMAX>
+__device__ __forceinline__ void srht_vm_wait_stages(int k) {
+  if constexpr (KMAX <= 0) {
+    srht_vm_wait<0>();
+  } else {
+    if (k >= KMAX)
+      srht_vm_wait<KMAX * IPT>();
+    else
+      srht_vm_wait_stages<IPT, KMAX - 1>(k);
+  }
+}
+
+// Per-wavefront state of up to QT row tiles (lane qi: row qi of each tile).
+template <typename TC, int QT>
+struct Srht2Tiles {
+  TC pos[QT];
+  uint32_t ka[QT], lowpar[QT];
+  int rofs[QT];
+  lsq_f4v acc[QT][4];
+  lsq_d4 acc64[QT][4];
+};
+
+// One stage of the streamed pass B for a wavefront holding K tiles: the matrix-core sums of stage buffer
+// Lc interleaved with the in-place fold of stage buffer Lf (when fold_next).  The fold's LDS reads,
+// butterflies and writes are independent of the MFMAs, so the scheduler is asked to alternate them.
+template <typename TC, int FB, int QT, int K, int JA, int UPT, int UNITS>
+__device__ __forceinline__ void srht2_stage(Srht2Tiles<TC, QT>& W, const TC* Lc, TC* Lf, bool fold_next,
+                                           uint32_t ja_stage, bool chain_end, int tid) {
+  constexpr int F = 1 << FB;
+  constexpr int NT = 64 * SRHT2_NW;
+  constexpr int NSTEP = JA / 4;
+  constexpr uint32_t ALL = (1u << NSTEP) - 1u;
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  // fold operands first (their LDS latency overlaps the first MFMAs)
+  TC x[UPT][F];
+  TC* pf[UPT];
+  // (the last stage folds the buffer after it too: stale or unused data that nothing reads, so that the
+  // fold needs no branch around it when every thread has a unit)
+  const bool fa = UNITS >= NT || (fold_next && tid < UNITS);
+#pragma unroll
+  for (int i = 0; i < UPT; ++i) {
+    const int u = tid + NT * i;
+    pf[i] = Lf + (u >> 6) * F * 64 + (u & 63);
+    if (fa) {
+#pragma unroll
+      for (int b = 0; b < F; ++b) x[i][b] = pf[i][b * 64];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const uint32_t sb = W.lowpar[q] ^ ((__popc(W.ka[q] & ja_stage) & 1) ? ALL : 0u);
+    const TC* r = Lc + W.rofs[q];
+#pragma unroll
+    for (int s2 = 0; s2 < NSTEP; ++s2) {
+      const TC a = ((sb >> s2) & 1u) ? -W.pos[q] : W.pos[q];
+      if constexpr (sizeof(TC) == 4) {
+        const f4 u = *(const f4*)(r + 4 * s2 * F * 64);
+        W.acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.x, W.acc[q][0], 0, 0, 0);
+        W.acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.y, W.acc[q][1], 0, 0, 0);
+        W.acc[q][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.z, W.acc[q][2], 0, 0, 0);
+        W.acc[q][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.w, W.acc[q][3], 0, 0, 0);
+      } else {
+        const d2 u0 = *(const d2*)(r + 4 * s2 * F * 64), u1 = *(const d2*)(r + 4 * s2 * F * 64 + 32);
+        W.acc64[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.x, W.acc64[q][0], 0, 0, 0);
+        W.acc64[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.y, W.acc64[q][1], 0, 0, 0);
+        W.acc64[q][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u1.x, W.acc64[q][2], 0, 0, 0);
+        W.acc64[q][3] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u1.y, W.acc64[q][3], 0, 0, 0);
+      }
+    }
+  }
+  if (fa) {
+#pragma unroll
+    for (int i = 0; i < UPT; ++i) {
+#pragma unroll
+      for (int h = 1; h < F; h <<= 1)
+#pragma unroll
+        for (int b = 0; b < F; ++b)
+          if ((b & h) == 0) {
+            const TC a = x[i][b], c = x[i][b + h];
+            x[i][b] = a + c;
+            x[i][b + h] = a - c;
+          }
+#pragma unroll
+      for (int e = 0; e < F; ++e) pf[i][e * 64] = x[i][e];
+    }
+  }
+  // interleave: per MFMA, a share of the fold's VALU and LDS work
+  constexpr int NMF = K * NSTEP * 4;
+  constexpr int NVALU = UPT * F * FB;
+  constexpr int VPM = NMF > 0 ? (NVALU + NMF - 1) / NMF : 0;
+#pragma unroll
+  for (int i = 0; i < NMF; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
+    __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);    // VALU
+    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);      // one LDS write
+  }
+  if constexpr (sizeof(TC) == 4) {
+    // the FP32 chains end every 32 values of j_a, and at the last stage
+    if (chain_end) {
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) W.acc64[q][c][v] += (double)W.acc[q][c][v];
+          W.acc[q][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+        }
+    }
+  }
+}
+
+template <typename TC, int FB, int QT>
+__global__ __launch_bounds__(64 * SRHT2_NW, 1) void k_srht_passB_v2(
+    const TC* __restrict__ T, int64_t N2, int64_t d, int64_t dT, int L1, const int64_t* __restrict__ rows,
+    const int* __restrict__ slot, const int* __restrict__ order, const int* __restrict__ bstart, int64_t m,
+    double* __restrict__ partial) {
+  constexpr int F = 1 << FB;
+  constexpr int NT = 64 * SRHT2_NW;
+  constexpr int STG = Srht2Shape<TC, FB>::STG, NBUF = Srht2Shape<TC, FB>::NBUF;
+  constexpr int SR = STG / (64 * (int)sizeof(TC));         // rows of T per stage
+  constexpr int JA = SR / F;                               // values of j_a per stage
+  constexpr int NSTEP = JA / 4;                            // MFMA steps per stage
+  constexpr int IPT = STG / (NT * 16);                     // 16-byte loads per thread per stage
+  constexpr int STE = STG / (int)sizeof(TC);               // elements per stage
+  constexpr int UNITS = JA * 64;                           // fold units (j_a, column) per stage
+  constexpr int UPT = UNITS > NT ? UNITS / NT : 1;
+  constexpr int CHAINS = sizeof(TC) == 4 ? 32 / JA : 1;    // stages per FP32 chain (32 values of j_a)
+  static_assert(NSTEP >= 1 && JA % 4 == 0, "stage shape");
+  static_assert(IPT >= 1 && IPT * NT * 16 == STG, "stage loads");
+  static_assert(NBUF >= 4 && NBUF * STG == SRHT2_LDS, "stage buffers");
+  static_assert(UNITS <= NT || UNITS % NT == 0, "fold map");
+  static_assert(sizeof(TC) == 8 || (JA <= 32 && 32 % JA == 0), "chain length");
+  __shared__ __attribute__((aligned(16))) TC L[NBUF * STE];
+  __shared__ SrhtTiles2 S;
+  const int klo = blockIdx.z;
+  const int sl = slot[klo];
+  if (sl < 0) return;
+  const int js = blockIdx.y, JS = gridDim.y;
+  const int64_t jh0 = N2 * js / JS, jh1 = N2 * (js + 1) / JS;  // multiples of SR
+  const uint32_t ja0 = (uint32_t)(jh0 >> FB);
+  const int nst = (int)((jh1 - jh0) / SR);
+  const int b0 = bstart[klo], b1 = bstart[klo + 1];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int qi = lane & 15, kk = lane >> 4;
+  const int64_t c0 = (int64_t)blockIdx.x * 64;
+  double* out = partial + (int64_t)js * m * d;
+  // the workgroup's stages, one contiguous range each
+  const TC* gbase = T + (((int64_t)sl * gridDim.x + blockIdx.x) * N2 + jh0) * 64;
+  auto issue = [&](int st) {
+    const char* g = (const char*)(gbase + (int64_t)st * STE);
+    char* l = (char*)(L + (st % NBUF) * STE);
+#pragma unroll
+    for (int k = 0; k < IPT; ++k) {
+      const int c = k * SRHT2_NW + wv;  // 1 KB chunk of the stage
+      srht_dma16(g + c * 1024 + lane * 16, l + c * 1024);
+    }
+  };
+  for (int cb = b0; cb < b1; cb += SRHT2_LROWS) {
+    const int nt = __builtin_amdgcn_readfirstlane(
+        srht_tile_build<FB>(S, cb, min(b1, cb + SRHT2_LROWS), rows, order, L1));
+    for (int tg = 0; tg < nt; tg += SRHT2_NW * QT) {
+      // this wavefront's tiles: tg + wv + 8 q for q < nq
+      const int nq = __builtin_amdgcn_readfirstlane(max(0, min(QT, (nt - tg - wv + SRHT2_NW - 1) / SRHT2_NW)));
+      Srht2Tiles<TC, QT> W;
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        const int t = tg + wv + SRHT2_NW * q;
+        const int qq = q < nq ? S.tq[t][qi] : -1;
+        W.pos[q] = qq >= 0 ? (TC)1 : (TC)0;
+        W.ka[q] = qq >= 0 ? S.tka[t][qi] : 0u;
+        const int e = q < nq ? S.te[t] : 0;
+        W.lowpar[q] = 0u;
+#pragma unroll
+        for (int st = 0; st < NSTEP; ++st)
+          W.lowpar[q] |= (uint32_t)(__popc(W.ka[q] & (uint32_t)(4 * st + kk)) & 1) << st;
+        W.rofs[q] = (kk * F + e) * 64 + srht_ucol<TC>(qi, 0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          W.acc[q][c] = (lsq_f4v){0.f, 0.f, 0.f, 0.f};
+          W.acc64[q][c] = (lsq_d4){0.0, 0.0, 0.0, 0.0};
+        }
+      }
+      // One sweep: stage st from buffer st % NBUF, interleaved with the fold of stage st + 1 (if any), for a
+      // wavefront of KC tiles (a compile-time count, so that each count has its own straight-line body).
+      auto sweep = [&](auto kc) {
+        constexpr int KC = decltype(kc)::value;
+        // Prologue: stages 0 .. NBUF - 2 in flight, stage 0 folded (a stage call with no tiles).  The counts
+        // of the waits are of this wave's stage loads alone: the previous sweep's result stores are drained
+        // first.
+        srht_vm_wait<0>();
+        lds_barrier();  // the previous sweep no longer reads the buffers
+        const int npro = min(nst, NBUF - 1);
+        for (int st = 0; st < npro; ++st) issue(st);
+        srht_vm_wait_stages<IPT, NBUF - 2>(npro - 1);  // stage 0 landed
+        lds_barrier();
+        srht2_stage<TC, FB, QT, 0, JA, UPT, UNITS>(W, L, L, true, 0u, false, tid);  // fold of stage 0
+        for (int st = 0; st < nst; ++st) {
+          // this wave's loads of stage st + 1 have landed; stages st + 2 .. min(nst, st + NBUF - 1) - 1 may
+          // still be in flight
+          srht_vm_wait_stages<IPT, NBUF - 3>(max(0, min(nst, st + NBUF - 1) - (st + 2)));
+          lds_barrier();  // every wave's loads of st + 1, the fold of st, the compute of st - 1: done
+          if (st + NBUF - 1 < nst) issue(st + NBUF - 1);  // into the buffer of stage st - 1
+          const uint32_t ja_stage = ja0 + (uint32_t)(JA * st);
+          const bool ce = (st + 1) % CHAINS == 0 || st + 1 == nst;
+          srht2_stage<TC, FB, QT, KC, JA, UPT, UNITS>(W, L + (st % NBUF) * STE, L + ((st + 1) % NBUF) * STE,
+                                                     st + 1 < nst, ja_stage, ce, tid);
+        }
+      };
+      switch (nq) {
+        case 0: sweep(std::integral_constant<int, 0>()); break;
+        case 1: sweep(std::integral_constant<int, (1 < QT ? 1 : QT)>()); break;
+        case 2: sweep(std::integral_constant<int, (2 < QT ? 2 : QT)>()); break;
+        case 3: sweep(std::integral_constant<int, (3 < QT ? 3 : QT)>()); break;
+        default: sweep(std::integral_constant<int, QT>()); break;
+      }
+#pragma unroll
+      for (int q = 0; q < QT; ++q) {
+        if (q >= nq) continue;
+        const int t = tg + wv + SRHT2_NW * q;
+        // result lane l, register v: tile row 4 (l / 16) + v (FP32 MFMA) or l / 16 + 4 v (FP64 MFMA)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int qq = S.tq[t][sizeof(TC) == 4 ? 4 * kk + v : kk + 4 * v];
+          if (qq < 0) continue;
+          double* o = out + (int64_t)order[qq] * d;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            const int64_t col = c0 + srht_ucol<TC>(qi, c);
+            if (col < d) o[col] = W.acc64[q][c][v];
+          }
+        }
+      }
+    }
+  }
+}
+
 // j_hi ranges of the LDS-staged pass B: about g_srht_passb_wgs (8192) workgroups in all, at most the
 // partial buffer's ranges, at least two stages (256 rows of T for FP32, 128 for FP64) per range.
 static int srht_js_lds(int64_t N1, int64_t N2, int64_t ncb) {
@@ -1185,12 +1469,23 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
       const int64_t ncb = ncbs;
       JS = srht_js_lds(p.N1, p.N2, ncb);
       dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
-      // sixteen wavefronts, one sweep over T for up to 16 tiles.  The 8-point fold from 64 rows per bucket
-      // on average (measured at n = 2^22, d = 1024: sketches 3-8 % faster from 64 to 256 rows, where its
-      // tiles take half the MFMA terms).  Tuning: 2 eight wavefronts, 4-point; 3 sixteen, 4-point;
-      // 4 sixteen, 8-point.
+      // Sixteen wavefronts of one tile each (register-staged), one sweep over T for up to 16 tiles, the
+      // 8-point fold from 64 rows per bucket on average (measured at n = 2^22, d = 1024: sketches 3-8 %
+      // faster from 64 to 256 rows, where its tiles take half the MFMA terms); from 192 rows (more than 16
+      // tiles: a second sweep) the streamed form with up to 32 tiles per sweep and the 16-point fold
+      // (12.2 against 15.4 ms at m = 65536).  Options: 2 eight wavefronts, 4-point; 3 sixteen, 4-point;
+      // 4 sixteen, 8-point; 5 and 6 streamed, 8- and 16-point.
+      const bool stream = p.passb >= 5 || (p.passb == 0 && p.m >= (int64_t)g_srht_stream_rows_f32 * p.N1);
       const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= (int64_t)g_srht_fold8_rows_f32 * p.N1);
-      if (p.passb == 2)
+      if (stream) {
+        const bool f16 = p.passb != 5;
+        if (f16)
+          hipLaunchKernelGGL((k_srht_passB_v2<float, 4, 4>), gl, dim3(64 * SRHT2_NW), 0, st, (const float*)T, p.N2,
+                             d, dT, L1, rows, slot, order, bstart, p.m, partial);
+        else
+          hipLaunchKernelGGL((k_srht_passB_v2<float, 3, 4>), gl, dim3(64 * SRHT2_NW), 0, st, (const float*)T, p.N2,
+                             d, dT, L1, rows, slot, order, bstart, p.m, partial);
+      } else if (p.passb == 2)
         hipLaunchKernelGGL((k_srht_passB_u<float, 8, 2>), gl, dim3(512), 0, st, (const float*)T, p.N2, d, dT, L1,
                            rows, slot, order, bstart, p.m, partial);
       else if (f8)
@@ -1212,10 +1507,19 @@ static void srht_apply_t(hipStream_t st, const TA* A, int64_t n, int64_t d, int6
     const int64_t ncb = ncbs;
     JS = srht_js_lds(p.N1, p.N2, ncb);
     dim3 gl((unsigned)ncb, (unsigned)JS, (unsigned)p.N1);
-    // as for FP32 T; the FP64 8-point form's 64 KB stages leave one workgroup per CU (measured at n = 2^22,
-    // d = 1024: sketches 5-9 % faster from 128 to 256 rows per bucket, even at 96)
+    // as for FP32 T; the register-staged FP64 8-point form's 64 KB stages leave one workgroup per CU
+    // (measured at n = 2^22, d = 1024: sketches 5-9 % faster from 128 to 256 rows per bucket, even at 96)
+    const bool stream = p.passb >= 5 || (p.passb == 0 && p.m >= (int64_t)g_srht_stream_rows_f64 * p.N1);
     const bool f8 = p.passb == 4 || (p.passb == 0 && p.m >= (int64_t)g_srht_fold8_rows_f64 * p.N1);
-    if (p.passb == 2)
+    if (stream) {
+      const bool f16 = p.passb != 5;
+      if (f16)
+        hipLaunchKernelGGL((k_srht_passB_v2<double, 4, 4>), gl, dim3(64 * SRHT2_NW), 0, st, (const double*)T, p.N2,
+                           d, dT, L1, rows, slot, order, bstart, p.m, partial);
+      else
+        hipLaunchKernelGGL((k_srht_passB_v2<double, 3, 4>), gl, dim3(64 * SRHT2_NW), 0, st, (const double*)T, p.N2,
+                           d, dT, L1, rows, slot, order, bstart, p.m, partial);
+    } else if (p.passb == 2)
       hipLaunchKernelGGL((k_srht_passB_u<double, 8, 2>), gl, dim3(512), 0, st, (const double*)T, p.N2, d, dT, L1, rows,
                          slot, order, bstart, p.m, partial);
     else if (f8)

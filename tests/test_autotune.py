@@ -32,17 +32,22 @@ def test_choose_and_apply_from_table(tmp_path):
 
 def test_choose_all_knobs_and_fold_threshold():
     entry = {"fused_groups_per_cu": {"f32": {"1024": 2}},
-             "srht": {"f32": {"1024": {"srht_passa_wgs": 65536, "srht_passb_wgs": 4096, "fold8_rows": 96},
-                              "256": {"srht_passa_wgs": 32768, "srht_passb_wgs": 8192, "fold8_rows": 48}},
-                      "f64": {"1024": {"srht_passa_wgs": 262144, "srht_passb_wgs": 4096, "fold8_rows": 80}}},
+             "srht": {"f32": {"1024": {"srht_passa_wgs": 65536, "srht_passb_wgs": 4096, "fold8_rows": 96,
+                                       "stream_rows": 160},
+                              "256": {"srht_passa_wgs": 32768, "srht_passb_wgs": 8192, "fold8_rows": 48,
+                                      "stream_rows": 192}},
+                      "f64": {"1024": {"srht_passa_wgs": 262144, "srht_passb_wgs": 4096, "fold8_rows": 80,
+                                       "stream_rows": 128}}},
              "gauss_wgs": 2048, "gram_wgs": {"256": 1024, "1024": 4096}}
     assert autotune.choose(entry, "f32", 1024) == {"fused_groups_per_cu": 2, "srht_passa_wgs": 65536,
                                                    "srht_passb_wgs": 4096, "srht_fold8_rows_f32": 96,
-                                                   "srht_fold8_rows_f64": 80, "gauss_wgs": 2048, "gram_wgs": 4096}
+                                                   "srht_fold8_rows_f64": 80, "srht_stream_rows_f32": 160,
+                                                   "srht_stream_rows_f64": 128, "gauss_wgs": 2048,
+                                                   "gram_wgs": 4096}
     assert autotune.choose(entry, "f64", 1024)["srht_passa_wgs"] == 262144
     # d = 300 takes the 256 bucket; a bucket without SRHT entries takes the nearest measured one
     v = autotune.choose(entry, "f32", 300)
-    assert v["srht_fold8_rows_f32"] == 48 and v["gram_wgs"] == 1024
+    assert v["srht_fold8_rows_f32"] == 48 and v["srht_stream_rows_f32"] == 192 and v["gram_wgs"] == 1024
     assert autotune.choose(entry, "f32", 64)["srht_passa_wgs"] == 32768
     # the 8-point form from the smallest count where it stays faster
     t4 = {32: 1.0, 48: 1.0, 64: 1.0, 96: 1.0}
@@ -56,7 +61,7 @@ def test_bad_knob_values_rejected():
         lsq.tune("fused_groups_per_cu", 0)
     with pytest.raises(lsq.LsqError):
         lsq.tune("no_such_knob", 1)
-    for key, bad in (("srht_fold8_rows_f32", 0), ("srht_passb_wgs", 100), ("gauss_wgs", 1 << 20),
+    for key, bad in (("srht_fold8_rows_f32", 0), ("srht_stream_rows_f64", 0), ("srht_passb_wgs", 100), ("gauss_wgs", 1 << 20),
                      ("gram_wgs", 10), ("srht_passa_wgs", -1)):
         with pytest.raises(lsq.LsqError):
             lsq.tune(key, bad)

@@ -1,5 +1,5 @@
 """Parity at the full benchmark size (n = 2^22, d = 1024, kappa = 1e6), in the launch configuration
-bench.py times (the autotuner's table applied; the sketch size m = 40960 that the Section 6 chooser
+bench.py times (the autotuner's table applied; the sketch size m = 65536 that the Section 6 chooser
 picks for both forms, and m = 4096 = 4d), on outputs the oracle can compute one by one and on
 properties that hold at any size:
 
@@ -9,9 +9,10 @@ properties that hold at any size:
   * exact SRHT parity: with integer A in {-3..3} every partial sum of the transform is an integer below
     3 N = 1.26e7 < 2^24, so the FP32 and FP64 paths (pass A, the 4- and 8-point folds, the matrix-core
     chains) must reproduce the oracle's integer sums exactly: 64 output rows from 64 distinct k_lo
-    buckets, all 1024 columns, at m = 40960 (the 8-point forms) and m = 24576;
+    buckets, all 1024 columns, at m = 65536 (the streamed 16-point forms), 40960 (the staged 8-point
+    forms) and 24576;
   * the FP64 and mixed solves against the exact minimiser of the planted problem (relative A-norm
-    error 1e-10) at m = 4096 and 40960; the normal-equation residual ||A^T (y - A x)|| / ||A^T y||,
+    error 1e-10) at m = 4096 and 65536; the normal-equation residual ||A^T (y - A x)|| / ||A^T y||,
     which the A-norm error bounds by kappa times, is reported and checked at that level;
   * the mixed solve at kappa = 1e8 (beyond the FP64 conditioning floor of plain PCG) to 1e-10."""
 import sys
@@ -22,7 +23,7 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 N_ROWS, D, M, KAPPA, SEED = 1 << 22, 1024, 4096, 1e6, 3001
-M_BENCH = 40960
+M_BENCH = 65536
 EPS64, EPS32 = 2.0 ** -52, 2.0 ** -23
 
 
@@ -163,7 +164,7 @@ def _distinct_bucket_rows(m, count=64):
 _EXACT_REF = {}
 
 
-@pytest.mark.parametrize("m", [M_BENCH, 24576])
+@pytest.mark.parametrize("m", [M_BENCH, 40960, 24576])
 @pytest.mark.parametrize("compute", ["f32", "f64"])
 def test_fullsize_srht_exact(big, intA, compute, m):
     """Integer A: the GPU S A times sqrt(m) must be the oracle's integer sums exactly."""
@@ -193,7 +194,7 @@ def test_fullsize_srht_exact(big, intA, compute, m):
 
 
 def test_fullsize_mixed_kappa_1e8(big):
-    """Mixed form at kappa = 1e8, m = 40960: the refinement residual in double-double arithmetic takes
+    """Mixed form at kappa = 1e8, m = 65536: the refinement residual in double-double arithmetic takes
     the solve to the exact minimiser of the stored FP32 problem below 1e-10."""
     import torch
 

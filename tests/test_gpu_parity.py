@@ -158,10 +158,11 @@ def test_srht_sketch(ctx, n, d, m):
 
 @pytest.mark.parametrize("n,d,m", [(300000, 130, 20000), (1 << 17, 20, 100000)])
 def test_srht_pass_b_forms(ctx, n, d, m):
-    """The large-bucket forms of the sampled transform (tuning key srht_passb: 0 automatic, 1
+    """The large-bucket forms of the sampled transform (option srht_passb: 0 automatic, 1
     register-direct for FP32 T, 2 eight wavefronts, 3 sixteen with the 4-point fold, 4 sixteen with the
-    8-point fold) all meet the oracle bound; 2 and 3 take the same arithmetic per output element and agree
-    bitwise."""
+    8-point fold, 5 and 6 the intermediate streamed into LDS with the 8- and 16-point folds) all meet the
+    oracle bound; 2 and 3 take the same arithmetic per output element and agree bitwise, and so do the
+    automatic form and the streamed 16-point form it picks at 390 rows per bucket."""
     from oracle import draws, sketch
     from paper_1911_02675_amd import lsq
     say("srht pass B forms", n, d, m)
@@ -172,7 +173,7 @@ def test_srht_pass_b_forms(ctx, n, d, m):
     ref32 = sketch.srht_sketch(A.astype(np.float32).astype(np.float64), m, 9, 2)
     got = {}
     try:
-        for mode in (0, 1, 2, 3, 4):
+        for mode in (0, 1, 2, 3, 4, 5, 6):
             ctx.set_option("srht_passb", mode)
             got[mode] = (_sa(ctx, A, "srht", m, seed=9, t=2),
                          _sa(ctx, A.astype(np.float32), "srht", m, seed=9, t=2, compute="f32"))
@@ -182,17 +183,22 @@ def test_srht_pass_b_forms(ctx, n, d, m):
         assert np.all(np.abs(g64 - ref) <= 8 * (math.log2(N) + 2) * EPS * scale), mode
         assert np.all(np.abs(g32 - ref32) <= 8 * (math.log2(N) + 2) * 2.0 ** -24 * scale), mode
     assert np.array_equal(got[2][0], got[3][0]) and np.array_equal(got[2][1], got[3][1])
+    # the automatic form at 390 rows per bucket is the streamed one with the 16-point fold
+    if m / 256 >= 192:
+        assert np.array_equal(got[0][0], got[6][0]) and np.array_equal(got[0][1], got[6][1])
 
 
 @pytest.mark.parametrize("n,d,m", [(100, 3, 16), (4096, 64, 256), (20000, 129, 700), (1 << 15, 48, 12000),
-                                   (300000, 130, 20000), (1 << 17, 20, 100000), (1 << 18, 64, 40000)])
+                                   (300000, 130, 20000), (1 << 17, 20, 100000), (1 << 18, 64, 40000),
+                                   (1 << 18, 24, 160000)])
 def test_srht_exact_integer(ctx, n, d, m):
     """Exact parity of every SRHT form.  With A in {-2..2} every partial sum of the transform is an
     integer of magnitude at most 2 N < 2^24, exact in FP32 and FP64 alike, so S A sqrt(m) must equal
-    the oracle's transform exactly: every pass B form (tuning key srht_passb 0-4, each taken where the
+    the oracle's transform exactly: every pass B form (option srht_passb 0-6, each taken where the
     buckets are large), FP64 and FP32 A, FP64 and FP32 transforms, the 16-byte vector pass A and the
     scalar one (leading dimension d + 1).  A wrong sign, index or fold in any of them changes some
-    output integer."""
+    output integer.  m = 100000 over 2^17 rows (390 per bucket) makes the streamed forms take two
+    sweeps over some buckets' intermediate, m = 160000 (625 per bucket) two tile chunks."""
     from oracle import sketch
     from paper_1911_02675_amd import lsq
     torch = _torch()
@@ -207,7 +213,7 @@ def test_srht_exact_integer(ctx, n, d, m):
     cases = {"f64/f64": (dev(Ai), "f64"), "f32/f32": (dev(Ai.astype(np.float32)), "f32"),
              "f32/f64": (dev(Ai.astype(np.float32)), "f64"), "f64/f32": (dev(Ai), "f32"),
              "f64 lda=d+1": (pad[:, :d], "f64"), "f32 lda=d+1": (pad.float()[:, :d], "f32")}
-    modes = (0, 1, 2, 3, 4) if m > 24 * 256 else (0,)
+    modes = (0, 1, 2, 3, 4, 5, 6) if m > 24 * 256 else (0,)
     try:
         for mode in modes:
             ctx.set_option("srht_passb", mode)
