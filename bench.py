@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--count", type=int, default=512, help="c4: number of problems")
     ap.add_argument("--slots", default="0", help="c4: comma list of batched workgroup counts to time "
                                                  "(0 = one per compute unit)")
+    ap.add_argument("--gang-units", default="",
+                    help="c4: comma list of batched gang sizes (elements of n d per workgroup; 0 = no gangs) "
+                         "to time at every slot count (default: the library's)")
     ap.add_argument("--no-loop", action="store_true", help="c4: skip the per-problem loop")
     ap.add_argument("--seeds", type=int, default=32, help="c5: sketch seeds per configuration")
     ap.add_argument("--c5-methods", default="ihs,fcg,fixed,pcg",
@@ -257,8 +260,11 @@ def sweep_c4(a):
         return time.perf_counter() - t, st, infos
 
     results = []
-    for slots in [int(v) for v in a.slots.split(",")]:
+    units = [int(v) for v in a.gang_units.split(",")] if a.gang_units else [None]
+    for slots, unit in [(sl, u) for sl in (int(v) for v in a.slots.split(",")) for u in units]:
         lsq.tune("batched_slots", slots)
+        if unit is not None:
+            lsq.tune("batched_gang_unit", unit)
         for _ in range(a.warmup):
             batch()
         times = []
@@ -288,7 +294,7 @@ def sweep_c4(a):
                  "phase_ms_sum": {"sketch": round(sum(i.t_sketch_ms for i in infos), 2),
                                   "factor": round(sum(i.t_factor_ms for i in infos), 2),
                                   "iterate": round(sum(i.t_iter_ms for i in infos), 2)}}
-        rec = {"sweep": "c4", "count": a.count, "slots": slots, "status": st, "schedule": sched,
+        rec = {"sweep": "c4", "count": a.count, "slots": slots, "gang_unit": unit, "status": st, "schedule": sched,
                "failed": sum(1 for i in infos if i.status != 0),
                "batch_s": round(dt, 5), "kernel_ms": round(kern_ms, 3),
                "solves_per_s": round(a.count / dt, 1),
@@ -298,11 +304,12 @@ def sweep_c4(a):
                "iters_max": max(i.iters for i in infos),
                "refinements_mean": round(float(np.mean([i.refinements for i in infos])), 2),
                "max_rel_a_norm_error": max(e)}
-        log(f"[c4] slots {slots}: {dt * 1e3:.1f} ms per sweep ({a.count / dt:.0f} solves/s), kernel "
+        log(f"[c4] slots {slots} gang unit {unit}: {dt * 1e3:.1f} ms per sweep ({a.count / dt:.0f} solves/s), kernel "
             f"{kern_ms:.1f} ms, {rec['agg_gbs']} GB/s, max e_A {max(e):.2e}, failed {rec['failed']}; "
             f"schedule {json.dumps(sched)}")
         results.append(rec)
     lsq.tune("batched_slots", 0)
+    lsq.tune("batched_gang_unit", 8 << 20)
     best = min(results, key=lambda r: r["batch_s"])
     loop = None
     if not a.no_loop:

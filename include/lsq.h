@@ -301,9 +301,15 @@ lsq_status lsq_fcg_solve(lsq_ctx* ctx, const lsq_problem* prob, const lsq_sketch
 /* `count` independent problems solved together (Section 1.2 with the sparse embedding of
  * Section 2, the SJLT): the sketch S_i A_i, the Householder QR S_i A_i = Q_i R_i, W_i = R_i^{-1}
  * and PCG (inside FP64 iterative refinement when opts->mixed) of every problem run inside one
- * persistent kernel, one workgroup per problem, problems taken from a work queue ordered by
- * decreasing n_i d_i.  The launch is captured in a HIP graph that is replayed while the batch
- * shape (count, workspace sizes, options) stays the same.
+ * persistent kernel, problems taken from a work queue ordered by decreasing work per workgroup.  A
+ * problem is solved by K_i = round(n_i d_i / "batched_gang_unit") workgroups (1 <= K_i <= 4; lsq_tune,
+ * default 8 Mi elements, 0 = one workgroup for every problem): the first factors S_i A_i, then each of
+ * the K_i streams its block of rows in every pass, and the partial sums are added in the same order on
+ * all of them after a barrier in device memory (bounded: a barrier that runs out of time reports
+ * LSQ_ERR_HIP for that problem).  K_i depends on the problem alone, so the results do not depend on
+ * the number of workgroups as long as there are at least 4 (UNSUPPORTED when some K_i exceeds it).  The
+ * launch is captured in a HIP graph that is replayed while the batch shape (count, workspace sizes,
+ * options) stays the same.
  *   probs, descs, xs: host arrays of length count.  xs[i]: device pointer to x_i (d_i entries;
  *     in: x_0, zeros are a valid start; out: the solution).
  *   Rs (optional host array, entries may be NULL): device d_i x d_i row-major buffers that
@@ -361,7 +367,8 @@ lsq_status lsq_copy_bandwidth(lsq_ctx* ctx, const void* src, void* dst, int64_t 
  * measured table; they change launch shapes (and with them the fixed order of some reductions), not the
  * method.  Keys: "fused_groups_per_cu" (workgroups per CU of the fused pass, 1..64, default 8);
  * "batched_slots" (workgroups of the batched persistent kernel, 0 = one per compute unit, else
- * 1..65536); "srht_fold8_rows_f32" / "srht_fold8_rows_f64" (the SRHT's staged second pass folds by
+ * 1..65536); "batched_gang_unit" (elements of n d per workgroup of a batched problem's gang, 0 or at
+ * least 65536; default 8 Mi); "srht_fold8_rows_f32" / "srht_fold8_rows_f64" (the SRHT's staged second pass folds by
  * the 8-point transform, rather than the 4-point one, from this many selected rows per 256-row bucket on
  * average, FP32 / FP64 intermediate; defaults 64 / 128); "srht_stream_rows_f32" / "srht_stream_rows_f64"
  * (from this many rows per bucket the streamed form with the 16-point fold; default 192 for both);

@@ -9,6 +9,8 @@ Knobs measured (see lsq_tune in include/lsq.h), each as the fastest of a few can
                        row width and on how many rows a workgroup streams);
   batched_slots        workgroups of the persistent batched kernel (each streams one problem; fewer
                        than one per compute unit can win when the largest problems set the makespan);
+  batched_gang_unit    elements of n d per workgroup of a gang (problems above it are solved by 2-4
+                       workgroups together), timed jointly with batched_slots;
   srht_passa_wgs       workgroups of the SRHT's first pass, per transform precision and d bucket (timed
                        at m = 4d, where the second pass is small);
   srht_passb_wgs       workgroups of the LDS-staged second pass (timed at m = 40 d);
@@ -46,13 +48,14 @@ DEFAULT_TABLE = os.path.join(HERE, "tune_table.json")
 D_BUCKETS = (64, 256, 1024)
 GPC_CANDIDATES = (2, 4, 8, 16)
 SLOT_CANDIDATES = (128, 192, 256)
+GANG_CANDIDATES = (0, 6 << 20, 8 << 20, 10 << 20)
 PASSA_CANDIDATES = (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
 PASSB_CANDIDATES = (4096, 8192, 16384)
 FOLD_ROWS = (32, 48, 64, 96, 128, 160, 192, 256)
 GAUSS_CANDIDATES = (512, 1024, 2048, 4096)
 GRAM_CANDIDATES = (1024, 2048, 4096)
 # library defaults, restored after measuring
-DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
+DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "batched_gang_unit": 8 << 20, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
             "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128,
             "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gram_wgs": 2048}
 
@@ -102,6 +105,8 @@ def choose(entry, dtype="f32", d=1024):
         out["fused_groups_per_cu"] = int(g.get(bucket(d), next(iter(g.values()))))
     if "batched_slots" in entry:
         out["batched_slots"] = int(entry["batched_slots"])
+    if "batched_gang_unit" in entry:
+        out["batched_gang_unit"] = int(entry["batched_gang_unit"])
     srht = entry.get("srht", {})
     sr = _by_bucket(srht.get(dtype, {}), d)
     if sr:
@@ -190,8 +195,9 @@ def measure_batched(ctx, quick=False):
         xs.append(torch.zeros(d, dtype=torch.float64, device="cuda"))
         descs.append(lsq.sketch_desc("sjlt", 4 * d, seed=1000 + i, s=4))
     res = {}
-    for slots in SLOT_CANDIDATES:
+    for slots, unit in [(sl, u) for sl in SLOT_CANDIDATES for u in GANG_CANDIDATES]:
         lsq.tune("batched_slots", slots)
+        lsq.tune("batched_gang_unit", unit)
         best = None
         for _ in range(3):
             for x in xs:
@@ -203,8 +209,9 @@ def measure_batched(ctx, quick=False):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t
             best = dt if best is None else min(best, dt)
-        res[str(slots)] = round(count / best, 1)
+        res[f"{slots}/{unit}"] = round(count / best, 1)
     lsq.tune("batched_slots", 0)
+    lsq.tune("batched_gang_unit", DEFAULTS["batched_gang_unit"])
     return res
 
 
@@ -334,7 +341,8 @@ def tune(quick=False, path=None):
             lsq.tune(k, v)
     entry = {"fused_groups_per_cu": {dt: {b: int(max(row, key=row.get)) for b, row in per.items()}
                                      for dt, per in fused.items()},
-             "batched_slots": int(max(batched, key=batched.get)),
+             "batched_slots": int(max(batched, key=batched.get).split("/")[0]),
+             "batched_gang_unit": int(max(batched, key=batched.get).split("/")[1]),
              "srht": {dt: {b: {"srht_passa_wgs": _argmin(rec["passa"]), "srht_passb_wgs": _argmin(rec["passb"]),
                                "fold8_rows": _fold_threshold({int(k): v for k, v in rec["fold4"].items()},
                                                              {int(k): v for k, v in rec["fold8"].items()}),

@@ -1341,6 +1341,12 @@ lsq_status lsq_tune(const char* key, int64_t value) {
     g_batched_slots = (int)value;
     return LSQ_OK;
   }
+  if (k == "batched_gang_unit") {
+    if (value < 0 || (value > 0 && value < 65536))
+      return fail(LSQ_ERR_INVALID_ARG, "batched_gang_unit: 0 (no gangs) or at least 65536 elements");
+    g_batched_gang_unit = value;
+    return LSQ_OK;
+  }
   struct Knob {
     const char* key;
     int* var;
@@ -1424,12 +1430,30 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* p
     mpmax = std::max(mpmax, (s.m + 15) / 16 * 16);
     dpmax = std::max(dpmax, (p.d + 15) / 16 * 16);
   }
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-    return probs[a].n * probs[a].d > probs[b].n * probs[b].d;
-  });
   int cus = 0;
   HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->dev));
-  const int slots = std::min<int64_t>(count, g_batched_slots > 0 ? g_batched_slots : std::max(cus, 1));
+  // gang size of each problem: one workgroup per g_batched_gang_unit elements of n d (rounded), at most
+  // BATCH_GANG_KMAX; a function of the problem alone, so that the result does not depend on the number
+  // of workgroups (as long as there are at least BATCH_GANG_KMAX of them)
+  auto gang_size = [&](int i) -> int {
+    if (g_batched_gang_unit <= 0) return 1;
+    const double nd = (double)probs[i].n * (double)probs[i].d;
+    const int k = (int)std::llround(nd / (double)g_batched_gang_unit);
+    return std::max(1, std::min(BATCH_GANG_KMAX, k));
+  };
+  std::vector<int> gsize(count);
+  int64_t ntasks = 0;
+  for (int i = 0; i < count; ++i) {
+    gsize[i] = gang_size(i);
+    ntasks += gsize[i];
+  }
+  // queue order: largest work per member first (longest processing time first)
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    return probs[a].n * probs[a].d / gsize[a] > probs[b].n * probs[b].d / gsize[b];
+  });
+  const int slots = (int)std::min<int64_t>(ntasks, g_batched_slots > 0 ? g_batched_slots : std::max(cus, 1));
+  for (int i = 0; i < count; ++i)
+    if (gsize[i] > slots) return fail(LSQ_ERR_UNSUPPORTED, "batched form: fewer workgroups than a gang needs");
   // workspace (per slot) and the problem table
   BatchArgs a;
   memset(&a, 0, sizeof(a));
@@ -1445,6 +1469,22 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* p
   a.last_stride = 256;
   BatchDesc* dtab;
   CHK(wsT(c, "b_desc", (size_t)count, &dtab));
+  BatchTask* ttab;
+  CHK(wsT(c, "b_tasks", (size_t)ntasks, &ttab));
+  a.ntasks = (int)ntasks;
+  std::vector<BatchTask> tasks;
+  tasks.reserve(ntasks);
+  int ngangs = 0;
+  for (int q = 0; q < count; ++q) {
+    const int K = gsize[order[q]];
+    const int gid = K > 1 ? ngangs++ : -1;
+    for (int r = 0; r < K; ++r) tasks.push_back(BatchTask{q, r, K, gid});
+  }
+  a.ngangs = ngangs;
+  a.gpart_stride = dpmax + 1;
+  CHK(wsT(c, "b_gstate", (size_t)std::max(ngangs, 1) * 4, &a.gstate));
+  CHK(wsT(c, "b_gpart", (size_t)std::max(ngangs, 1) * 2 * BATCH_GANG_KMAX * a.gpart_stride, &a.gpart));
+  a.tasks = ttab;
   CHK(wsT(c, "b_out", (size_t)count, &a.out));
   CHK(wsT(c, "b_queue", 1, &a.queue));
   CHK(wsT(c, "b_keys", (size_t)slots * kmax, &a.keys));
@@ -1516,6 +1556,7 @@ lsq_status lsq_pcg_solve_batched(lsq_ctx* c, int32_t count, const lsq_problem* p
   HIPCHK(hipEventRecord(c->bev[0], c->st));
   HIPCHK(hipStreamWaitEvent(c->bst, c->bev[0], 0));
   HIPCHK(hipMemcpyAsync(dtab, table.data(), sizeof(BatchDesc) * count, hipMemcpyHostToDevice, c->bst));
+  HIPCHK(hipMemcpyAsync(ttab, tasks.data(), sizeof(BatchTask) * tasks.size(), hipMemcpyHostToDevice, c->bst));
   HIPCHK(hipEventRecord(c->bev[1], c->bst));
   HIPCHK(hipGraphLaunch(c->bexec, c->bst));
   HIPCHK(hipEventRecord(c->bev[2], c->bst));

@@ -24,6 +24,8 @@
 // global instructions.
 #include "internal.h"
 
+#include <algorithm>
+
 namespace lsq {
 
 namespace {
@@ -581,7 +583,7 @@ template <typename TA, int VEC, int G, int NV, int MODE>
 __device__ __forceinline__ void b_fused(const TA LSQ_G* __restrict__ A, int64_t lda, int64_t n,
                                         const TA LSQ_G* __restrict__ last, int d,
                                         const double LSQ_G* __restrict__ y, const double* v, double* w,
-                                        double* scal, double* red) {
+                                        double* scal, double* red, bool has_last) {
   constexpr int RPW = 64 / G;    // rows per wave per step
   constexpr int RS = BNW * RPW;  // rows per workgroup step
   constexpr int U = NV >= 8 ? 1 : 8 / NV;  // rows in flight per lane group (U NV loads per lane)
@@ -603,9 +605,10 @@ __device__ __forceinline__ void b_fused(const TA LSQ_G* __restrict__ A, int64_t 
     }
   }
   double ss = 0.0;
-  // rows [0, nm) are read with whole chunks; when d is not a multiple of VEC the last row's
-  // straddling chunk would run past the matrix, so that row is read element-wise at the end
-  const int nm = (VEC > 1 && d % VEC != 0) ? (int)n - 1 : (int)n;
+  // rows [0, nm) are read with whole chunks; when d is not a multiple of VEC the matrix's last row's
+  // straddling chunk would run past the matrix, so that row (when this block holds it) is read
+  // element-wise at the end
+  const int nm = (VEC > 1 && d % VEC != 0 && has_last) ? (int)n - 1 : (int)n;
   const int row0 = wv * RPW + rw;
   const int64_t kstep = (int64_t)RS * lda;
   // one row of the lane group: masked chunk values -> q -> accumulators
@@ -765,19 +768,82 @@ __device__ __forceinline__ void b_precond(const double LSQ_G* W, const double LS
   __syncthreads();
 }
 
+// ---------------------------------------------------------------------------------------------
+// Gangs: a problem above the gang size is solved by K workgroups together (K fixed by n d, so the
+// result does not depend on the number of workgroups).  Member r streams rows [n r / K, n (r + 1) / K)
+// in every pass and writes its partial A^T(.) and its sum of squares; after a barrier every member adds
+// the K partials in rank order, so all members hold the same sums and take the same PCG steps.  The
+// barrier is a counter in device memory (release fence, atomic add, acquire spin); its wait is bounded,
+// and a wait that runs out marks the gang broken (the problem then reports LSQ_ERR_HIP) instead of
+// hanging.  The K member tasks of a gang sit next to each other in the queue, so with at least K
+// workgroups they are always taken by K workgroups that run at the same time.
+// ---------------------------------------------------------------------------------------------
+struct Gang {
+  int K, rank, epoch;
+  int LSQ_G* st;      // [0] barrier count, [1] leader slot, [2] setup status, [3] broken
+  double LSQ_G* part;  // 2 x KMAX rows of pstride doubles
+  int64_t pstride;
+};
+
+constexpr int B_GANG_SPIN = 1 << 22;  // barrier polls before the gang is declared broken
+
+__device__ __forceinline__ void gang_barrier(Gang& g) {
+  g.epoch += 1;  // every thread keeps the same count
+  __threadfence();
+  __syncthreads();
+  if (b_tid() == 0) {
+    atomicAdd((int*)g.st, 1);
+    const int target = g.K * g.epoch;
+    int spins = 0;
+    while (__hip_atomic_load((int*)g.st, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      // a broken gang no longer waits (its result is discarded)
+      if (__hip_atomic_load((int*)g.st + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) break;
+      __builtin_amdgcn_s_sleep(8);
+      if (++spins >= B_GANG_SPIN) {
+        __hip_atomic_store((int*)g.st + 3, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+  }
+  __threadfence();
+  __syncthreads();
+}
+
+// w (d values in LDS) and *scal of this member -> the sums over the gang's members, in rank order.
+__device__ __forceinline__ void gang_reduce(Gang& g, double* w, double* scal, int d) {
+  const int tid = b_tid();
+  double LSQ_G* mine = g.part + ((int64_t)((g.epoch + 1) & 1) * BATCH_GANG_KMAX + g.rank) * g.pstride;
+  for (int c = tid; c < d; c += BT) mine[c] = w[c];
+  if (tid == BT - 1) mine[d] = *scal;
+  gang_barrier(g);
+  const double LSQ_G* all = g.part + (int64_t)(g.epoch & 1) * BATCH_GANG_KMAX * g.pstride;
+  for (int c = tid; c <= d; c += BT) {
+    double s = all[c];
+    for (int k = 1; k < g.K; ++k) s += all[k * g.pstride + c];
+    if (c < d)
+      w[c] = s;
+    else
+      *scal = s;
+  }
+  __syncthreads();
+}
+
 // PCG (and the refinement loop of the mixed form) for one problem, with the stop rule of the
-// single-problem solver: proxy 4 sqrt(rho_t / rho_0) <= tol.  Result written to *out.
+// single-problem solver: proxy 4 sqrt(rho_t / rho_0) <= tol.  Result written to *out.  With a gang,
+// A and y are this member's row block (n rows, has_last when it holds the matrix's last row), every
+// pass is followed by the gang's reduction, and only the leader writes x and *out.
 struct PcgArgs {
   int64_t n, lda;
   int d, dp, mixed, max_iter, max_refine;
   double tol;
+  bool has_last;
 };
 
 template <typename TA, int VEC, int G, int NV>
 LSQ_NOINLINE __device__ void b_pcg(const TA LSQ_G* A, const TA LSQ_G* last, const double LSQ_G* yg,
                                    double LSQ_G* xg,
                                    const double LSQ_G* W, const double LSQ_G* WT, PcgArgs pa,
-                                   BatchOut LSQ_G* out) {
+                                   BatchOut LSQ_G* out, Gang* gang) {
   auto& L = g_L.it;
   const int tid = b_tid();
   const int d = pa.d;
@@ -797,7 +863,8 @@ LSQ_NOINLINE __device__ void b_pcg(const TA LSQ_G* A, const TA LSQ_G* last, cons
   double est = 0.0, rho_b = -1.0;
   bool inner_done = false;
   for (int k = 0; k < outer; ++k) {
-    b_fused<TA, VEC, G, NV, 1>(A, pa.lda, pa.n, last, d, yg, x, r, &L.scal, L.red);
+    b_fused<TA, VEC, G, NV, 1>(A, pa.lda, pa.n, last, d, yg, x, r, &L.scal, L.red, pa.has_last);
+    if (gang) gang_reduce(*gang, r, &L.scal, d);
     b_precond(W, WT, d, pa.dp, r, L.u, rh);
     double rho = b_dot(r, rh, d, L.sc);
     double tol_in;
@@ -828,7 +895,8 @@ LSQ_NOINLINE __device__ void b_pcg(const TA LSQ_G* A, const TA LSQ_G* last, cons
     inner_done = !(rho0 > 0.0);
     int it = 0;
     while (!inner_done && it < pa.max_iter) {
-      b_fused<TA, VEC, G, NV, 0>(A, pa.lda, pa.n, last, d, nullptr, p, w, &L.scal, L.red);
+      b_fused<TA, VEC, G, NV, 0>(A, pa.lda, pa.n, last, d, nullptr, p, w, &L.scal, L.red, pa.has_last);
+      if (gang) gang_reduce(*gang, w, &L.scal, d);
       const double pHp = uni(L.scal);
       if (!(pHp > 0.0) || !isfinite(pHp)) {
         status = isfinite(pHp) ? (int)LSQ_ERR_RANK : (int)LSQ_ERR_NONFINITE;
@@ -862,10 +930,14 @@ LSQ_NOINLINE __device__ void b_pcg(const TA LSQ_G* A, const TA LSQ_G* last, cons
       __syncthreads();
     }
   }
-  for (int c = tid; c < d; c += BT) xg[c] = x[c];
+  const bool lead = !gang || gang->rank == 0;
+  if (lead)
+    for (int c = tid; c < d; c += BT) xg[c] = x[c];
   const bool conv = pa.mixed ? (est <= pa.tol) : inner_done;
   if (status == 0 && !conv) status = (int)LSQ_ERR_NOT_CONVERGED;
-  if (tid == 0) {
+  if (gang && __hip_atomic_load((const int*)gang->st + 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+    status = (int)LSQ_ERR_HIP;  // a gang barrier ran out of time: the sums are not to be trusted
+  if (lead && tid == 0) {
     out->status = status;
     out->iters = total;
     out->refinements = refinements;
@@ -936,11 +1008,64 @@ __device__ __forceinline__ Map choose_map(int a_f32, const void* A, int64_t lda,
     }                                             \
   }
 
-__device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
+// Iterations of problem pd on this workgroup's row block (the whole matrix when gang is null).
+__device__ __forceinline__ void b_iterate(const BatchArgs& a, const BatchDesc& pd, const Map& mapv,
+                                          const double LSQ_G* W, const double LSQ_G* WT, double LSQ_G* last,
+                                          BatchOut LSQ_G* out, Gang* gang) {
+  const int d = pd.d;
+  const int K = gang ? gang->K : 1, rank = gang ? gang->rank : 0;
+  const int64_t r0 = pd.n * rank / K, r1 = pd.n * (rank + 1) / K;
+  PcgArgs pa;
+  pa.n = r1 - r0;
+  pa.lda = pd.lda;
+  pa.d = d;
+  pa.dp = (d + 15) & ~15;
+  pa.mixed = a.mixed;
+  pa.max_iter = a.max_iter;
+  pa.max_refine = a.max_refine;
+  pa.tol = a.tol;
+  pa.has_last = rank == K - 1;
+#define LSQ_B_PCG(T_, V_, G_, N_)                                                                       \
+  b_pcg<T_, V_, G_, N_>((const T_ LSQ_G*)pd.A + r0 * pd.lda, (const T_ LSQ_G*)last,                     \
+                        (const double LSQ_G*)pd.y + r0, (double LSQ_G*)pd.x, W, WT, pa, out, gang);
+  if (pd.a_f32) {
+    LSQ_B_FOR_MAPS(float, LSQ_B_PCG)
+  } else {
+    LSQ_B_FOR_MAPS(double, LSQ_B_PCG)
+  }
+#undef LSQ_B_PCG
+}
+
+__device__ __forceinline__ void b_solve(const BatchArgs& a, const BatchTask tk, int slot) {
   const uint64_t t_start = wall_clock64();
+  const int q = tk.q;
   const BatchDesc pd = a.descs[q];
   const int d = pd.d, m = pd.m;
   const int dp = (d + 15) & ~15, mp = (m + 15) & ~15;
+  BatchOut LSQ_G* out = (BatchOut LSQ_G*)(a.out + pd.idx);
+  const Map mapv = choose_map(pd.a_f32, pd.A, pd.lda, d);
+  Gang gang;
+  Gang* gp = nullptr;
+  if (tk.K > 1) {
+    gang.K = tk.K;
+    gang.rank = tk.rank;
+    gang.epoch = 0;
+    gang.st = (int LSQ_G*)(a.gstate + 4 * (int64_t)tk.gang);
+    gang.part = (double LSQ_G*)(a.gpart + (int64_t)tk.gang * 2 * BATCH_GANG_KMAX * a.gpart_stride);
+    gang.pstride = a.gpart_stride;
+    gp = &gang;
+  }
+  if (gp && tk.rank > 0) {
+    // a member: the leader's factorization, then this member's rows
+    gang_barrier(gang);
+    const int ok = __hip_atomic_load((const int*)gang.st + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int lslot = __hip_atomic_load((const int*)gang.st + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (ok != 1) return;  // the leader reports the failure
+    const double LSQ_G* W = (const double LSQ_G*)(a.W + (int64_t)lslot * a.r_stride);
+    const double LSQ_G* WT = (const double LSQ_G*)(a.WT + (int64_t)lslot * a.r_stride);
+    b_iterate(a, pd, mapv, W, WT, (double LSQ_G*)(a.last + (int64_t)slot * a.last_stride), out, gp);
+    return;
+  }
   uint32_t LSQ_G* keys = (uint32_t LSQ_G*)(a.keys + (int64_t)slot * a.keys_stride);
   uint32_t LSQ_G* sorted = (uint32_t LSQ_G*)(a.sorted + (int64_t)slot * a.keys_stride);
   double LSQ_G* SA = (double LSQ_G*)(a.SA + (int64_t)slot * a.sa_stride);
@@ -948,7 +1073,6 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
   double LSQ_G* R = (double LSQ_G*)(a.R + (int64_t)slot * a.r_stride);
   double LSQ_G* W = (double LSQ_G*)(a.W + (int64_t)slot * a.r_stride);
   double LSQ_G* WT = (double LSQ_G*)(a.WT + (int64_t)slot * a.r_stride);
-  BatchOut LSQ_G* out = (BatchOut LSQ_G*)(a.out + pd.idx);
   // zero-padded copy of the last row of A (see load_chunk)
   double LSQ_G* last = (double LSQ_G*)(a.last + (int64_t)slot * a.last_stride);
   for (int c = b_tid(); c < B_DMAX; c += BT) {
@@ -960,8 +1084,8 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
       last[c] = c < d ? Ad[c] : 0.0;
     }
   }
+  if (gp && b_tid() == 0) gang.st[1] = slot;  // published by the barrier after the factorization
   __syncthreads();
-  const Map mapv = choose_map(pd.a_f32, pd.A, pd.lda, d);
   if (b_tid() == 0) out->t_start = t_start;
   // 1. sketch
   const int drew = b_sort(pd.n, m, pd.s, pd.seed, pd.t, keys, sorted);
@@ -987,51 +1111,44 @@ __device__ __forceinline__ void b_solve(const BatchArgs& a, int q, int slot) {
       out->est = 0.0;
       out->t_factor = out->t_end = wall_clock64();
     }
+    if (gp) {
+      if (b_tid() == 0) gang.st[2] = 2;
+      gang_barrier(gang);  // releases the members, who then leave
+    }
     __syncthreads();
     return;
   }
   // 3. W = R^{-1};  4. iterate
   b_trinv(R, dp, W, WT);
   if (b_tid() == 0) out->t_factor = wall_clock64();
-  PcgArgs pa;
-  pa.n = pd.n;
-  pa.lda = pd.lda;
-  pa.d = d;
-  pa.dp = dp;
-  pa.mixed = a.mixed;
-  pa.max_iter = a.max_iter;
-  pa.max_refine = a.max_refine;
-  pa.tol = a.tol;
-#define LSQ_B_PCG(T_, V_, G_, N_)                                                                 \
-  b_pcg<T_, V_, G_, N_>((const T_ LSQ_G*)pd.A, (const T_ LSQ_G*)last, (const double LSQ_G*)pd.y, \
-                        (double LSQ_G*)pd.x, W, WT, pa, out);
-  if (pd.a_f32) {
-    LSQ_B_FOR_MAPS(float, LSQ_B_PCG)
-  } else {
-    LSQ_B_FOR_MAPS(double, LSQ_B_PCG)
+  if (gp) {
+    if (b_tid() == 0) gang.st[2] = 1;
+    gang_barrier(gang);  // W, W^T and the leader's slot to the members
   }
-#undef LSQ_B_PCG
+  b_iterate(a, pd, mapv, W, WT, last, out, gp);
   if (b_tid() == 0) out->t_end = wall_clock64();
 }
 
 }  // namespace
 
 int g_batched_slots = 0;
+int64_t g_batched_gang_unit = 8 << 20;
 
 __global__ __launch_bounds__(BT) void k_batched(const BatchArgs a) {
-  const int count = a.count;
+  const int ntasks = a.ntasks;
   for (;;) {
     if (b_tid() == 0) g_L.qidx = atomicAdd(a.queue, 1);
     __syncthreads();
     const int q = uni(g_L.qidx);
     __syncthreads();
-    if (q >= count) break;
-    b_solve(a, q, blockIdx.x);
+    if (q >= ntasks) break;
+    b_solve(a, a.tasks[q], blockIdx.x);
   }
 }
 
-__global__ void k_batch_reset(int* queue, BatchOut* out, int count) {
+__global__ void k_batch_reset(int* queue, BatchOut* out, int count, int* gstate, int ngangs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 4 * ngangs) gstate[i] = 0;
   if (i == 0) *queue = 0;
   if (i < count) {
     out[i].status = -1;
@@ -1044,8 +1161,9 @@ __global__ void k_batch_reset(int* queue, BatchOut* out, int count) {
 }
 
 void batched_launch(hipStream_t st, const BatchArgs& a, int slots) {
-  hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)((a.count + 255) / 256)), dim3(256), 0, st, a.queue,
-                     a.out, a.count);
+  const int nr = std::max(a.count, 4 * a.ngangs);
+  hipLaunchKernelGGL(k_batch_reset, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, a.queue, a.out,
+                     a.count, a.gstate, a.ngangs);
   hipLaunchKernelGGL(k_batched, dim3((unsigned)slots), dim3(BT), 0, st, a);
 }
 

@@ -228,18 +228,31 @@ struct BatchOut {
   double est;
   uint64_t t_start, t_sketch, t_factor, t_end;  // device wall clock at the phase boundaries
 };
-// Kernel arguments: the problem table, results, queue counter, solver options and the per-slot
-// workspace (slot = workgroup index; strides in elements).
+// One entry of the work queue: problem q (position in the table), member `rank` of a gang of K
+// workgroups (K = 1: the problem alone), gang index (-1 for K = 1).
+struct BatchTask {
+  int32_t q, rank, K, gang;
+};
+constexpr int BATCH_GANG_KMAX = 4;  // workgroups per problem at most
+// Kernel arguments: the problem table, the task queue (ntasks entries), results, queue counter, solver
+// options, the per-slot workspace (slot = workgroup index; strides in elements) and the per-gang state
+// (gstate: 4 ints per gang, barrier count, leader slot, setup status, broken flag; gpart: 2 x KMAX
+// partial rows of gpart_stride doubles per gang).
 struct BatchArgs {
   const BatchDesc* descs;
+  const BatchTask* tasks;
   BatchOut* out;
   int* queue;
-  int count, mixed, max_iter, max_refine;
+  int count, ntasks, ngangs, mixed, max_iter, max_refine;
   double tol;
   uint32_t *keys, *sorted;
   double *SA, *V, *R, *W, *WT, *last;
   int64_t keys_stride, sa_stride, v_stride, r_stride, last_stride;
+  int* gstate;
+  double* gpart;
+  int64_t gpart_stride;
 };
+extern int64_t g_batched_gang_unit;  // elements (n d) per gang member; 0: no gangs
 // Resets the queue and the results, then launches the persistent kernel with `slots` workgroups.
 void batched_launch(hipStream_t st, const BatchArgs& a, int slots);
 

@@ -27,7 +27,7 @@ def test_autotune_quick(tmp_path):
     assert all(v in autotune.GRAM_CANDIDATES for v in entry["gram_wgs"].values())
     try:
         vals = autotune.apply("f32", 512, path=p)
-        assert set(vals) == {"fused_groups_per_cu", "batched_slots", "srht_passa_wgs", "srht_passb_wgs",
+        assert set(vals) == {"fused_groups_per_cu", "batched_slots", "batched_gang_unit", "srht_passa_wgs", "srht_passb_wgs",
                              "srht_fold8_rows_f32", "srht_fold8_rows_f64", "srht_stream_rows_f32",
                              "srht_stream_rows_f64", "gauss_wgs", "gram_wgs"}
     finally:

@@ -247,3 +247,47 @@ def test_batched_argument_errors(ctx):
                                  [lsq.sketch_desc("sjlt", 1024, seed=1, s=4)],
                                  [torch.zeros(300, dtype=torch.float64, device="cuda")],
                                  raise_on_error=False)[0] == lsq.LSQ_ERR_UNSUPPORTED
+
+
+def test_batched_gangs(ctx):
+    """Problems above the gang size are solved by gangs of 2-4 workgroups (rows split in K blocks, the
+    partial sums added in rank order): every problem still meets the oracle bounds, the solutions are
+    bitwise equal for any number of workgroups from 4 up (the gang sizes depend on n d alone), and
+    within the stop rule's tolerance of the solutions without gangs."""
+    from oracle.solve import a_norm_error
+    from paper_1911_02675_amd import lsq
+    cases = CASES[:6] + CASES[10:]
+    ref = None
+    try:
+        lsq.tune("batched_gang_unit", 65536)  # K = round(n d / 65536) up to 4: gangs for most problems here
+        for slots in (0, 4, 7):
+            lsq.tune("batched_slots", slots)
+            cs = _make(cases)
+            st, infos = _run(ctx, cs)
+            assert st == 0
+            xs = [host(c.x) for c in cs]
+            say(f"  gangs, slots {slots}: iters {[i.iters for i in infos]}")
+            if ref is None:
+                ref = xs
+                for c, info in zip(cs, infos):
+                    _check_case(c, info)
+            else:
+                for a, b in zip(ref, xs):
+                    assert np.array_equal(a, b)
+        # fewer workgroups than a gang needs: refused
+        lsq.tune("batched_slots", 3)
+        cs = _make([CASES[3]])  # n d = 5.1e6: a gang of 4
+        with pytest.raises(lsq.LsqError) as e:
+            _run(ctx, cs)
+        assert e.value.status == lsq.LSQ_ERR_UNSUPPORTED
+    finally:
+        lsq.tune("batched_slots", 0)
+        lsq.tune("batched_gang_unit", 8 << 20)
+    lsq.tune("batched_gang_unit", 0)
+    try:
+        cs = _make(cases)
+        _run(ctx, cs)
+        for c, x in zip(cs, ref):
+            assert a_norm_error(c.A64, host(c.x), x) <= 3e-10
+    finally:
+        lsq.tune("batched_gang_unit", 8 << 20)
