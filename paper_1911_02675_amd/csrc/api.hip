@@ -1359,6 +1359,9 @@ lsq_status lsq_tune(const char* key, int64_t value) {
                         {"srht_passa_wgs", &g_srht_passa_wgs, 0, 1 << 22},
                         {"srht_passb_wgs", &g_srht_passb_wgs, 256, 1 << 20},
                         {"gauss_wgs", &g_gauss_wgs, 64, 1 << 16},
+                        {"gauss_planes_min_d", &g_gauss_planes_min_d, 1, 1 << 30},
+                        {"gauss_planes_wgs", &g_gauss_planes_wgs, 8, 1 << 16},
+                        {"gauss_chunk_rows", &g_gauss_chunk_rows, 0, 1 << 30},
                         {"gram_wgs", &g_gram_wgs, 64, 1 << 16}};
   for (const Knob& kn : knobs)
     if (k == kn.key) {

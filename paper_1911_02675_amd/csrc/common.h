@@ -35,26 +35,35 @@ __host__ __device__ __forceinline__ void mul128(uint64_t a, uint64_t b, uint64_t
 #endif
 }
 
+// Philox4x64 with its state exposed, so that the ten rounds of one block can be evaluated in pieces
+// (rounds [R0, R1) at a time) spread between other instructions.  Round r uses the key bumped r times
+// by the Weyl constants.
+struct PhiloxState {
+  uint64_t c0, c1, c2, c3, k0, k1;
+  template <int R0, int R1>
+  __host__ __device__ __forceinline__ void rounds() {
+    const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = R0; r < R1; ++r) {
+      const uint64_t kr0 = k0 + (uint64_t)r * W0, kr1 = k1 + (uint64_t)r * W1;
+      uint64_t lo0, hi0, lo1, hi1;
+      mul128(M0, c0, lo0, hi0);
+      mul128(M1, c2, lo1, hi1);
+      const uint64_t n0 = hi1 ^ c1 ^ kr0, n2 = hi0 ^ c3 ^ kr1;
+      c0 = n0;
+      c1 = lo1;
+      c2 = n2;
+      c3 = lo0;
+    }
+  }
+};
+
 __host__ __device__ __forceinline__ u64x4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
                                                         uint64_t c3, uint64_t k0, uint64_t k1) {
-  const uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
-  const uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
-#pragma unroll
-  for (int r = 0; r < 10; ++r) {
-    if (r) {
-      k0 += W0;
-      k1 += W1;
-    }
-    uint64_t lo0, hi0, lo1, hi1;
-    mul128(M0, c0, lo0, hi0);
-    mul128(M1, c2, lo1, hi1);
-    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-  return {c0, c1, c2, c3};
+  PhiloxState s{c0, c1, c2, c3, k0, k1};
+  s.rounds<0, 10>();
+  return {s.c0, s.c1, s.c2, s.c3};
 }
 
 enum : uint64_t { TAG_SRHT = 1, TAG_SJLT = 2, TAG_GAUSS = 3 };

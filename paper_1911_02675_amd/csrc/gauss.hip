@@ -3,6 +3,8 @@
 // its block of S in registers from Philox words and multiplies it with a tile of A on the matrix cores.
 // The reduction over the long dimension n is split across workgroups (partials), then summed in a fixed
 // order.
+#include <type_traits>
+
 #include "internal.h"
 
 namespace lsq {
@@ -379,6 +381,242 @@ __global__ __launch_bounds__(GB_WAVES * 64) void k_gauss_bf16(uint64_t seed, uin
   }
 }
 
+// --------------------------------------------------------------------------------------------------
+// Precision form for wide A (d >= g_gauss_planes_min_d).  The three BF16 terms of A are formed once per
+// chunk of rows by k_gauss_split3 and stored in the order the matrix cores read them: unit (k-block kb
+// of 32 rows, column group g of 512 columns, term p) is 32 KB, 32 column tiles of 1 KB, lane l of tile
+// ct holding rows 8 (l / 16) .. + 7 of column 512 g + 16 ct + l % 16 (zero past the chunk and past d).
+// The product kernel moves whole units into LDS with global-to-LDS loads (no registers, no VALU), and
+// every normal meets 512 columns (three MFMAs per 16 of them), twice the reach of k_gauss_bf16: the
+// Philox and Box-Muller work per MFMA halves and the split leaves the product loop altogether.
+// Workgroup: 8 wavefronts (two per SIMD), 64 rows of S A x 512 columns; wavefront w keeps the 4 x 4
+// tiles of columns 64 w .. 64 w + 63 (row tile r, column tile c: acc[r][c]).  The four fragments of S
+// a step needs are evaluated by four wavefronts, one Philox block per lane: wavefront w (row tile w % 4)
+// forms the fragments of the steps of parity w / 4, during the step two before, and passes them on
+// through LDS; on each SIMD one wavefront forms normals while both issue MFMAs.  A ring of 4 units in
+// LDS keeps three in flight.  FP32 chains of GP_FOLD steps are added into FP32 sums, and those into the
+// FP64 partial in global memory every GP_FLUSH steps and at the end.
+// --------------------------------------------------------------------------------------------------
+constexpr int GP_WAVES = 8, GP_MT = 64, GP_NT = 512, GP_WCT = 4, GP_UNIT = 32768, GP_RING = 4;
+constexpr int GP_DMA = GP_UNIT / (GP_WAVES * 64 * 16);  // 16-byte global-to-LDS loads per thread per unit
+constexpr int GP_FOLD = 8, GP_FLUSH = 64;
+static_assert(GP_WAVES * GP_WCT * 16 == GP_NT && GP_NT * 32 * 2 == GP_UNIT && GP_DMA >= 1, "unit shape");
+static_assert(GP_FLUSH % GP_FOLD == 0, "flushes at fold boundaries");
+
+// One workgroup per (k-block, column group): wavefront w forms column tiles w + 4 j (j < 8), lane l
+// its fragment of 8 rows; the three terms a = A1 + A2 + A3 as in k_gauss_bf16 (rounded to FP32 first).
+template <typename TA>
+__global__ __launch_bounds__(256) void k_gauss_split3(const TA* __restrict__ A, int64_t lda, int64_t d,
+                                                      int64_t r0, int64_t r1, int ng, char* __restrict__ planes) {
+  const int64_t kb = blockIdx.x / ng;
+  const int g = (int)(blockIdx.x - kb * ng);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t rb = r0 + kb * 32 + 8 * (lane >> 4);
+  char* ub = planes + (kb * ng + g) * 3 * (int64_t)GP_UNIT + lane * 16;
+#pragma unroll 2
+  for (int j = 0; j < GP_NT / 16 / 4; ++j) {
+    const int ct = w + 4 * j;
+    const int64_t col = (int64_t)g * GP_NT + ct * 16 + (lane & 15);
+    g_bf8 h, gg, e;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t row = rb + i;
+      const float a = (row < r1 && col < d) ? (float)A[row * lda + col] : 0.0f;
+      const __bf16 h0 = (__bf16)a;
+      const float r = a - (float)h0;
+      const __bf16 g0 = (__bf16)r;
+      const float q = r - (float)g0;
+      h[i] = h0;
+      gg[i] = g0;
+      e[i] = (__bf16)q;
+    }
+    *(g_bf8*)(ub + ct * 1024) = h;
+    *(g_bf8*)(ub + GP_UNIT + ct * 1024) = gg;
+    *(g_bf8*)(ub + 2 * GP_UNIT + ct * 1024) = e;
+  }
+}
+
+// Eight normals S[irow][8 blk + i] rounded to BF16 (zeros for rows past m) from a finished Philox block.
+__device__ __forceinline__ g_bf8 gp_normals(const PhiloxState& P, bool iok) {
+  const uint64_t ws[4] = {P.c0, P.c1, P.c2, P.c3};
+  g_bf8 o;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float c, sn;
+    box_muller_pair_hw(ws[q], c, sn);
+    o[2 * q] = (__bf16)(iok ? c : 0.0f);
+    o[2 * q + 1] = (__bf16)(iok ? sn : 0.0f);
+  }
+  return o;
+}
+
+__global__ __launch_bounds__(GP_WAVES * 64, 1) void k_gauss_bf16_planes(
+    uint64_t seed, uint64_t t, const char* __restrict__ planes, int64_t r0, int64_t nkb, int ng, int64_t kbps,
+    int rtiles, int64_t m, int64_t d, int fresh_in, double* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) char Ring[GP_RING * GP_UNIT];
+  __shared__ __attribute__((aligned(16))) g_bf8 Nrm[2][4][64];
+  const int lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  // XCD-aware order: consecutive workgroups are dispatched to different XCDs, so the logical index
+  // L = (b mod 8) (G / 8) + b / 8 puts the row tiles of one (column group, k-split) on one XCD, where they
+  // read the same units from that XCD's L2
+  const int G = gridDim.x, b = blockIdx.x;
+  const int L = (G % 8 == 0) ? (b % 8) * (G / 8) + b / 8 : b;
+  const int rt = L % rtiles, rest = L / rtiles, g = rest % ng, ksi = rest / ng;
+  const int64_t kb0 = (int64_t)ksi * kbps, kb1 = min(nkb, kb0 + kbps);
+  const int ns = kb1 > kb0 ? (int)(kb1 - kb0) : 0;
+  const int nu = 3 * ns;
+  const int lg = lane >> 4;
+  const int myrt = wv & 3, par = wv >> 2;  // the row tile and the step parity whose normals this wavefront forms
+  const int64_t irow = (int64_t)rt * GP_MT + myrt * 16 + (lane & 15);
+  const bool iok = irow < m;
+  const char* gsrc = planes + ((kb0 * ng + g) * 3) * (int64_t)GP_UNIT + (wv * 1024 + lane * 16);
+  const int64_t ustride = (int64_t)ng * 3 * GP_UNIT;  // bytes from one step's units to the next step's
+
+  // unit j (step j / 3, term j % 3) into ring slot j % 4; past the last unit the last one is loaded
+  // again into a slot nobody reads, so every unit section waits for the same count of loads
+  auto issue = [&](int j) {
+    const int jj = j < nu ? j : nu - 1;
+    const int s = jj / 3, p = jj - 3 * s;
+    const char* src = gsrc + s * ustride + p * (int64_t)GP_UNIT;
+    char* dst = Ring + (j % GP_RING) * GP_UNIT + wv * 1024;
+#pragma unroll
+    for (int q = 0; q < GP_DMA; ++q)
+      __builtin_amdgcn_global_load_lds(src + q * GP_WAVES * 1024,
+                                       (__attribute__((address_space(3))) void*)(dst + q * GP_WAVES * 1024), 16, 0,
+                                       0);
+  };
+  auto philox_at = [&](int s) {
+    return PhiloxState{(uint64_t)((r0 >> 3) + (kb0 + s) * 4 + lg), TAG_GAUSS, t, (uint64_t)irow, seed, 0};
+  };
+
+  g_f4 acc[4][GP_WCT], hi[4][GP_WCT];
+#pragma unroll
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < GP_WCT; ++c) {
+      acc[r][c] = (g_f4){0.0f, 0.0f, 0.0f, 0.0f};
+      hi[r][c] = (g_f4){0.0f, 0.0f, 0.0f, 0.0f};
+    }
+  bool fresh = fresh_in != 0;
+  // element offsets inside this k-split's partial (m d < 2^28 on this path: 32-bit byte offsets)
+  char* pbase = (char*)(part + (int64_t)ksi * m * d);
+  const int64_t row0 = (int64_t)rt * GP_MT + 4 * lg, col0 = (int64_t)g * GP_NT + wv * (GP_WCT * 16) + (lane & 15);
+  const uint32_t o0 = (uint32_t)(row0 * d + col0);
+  const int64_t rlim = m - row0, clim = d - col0;  // rows r 16 + v < rlim, columns c 16 < clim
+  // The sums into the FP64 partial: the first store of a launch sequence, then atomic adds without
+  // return (no registers held, no wait).  Each address has one writer (this lane), whose adds are applied
+  // in program order, so the partial is the same at every run.
+  auto flush = [&]() {
+    const bool st = fresh;
+    // the addresses are formed here, not hoisted out of the step loop (they would hold 64+ registers)
+    uint32_t ob = o0;
+    asm volatile("" : "+v"(ob));
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int rr = r * 16 + v;
+        if (rr < rlim) {
+          const uint32_t orow = ob + (uint32_t)(rr * d);
+#pragma unroll
+          for (int c = 0; c < GP_WCT; ++c)
+            if (c * 16 < clim) {
+              double* q = (double*)(pbase + (orow + (uint32_t)(c * 16)) * 8u);
+              if (st) *q = (double)hi[r][c][v];
+              else __hip_atomic_fetch_add(q, (double)hi[r][c][v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+      }
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int c = 0; c < GP_WCT; ++c) hi[r][c] = (g_f4){0.0f, 0.0f, 0.0f, 0.0f};
+    fresh = false;
+    vm_wait<0>();  // the stores and adds have left: unit loads are counted from zero again
+  };
+
+  if (ns > 0) {
+    issue(0);
+    issue(1);
+    issue(2);
+    {
+      PhiloxState P = philox_at(par);
+      P.rounds<0, 10>();
+      Nrm[par][myrt][lane] = gp_normals(P, iok);
+    }
+    g_bf8 af[4];
+    // one unit of step s: wait for it, pass the barrier, start the unit three ahead, 16 MFMAs; GEN: the
+    // Philox rounds [R0, R1) of this wavefront's next block ride along
+    auto unit = [&](int s, auto pc, auto gen, PhiloxState& P) {
+      constexpr int p = decltype(pc)::value;
+      constexpr bool GEN = decltype(gen)::value;
+      const int j = 3 * s + p;
+      vm_wait<2 * GP_DMA>();
+      lds_barrier();  // unit j has landed for every wavefront; unit j - 1's slot is no longer read
+      issue(j + 3);
+      if constexpr (p == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) af[r] = Nrm[s & 1][r][lane];
+      }
+      g_bf8 bv[GP_WCT];
+      {
+        static_assert(GP_WCT == 4, "one four-read statement per unit");
+        const uint32_t U = (uint32_t)(uintptr_t)(Ring + (j % GP_RING) * GP_UNIT + wv * GP_WCT * 1024 + lane * 16);
+        int4 x0, x1, x2, x3;
+        lds_read4_b128<1024>(U, x0, x1, x2, x3);
+        bv[0] = __builtin_bit_cast(g_bf8, x0);
+        bv[1] = __builtin_bit_cast(g_bf8, x1);
+        bv[2] = __builtin_bit_cast(g_bf8, x2);
+        bv[3] = __builtin_bit_cast(g_bf8, x3);
+      }
+#pragma unroll
+      for (int c = 0; c < GP_WCT; ++c)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bv[c], acc[r][c], 0, 0, 0);
+      if constexpr (GEN) {
+        if constexpr (p == 0) P.rounds<0, 4>();
+        else if constexpr (p == 1) P.rounds<4, 8>();
+        else P.rounds<8, 10>();
+      }
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using T = std::true_type;
+    using F = std::false_type;
+    for (int s = 0; s < ns; ++s) {
+      if ((s & 1) == par) {
+        // this wavefront's fragment of step s is consumed now: form the one of step s + 2
+        PhiloxState P = philox_at(s + 2);
+        unit(s, I0{}, T{}, P);
+        unit(s, I1{}, T{}, P);
+        unit(s, I2{}, T{}, P);
+        Nrm[s & 1][myrt][lane] = gp_normals(P, iok);  // every wavefront read slot s & 1 before this step's
+                                                      // second barrier
+      } else {
+        PhiloxState P{};
+        unit(s, I0{}, F{}, P);
+        unit(s, I1{}, F{}, P);
+        unit(s, I2{}, F{}, P);
+      }
+      if ((s + 1) % GP_FOLD == 0 || s == ns - 1) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+          for (int c = 0; c < GP_WCT; ++c) {
+            hi[r][c] += acc[r][c];
+            acc[r][c] = (g_f4){0.0f, 0.0f, 0.0f, 0.0f};
+          }
+        if ((s + 1) % GP_FLUSH == 0 || s == ns - 1) flush();
+      }
+    }
+  } else if (fresh) {
+    flush();  // an empty k-split still initialises its partial
+  }
+}
+
 int g_gauss_wgs = 1024;
 
 static int64_t gauss_nks(int64_t m, int64_t d, int64_t n) {
@@ -391,8 +629,46 @@ static int64_t gauss_nks(int64_t m, int64_t d, int64_t n) {
   return nks < 1 ? 1 : nks;
 }
 
+int g_gauss_planes_min_d = 384;
+int g_gauss_planes_wgs = 256;
+int g_gauss_chunk_rows = 0;
+
+// The plan of the planes form: column groups, row tiles, k-splits per launch (about g_gauss_planes_wgs
+// workgroups, one per compute unit) and rows per chunk (planes of about 1 GiB unless set).
+struct GpPlan {
+  int ng, rtiles, ks;
+  int64_t rc;
+};
+// (m d below 2^28: the product kernel addresses its partial with 32-bit byte offsets)
+static bool gauss_planes(int64_t m, int64_t d, int bf16) {
+  return bf16 && d >= g_gauss_planes_min_d && m * d < ((int64_t)1 << 28);
+}
+static GpPlan gp_plan(int64_t m, int64_t d, int64_t n) {
+  GpPlan p;
+  p.ng = (int)((d + GP_NT - 1) / GP_NT);
+  p.rtiles = (int)((m + GP_MT - 1) / GP_MT);
+  const int64_t tiles = (int64_t)p.ng * p.rtiles;
+  int64_t ks = (g_gauss_planes_wgs + tiles - 1) / tiles;
+  const int64_t nkb = (n + 31) / 32;
+  if (ks > nkb) ks = nkb;
+  if (ks > 512) ks = 512;
+  p.ks = ks < 1 ? 1 : (int)ks;
+  int64_t rc = g_gauss_chunk_rows > 0 ? g_gauss_chunk_rows : ((int64_t)1 << 30) / (6 * (int64_t)GP_NT * p.ng);
+  rc = rc / 32 * 32;
+  if (rc < 32) rc = 32;
+  const int64_t n32 = nkb * 32;
+  p.rc = rc < n32 ? rc : n32;
+  return p;
+}
+static size_t gp_part_bytes(int64_t m, int64_t d, const GpPlan& p) {
+  return ((size_t)p.ks * m * d * sizeof(double) + 255) / 256 * 256;
+}
+
 size_t gauss_partial_bytes(int64_t m, int64_t d, int64_t n, int bf16) {
-  (void)bf16;
+  if (gauss_planes(m, d, bf16)) {
+    const GpPlan p = gp_plan(m, d, n);
+    return gp_part_bytes(m, d, p) + (size_t)(p.rc / 32) * p.ng * 3 * GP_UNIT;
+  }
   return (size_t)gauss_nks(m, d, n) * m * d * sizeof(double);
 }
 
@@ -402,6 +678,26 @@ void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a
   const int64_t nks = gauss_nks(m, d, n);
   int64_t kchunk = (n + nks - 1) / nks;
   dim3 g((unsigned)((m + GM_ROWS - 1) / GM_ROWS), (unsigned)((d + GM_COLS - 1) / GM_COLS), (unsigned)nks);
+  if (gauss_planes(m, d, bf16)) {
+    const GpPlan p = gp_plan(m, d, n);
+    char* planes = (char*)partials + gp_part_bytes(m, d, p);
+    const int grid = p.rtiles * p.ng * p.ks;
+    for (int64_t r0 = 0; r0 < n; r0 += p.rc) {
+      const int64_t r1 = min(n, r0 + p.rc), nkb = (r1 - r0 + 31) / 32;
+      const dim3 gs((unsigned)(nkb * p.ng));
+      if (a_f32)
+        hipLaunchKernelGGL(k_gauss_split3<float>, gs, dim3(256), 0, st, (const float*)A, lda, d, r0, r1, p.ng, planes);
+      else
+        hipLaunchKernelGGL(k_gauss_split3<double>, gs, dim3(256), 0, st, (const double*)A, lda, d, r0, r1, p.ng,
+                           planes);
+      const int64_t kbps = (nkb + p.ks - 1) / p.ks;
+      hipLaunchKernelGGL(k_gauss_bf16_planes, dim3((unsigned)grid), dim3(GP_WAVES * 64), 0, st, seed, t,
+                         (const char*)planes, r0, nkb, p.ng, kbps, p.rtiles, m, d, r0 == 0 ? 1 : 0, partials);
+    }
+    hipLaunchKernelGGL(k_gauss_reduce, dim3((unsigned)((m * d + 255) / 256)), dim3(256), 0, st, partials,
+                       (int64_t)p.ks, m, d, 1.0 / sqrt((double)m), SA, ldsa);
+    return;
+  }
   if (bf16) {
     kchunk = (kchunk + GB_K - 1) / GB_K * GB_K;  // whole steps of 32 rows per chunk
     const bool v4 = a_f32 && ((uintptr_t)A % 16 == 0) && lda % 4 == 0 && d % 4 == 0;

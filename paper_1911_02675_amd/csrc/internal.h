@@ -7,6 +7,43 @@
 
 namespace lsq {
 
+// ---- device helpers shared by the kernels ------------------------------------------------------
+// Workgroup barrier for data exchanged through LDS only: this wavefront's LDS accesses complete
+// (lgkmcnt), then s_barrier; loads from global memory stay in flight (__syncthreads also drains them).
+// The empty asm statements keep the compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt unconstrained
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// s_waitcnt vmcnt(N): at most N of this wavefront's vector memory instructions (global loads, stores and
+// global-to-LDS loads, in issue order) still outstanding; expcnt and lgkmcnt unconstrained.
+template <int N>
+__device__ __forceinline__ void vm_wait() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+// Four 16-byte LDS reads at base + 0, 1, 2, 3 x STRIDE bytes, waited for inside the same statement.
+// For LDS that global-to-LDS loads fill: the compiler cannot tell which of those loads an ordinary LDS
+// read depends on and waits for all of them (vmcnt(0)), which would drain the loads issued ahead; the
+// caller orders these reads after the loads they need (vm_wait + barrier) itself.
+template <int STRIDE>
+__device__ __forceinline__ void lds_read4_b128(uint32_t base, int4& a, int4& b, int4& c, int4& e) {
+  static_assert(3 * STRIDE < 65536, "ds_read offset range");
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %4 offset:%5\n\t"
+      "ds_read_b128 %2, %4 offset:%6\n\t"
+      "ds_read_b128 %3, %4 offset:%7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(e)
+      : "v"(base), "i"(STRIDE), "i"(2 * STRIDE), "i"(3 * STRIDE)
+      : "memory");
+}
+
 // ---- draws.hip ----------------------------------------------------------------------------------
 // Per padded row j < N: sign (int8 +-1) and 64-bit selection key (SRHT specification).
 void launch_srht_draw(hipStream_t st, uint64_t seed, uint64_t t, int64_t N, int8_t* signs,
@@ -68,6 +105,8 @@ void sjlt_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_
                 int64_t d, int64_t lda, int64_t m, int s, SjltScratch sc, double* SA, int64_t ldsa);
 
 // Gaussian sketch SA = G A with G generated in registers (FP64 matrix cores; bf16 split on request).
+// The workspace (partials) holds the FP64 partial sums and, for the BF16 form at d >= the planes
+// threshold, the three BF16 terms of one chunk of rows of A after them.
 size_t gauss_partial_bytes(int64_t m, int64_t d, int64_t n, int bf16);
 void gauss_apply(hipStream_t st, uint64_t seed, uint64_t t, const void* A, int a_f32, int64_t n,
                  int64_t d, int64_t lda, int64_t m, int bf16, double* partials, double* SA,
@@ -147,6 +186,9 @@ extern int g_srht_stream_rows_f64;  // the same for an FP64 intermediate
 extern int g_srht_passa_wgs;        // SRHT pass A: workgroups aimed at (0: by the transform precision)
 extern int g_srht_passb_wgs;        // LDS-staged SRHT pass B: workgroups aimed at when splitting j_hi
 extern int g_gauss_wgs;             // Gaussian sketch: workgroups aimed at when splitting n
+extern int g_gauss_planes_min_d;    // BF16 Gaussian sketch: smallest d taking the planes form
+extern int g_gauss_planes_wgs;      // ... its workgroups per launch aimed at (one per compute unit)
+extern int g_gauss_chunk_rows;      // ... rows of A per chunk (0: planes of about 1 GiB)
 extern int g_gram_wgs;              // CholeskyQR Gram kernel: workgroups aimed at when splitting m
 extern int g_fused_groups_per_cu;   // tuning: fused-pass workgroups per CU
 extern int g_batched_slots;         // tuning: batched-kernel workgroups (0 = one per CU)

@@ -819,16 +819,6 @@ static int srht_js_cap(int64_t N2) { return srht_js(N2); }
 constexpr int SRHT_LROWS = 256;                 // rows of a bucket per tile build
 constexpr int SRHT_LMAXT = SRHT_LROWS / 16 + 8; // tiles per build at most (up to 8 fold groups)
 
-// Workgroup barrier for data exchanged through LDS only: this wavefront's LDS accesses complete
-// (lgkmcnt), then s_barrier; loads from global memory stay in flight (__syncthreads also drains them).
-// The empty asm statements keep the compiler from moving memory accesses across the barrier.
-__device__ __forceinline__ void lds_barrier() {
-  asm volatile("" ::: "memory");
-  __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt unconstrained
-  __builtin_amdgcn_s_barrier();
-  asm volatile("" ::: "memory");
-}
-
 // Row tiles of one chunk [cb, ce) of a bucket's selected rows (ce - cb <= SRHT_LROWS), grouped by
 // e = k_hi mod F (F = 2^FB, the width of the fold) in tiles of 16 (the order of rows inside a tile does not
 // change any output row; empty slots stay -1): one thread per row places itself with an LDS counter per
@@ -1145,21 +1135,14 @@ __device__ __forceinline__ void srht_dma16(const void* src, void* lds) {
   __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
 }
 
-template <int N>
-__device__ __forceinline__ void srht_vm_wait() {
-  // vmcnt(N) (bits 3:0 and 15:14), expcnt and lgkmcnt unconstrained
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
-}
-
 // vmcnt(k IPT) for a runtime k in [0, KMAX] (the waitcnt operand is an immediate)
 template <int IPT, int KMAX>
 __device__ __forceinline__ void srht_vm_wait_stages(int k) {
   if constexpr (KMAX <= 0) {
-    srht_vm_wait<0>();
+    vm_wait<0>();
   } else {
     if (k >= KMAX)
-      srht_vm_wait<KMAX * IPT>();
+      vm_wait<KMAX * IPT>();
     else
       srht_vm_wait_stages<IPT, KMAX - 1>(k);
   }
@@ -1344,7 +1327,7 @@ __global__ __launch_bounds__(64 * SRHT2_NW, 1) void k_srht_passB_v2(
         // Prologue: stages 0 .. NBUF - 2 in flight, stage 0 folded (a stage call with no tiles).  The counts
         // of the waits are of this wave's stage loads alone: the previous sweep's result stores are drained
         // first.
-        srht_vm_wait<0>();
+        vm_wait<0>();
         lds_barrier();  // the previous sweep no longer reads the buffers
         const int npro = min(nst, NBUF - 1);
         for (int st = 0; st < npro; ++st) issue(st);

@@ -26,15 +26,43 @@ def ctx():
     c.close()
 
 
-@pytest.mark.parametrize("n,d,m,dtype", [(5000, 33, 100, "f32"), (5000, 300, 300, "f64"), (70000, 64, 200, "f32"),
-                                         (3000, 1, 17, "f32"), (20001, 257, 129, "f32")])
-def test_gauss_bf16_sketch(ctx, n, d, m, dtype):
+# (n, d, m, dtype, rows per chunk of the planes form or None).  d >= 384 takes the planes form (the three
+# BF16 terms of A formed once per chunk of rows, 64 x 512 output tiles); ragged n, d and m, FP64 A,
+# several chunks (a small chunk size), and an m that leaves k-splits empty in the last chunk.
+CASES = [(5000, 33, 100, "f32", None), (5000, 300, 300, "f64", None), (70000, 64, 200, "f32", None),
+         (3000, 1, 17, "f32", None), (20001, 257, 129, "f32", None),
+         (20001, 700, 130, "f32", None), (9000, 512, 64, "f64", None), (5000, 384, 300, "f32", None),
+         (40000, 520, 70, "f32", 4096), (6000, 1000, 33, "f32", 2048)]
+
+
+@pytest.mark.parametrize("n,d,m,dtype,chunk", CASES)
+def test_gauss_bf16_sketch(ctx, n, d, m, dtype, chunk):
+    from paper_1911_02675_amd import lsq
+    say("gauss bf16", n, d, m, dtype, chunk)
+    try:
+        if chunk:
+            lsq.tune("gauss_chunk_rows", chunk)
+        _check_bf16_sketch(ctx, n, d, m, dtype)
+    finally:
+        lsq.tune("gauss_chunk_rows", 0)
+
+
+def test_gauss_bf16_both_forms(ctx):
+    """At d >= 384 the tile form (forced by a high threshold) and the planes form both meet the bound."""
+    from paper_1911_02675_amd import lsq
+    try:
+        lsq.tune("gauss_planes_min_d", 1 << 20)
+        _check_bf16_sketch(ctx, 20001, 700, 130, "f32")
+    finally:
+        lsq.tune("gauss_planes_min_d", 384)
+
+
+def _check_bf16_sketch(ctx, n, d, m, dtype):
     import torch
 
     from oracle.draws import gaussian_normals, round_bf16
     from oracle.sketch import gaussian_sketch_bf16
     from paper_1911_02675_amd import lsq
-    say("gauss bf16", n, d, m, dtype)
     rng = np.random.default_rng(n + d)
     A = rng.standard_normal((n, d)) * rng.uniform(0.5, 2.0, d)[None, :]
     if dtype == "f32":
@@ -58,21 +86,23 @@ def test_gauss_bf16_sketch(ctx, n, d, m, dtype):
     assert np.all(err <= bound)
 
 
-def test_gauss_bf16_preconditioner_quality(ctx):
+@pytest.mark.parametrize("d", [128, 512])
+def test_gauss_bf16_preconditioner_quality(ctx, d):
     """The BF16 sketch is a working preconditioner at kappa = 1e6: PCG to 1e-10 in about the
-    iterations of the FP64 Gaussian sketch with the same draws."""
+    iterations of the FP64 Gaussian sketch with the same draws (tile form at d = 128, planes form at
+    d = 512)."""
     import torch
 
     from oracle.solve import a_norm_error
     from paper_1911_02675_amd import lsq
     from synth import make_planted
-    P = make_planted(1 << 15, 128, 1e6, sigma=0.01, seed=77, want64=False, want32=True)
+    P = make_planted(1 << 15, d, 1e6, sigma=0.01, seed=77, want64=False, want32=True)
     A32, y, xs = P["A32"], P["y32"], P["x_star"]
     Ad, yd = torch.from_numpy(A32).cuda(), torch.from_numpy(y).cuda()
     its = {}
     for comp in ("f64", "bf16"):
-        x = torch.zeros(128, dtype=torch.float64, device="cuda")
-        st, info = ctx.pcg_solve(Ad, yd, lsq.sketch_desc("gaussian", 512, seed=5, compute=comp), x, tol=1e-10,
+        x = torch.zeros(d, dtype=torch.float64, device="cuda")
+        st, info = ctx.pcg_solve(Ad, yd, lsq.sketch_desc("gaussian", 4 * d, seed=5, compute=comp), x, tol=1e-10,
                                  mixed=1, max_refine=10, max_iter=300)
         torch.cuda.synchronize()
         e = a_norm_error(A32.astype(np.float64), x.cpu().numpy(), xs)
