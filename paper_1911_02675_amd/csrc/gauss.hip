@@ -473,18 +473,23 @@ __global__ __launch_bounds__(GP_WAVES * 64, 1) void k_gauss_bf16_planes(
   const char* gsrc = planes + ((kb0 * ng + g) * 3) * (int64_t)GP_UNIT + (wv * 1024 + lane * 16);
   const int64_t ustride = (int64_t)ng * 3 * GP_UNIT;  // bytes from one step's units to the next step's
 
-  // unit j (step j / 3, term j % 3) into ring slot j % 4; past the last unit the last one is loaded
-  // again into a slot nobody reads, so every unit section waits for the same count of loads
-  auto issue = [&](int j) {
+  // unit j (step j / 3, term j % 3) into ring slot j % 4, one 16-byte load per lane per piece q < GP_DMA;
+  // past the last unit the last one is loaded again into a slot nobody reads, so every unit section
+  // waits for the same count of loads
+  auto unit_src = [&](int j) {
     const int jj = j < nu ? j : nu - 1;
     const int s = jj / 3, p = jj - 3 * s;
-    const char* src = gsrc + s * ustride + p * (int64_t)GP_UNIT;
+    return gsrc + s * ustride + p * (int64_t)GP_UNIT;
+  };
+  auto issue_piece = [&](const char* src, int j, int q) {
     char* dst = Ring + (j % GP_RING) * GP_UNIT + wv * 1024;
+    __builtin_amdgcn_global_load_lds(src + q * GP_WAVES * 1024,
+                                     (__attribute__((address_space(3))) void*)(dst + q * GP_WAVES * 1024), 16, 0, 0);
+  };
+  auto issue = [&](int j) {
+    const char* src = unit_src(j);
 #pragma unroll
-    for (int q = 0; q < GP_DMA; ++q)
-      __builtin_amdgcn_global_load_lds(src + q * GP_WAVES * 1024,
-                                       (__attribute__((address_space(3))) void*)(dst + q * GP_WAVES * 1024), 16, 0,
-                                       0);
+    for (int q = 0; q < GP_DMA; ++q) issue_piece(src, j, q);
   };
   auto philox_at = [&](int s) {
     return PhiloxState{(uint64_t)((r0 >> 3) + (kb0 + s) * 4 + lg), TAG_GAUSS, t, (uint64_t)irow, seed, 0};
@@ -554,7 +559,7 @@ __global__ __launch_bounds__(GP_WAVES * 64, 1) void k_gauss_bf16_planes(
       const int j = 3 * s + p;
       vm_wait<2 * GP_DMA>();
       lds_barrier();  // unit j has landed for every wavefront; unit j - 1's slot is no longer read
-      issue(j + 3);
+      const char* nsrc = unit_src(j + 3);
       if constexpr (p == 0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) af[r] = Nrm[s & 1][r][lane];
@@ -570,15 +575,28 @@ __global__ __launch_bounds__(GP_WAVES * 64, 1) void k_gauss_bf16_planes(
         bv[2] = __builtin_bit_cast(g_bf8, x2);
         bv[3] = __builtin_bit_cast(g_bf8, x3);
       }
+      // the loads of unit j + 3 go out one piece per column tile, between the MFMAs: the CU's address
+      // unit takes about 20 cycles per 1 KB piece, and a wavefront whose load waits for it issues nothing
+      // after it, so eight wavefronts issuing all their pieces at once would stall their MFMAs
+      static_assert(GP_DMA == GP_WCT, "one piece per column tile");
 #pragma unroll
-      for (int c = 0; c < GP_WCT; ++c)
+      for (int c = 0; c < GP_WCT; ++c) {
+        issue_piece(nsrc, j + 3, c);
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           acc[r][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[r], bv[c], acc[r][c], 0, 0, 0);
+      }
       if constexpr (GEN) {
         if constexpr (p == 0) P.rounds<0, 4>();
         else if constexpr (p == 1) P.rounds<4, 8>();
         else P.rounds<8, 10>();
+      }
+      // the order the scheduler keeps: one load piece, four MFMAs (and a share of the Philox rounds)
+#pragma unroll
+      for (int c = 0; c < GP_WCT; ++c) {
+        __builtin_amdgcn_sched_group_barrier(0x010, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+
       }
     };
     using I0 = std::integral_constant<int, 0>;
