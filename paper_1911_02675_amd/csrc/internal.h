@@ -30,18 +30,110 @@ __device__ __forceinline__ void vm_wait() {
 // For LDS that global-to-LDS loads fill: the compiler cannot tell which of those loads an ordinary LDS
 // read depends on and waits for all of them (vmcnt(0)), which would drain the loads issued ahead; the
 // caller orders these reads after the loads they need (vm_wait + barrier) itself.
-template <int STRIDE>
-__device__ __forceinline__ void lds_read4_b128(uint32_t base, int4& a, int4& b, int4& c, int4& e) {
-  static_assert(3 * STRIDE < 65536, "ds_read offset range");
+template <int O0, int O1, int O2, int O3>
+__device__ __forceinline__ void lds_read4_b128_at(uint32_t base, int4& a, int4& b, int4& c, int4& e) {
+  static_assert(O0 >= 0 && O1 < 65536 && O2 < 65536 && O3 < 65536, "ds_read offset range");
   asm volatile(
-      "ds_read_b128 %0, %4\n\t"
-      "ds_read_b128 %1, %4 offset:%5\n\t"
-      "ds_read_b128 %2, %4 offset:%6\n\t"
-      "ds_read_b128 %3, %4 offset:%7\n\t"
+      "ds_read_b128 %0, %4 offset:%5\n\t"
+      "ds_read_b128 %1, %4 offset:%6\n\t"
+      "ds_read_b128 %2, %4 offset:%7\n\t"
+      "ds_read_b128 %3, %4 offset:%8\n\t"
       "s_waitcnt lgkmcnt(0)"
       : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(e)
-      : "v"(base), "i"(STRIDE), "i"(2 * STRIDE), "i"(3 * STRIDE)
+      : "v"(base), "i"(O0), "i"(O1), "i"(O2), "i"(O3)
       : "memory");
+}
+template <int STRIDE>
+__device__ __forceinline__ void lds_read4_b128(uint32_t base, int4& a, int4& b, int4& c, int4& e) {
+  lds_read4_b128_at<0, STRIDE, 2 * STRIDE, 3 * STRIDE>(base, a, b, c, e);
+}
+template <int O0, int O1>
+__device__ __forceinline__ void lds_read2_b128_at(uint32_t base, int4& a, int4& b) {
+  static_assert(O0 >= 0 && O1 < 65536, "ds_read offset range");
+  asm volatile(
+      "ds_read_b128 %0, %2 offset:%3\n\t"
+      "ds_read_b128 %1, %2 offset:%4\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b)
+      : "v"(base), "i"(O0), "i"(O1)
+      : "memory");
+}
+
+// F values (F = 8 or 16) of 4 or 8 bytes at base + k 64 elements, k < F (ds_read2st64: two per
+// instruction), waited for inside the statement; and the matching writes (not waited for: the next
+// lds_barrier drains them).  Same purpose as lds_read4_b128.
+typedef uint32_t lds_u2 __attribute__((ext_vector_type(2)));
+typedef uint64_t lds_q2 __attribute__((ext_vector_type(2)));
+template <typename V>
+__device__ __forceinline__ void lds_read8_st64(uint32_t base, V (&x)[4]);
+template <>
+__device__ __forceinline__ void lds_read8_st64<lds_u2>(uint32_t base, lds_u2 (&x)[4]) {
+  asm volatile(
+      "ds_read2st64_b32 %0, %4 offset1:1\n\t"
+      "ds_read2st64_b32 %1, %4 offset0:2 offset1:3\n\t"
+      "ds_read2st64_b32 %2, %4 offset0:4 offset1:5\n\t"
+      "ds_read2st64_b32 %3, %4 offset0:6 offset1:7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+      : "v"(base)
+      : "memory");
+}
+template <>
+__device__ __forceinline__ void lds_read8_st64<lds_q2>(uint32_t base, lds_q2 (&x)[4]) {
+  asm volatile(
+      "ds_read2st64_b64 %0, %4 offset1:1\n\t"
+      "ds_read2st64_b64 %1, %4 offset0:2 offset1:3\n\t"
+      "ds_read2st64_b64 %2, %4 offset0:4 offset1:5\n\t"
+      "ds_read2st64_b64 %3, %4 offset0:6 offset1:7\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+      : "v"(base)
+      : "memory");
+}
+template <typename V>
+__device__ __forceinline__ void lds_read16_st64(uint32_t base, V (&x)[8]);
+template <>
+__device__ __forceinline__ void lds_read16_st64<lds_u2>(uint32_t base, lds_u2 (&x)[8]) {
+  asm volatile(
+      "ds_read2st64_b32 %0, %8 offset1:1\n\t"
+      "ds_read2st64_b32 %1, %8 offset0:2 offset1:3\n\t"
+      "ds_read2st64_b32 %2, %8 offset0:4 offset1:5\n\t"
+      "ds_read2st64_b32 %3, %8 offset0:6 offset1:7\n\t"
+      "ds_read2st64_b32 %4, %8 offset0:8 offset1:9\n\t"
+      "ds_read2st64_b32 %5, %8 offset0:10 offset1:11\n\t"
+      "ds_read2st64_b32 %6, %8 offset0:12 offset1:13\n\t"
+      "ds_read2st64_b32 %7, %8 offset0:14 offset1:15\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7])
+      : "v"(base)
+      : "memory");
+}
+template <>
+__device__ __forceinline__ void lds_read16_st64<lds_q2>(uint32_t base, lds_q2 (&x)[8]) {
+  asm volatile(
+      "ds_read2st64_b64 %0, %8 offset1:1\n\t"
+      "ds_read2st64_b64 %1, %8 offset0:2 offset1:3\n\t"
+      "ds_read2st64_b64 %2, %8 offset0:4 offset1:5\n\t"
+      "ds_read2st64_b64 %3, %8 offset0:6 offset1:7\n\t"
+      "ds_read2st64_b64 %4, %8 offset0:8 offset1:9\n\t"
+      "ds_read2st64_b64 %5, %8 offset0:10 offset1:11\n\t"
+      "ds_read2st64_b64 %6, %8 offset0:12 offset1:13\n\t"
+      "ds_read2st64_b64 %7, %8 offset0:14 offset1:15\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3]), "=&v"(x[4]), "=&v"(x[5]), "=&v"(x[6]), "=&v"(x[7])
+      : "v"(base)
+      : "memory");
+}
+// one pair write: values a, b at base + (2 k) and (2 k + 1) x 64 elements
+template <int K>
+__device__ __forceinline__ void lds_write2_st64(uint32_t base, uint32_t a, uint32_t b) {
+  asm volatile("ds_write2st64_b32 %0, %1, %2 offset0:%3 offset1:%4" : : "v"(base), "v"(a), "v"(b), "i"(2 * K),
+               "i"(2 * K + 1) : "memory");
+}
+template <int K>
+__device__ __forceinline__ void lds_write2_st64(uint32_t base, uint64_t a, uint64_t b) {
+  asm volatile("ds_write2st64_b64 %0, %1, %2 offset0:%3 offset1:%4" : : "v"(base), "v"(a), "v"(b), "i"(2 * K),
+               "i"(2 * K + 1) : "memory");
 }
 
 // ---- draws.hip ----------------------------------------------------------------------------------

@@ -1170,36 +1170,59 @@ __device__ __forceinline__ void srht2_stage(Srht2Tiles<TC, QT>& W, const TC* Lc,
   constexpr uint32_t ALL = (1u << NSTEP) - 1u;
   typedef float f4 __attribute__((ext_vector_type(4)));
   typedef double d2 __attribute__((ext_vector_type(2)));
-  // fold operands first (their LDS latency overlaps the first MFMAs)
+  // Every access to the stage buffers goes through the asm statements of internal.h: the buffers are
+  // filled by global-to-LDS loads, and an ordinary LDS access would make the compiler wait for all of
+  // them (the ones issued ahead for later stages included).  The caller's vm_wait and barrier order
+  // these accesses after the loads they need.
+  typedef typename std::conditional<sizeof(TC) == 4, lds_u2, lds_q2>::type V2;
+  typedef typename std::conditional<sizeof(TC) == 4, uint32_t, uint64_t>::type UB;
+  // fold operands first
   TC x[UPT][F];
-  TC* pf[UPT];
+  uint32_t pf[UPT];
   // (the last stage folds the buffer after it too: stale or unused data that nothing reads, so that the
   // fold needs no branch around it when every thread has a unit)
   const bool fa = UNITS >= NT || (fold_next && tid < UNITS);
 #pragma unroll
   for (int i = 0; i < UPT; ++i) {
     const int u = tid + NT * i;
-    pf[i] = Lf + (u >> 6) * F * 64 + (u & 63);
+    pf[i] = (uint32_t)(uintptr_t)(Lf + (u >> 6) * F * 64 + (u & 63));
     if (fa) {
+      V2 x2[F / 2];
+      if constexpr (F == 16) lds_read16_st64<V2>(pf[i], x2);
+      else lds_read8_st64<V2>(pf[i], x2);
 #pragma unroll
-      for (int b = 0; b < F; ++b) x[i][b] = pf[i][b * 64];
+      for (int b = 0; b < F / 2; ++b) {
+        x[i][2 * b] = __builtin_bit_cast(TC, (UB)x2[b][0]);
+        x[i][2 * b + 1] = __builtin_bit_cast(TC, (UB)x2[b][1]);
+      }
     }
   }
+  static_assert(F == 8 || F == 16, "fold widths of the streamed form");
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     const uint32_t sb = W.lowpar[q] ^ ((__popc(W.ka[q] & ja_stage) & 1) ? ALL : 0u);
-    const TC* r = Lc + W.rofs[q];
+    const uint32_t r = (uint32_t)(uintptr_t)(Lc + W.rofs[q]);
+    // the tile's operands of the stage: NSTEP 16-byte reads (FP32) or 2 NSTEP (FP64)
+    int4 v[4];
+    if constexpr (sizeof(TC) == 4) {
+      if constexpr (NSTEP == 2) lds_read2_b128_at<0, 4 * F * 64 * 4>(r, v[0], v[1]);
+      else lds_read4_b128_at<0, 4 * F * 64 * 4, 8 * F * 64 * 4, 12 * F * 64 * 4>(r, v[0], v[1], v[2], v[3]);
+    } else {
+      if constexpr (NSTEP == 1) lds_read2_b128_at<0, 256>(r, v[0], v[1]);
+      else lds_read4_b128_at<0, 256, 4 * F * 64 * 8, 4 * F * 64 * 8 + 256>(r, v[0], v[1], v[2], v[3]);
+    }
+    static_assert(sizeof(TC) == 4 ? (NSTEP == 2 || NSTEP == 4) : (NSTEP == 1 || NSTEP == 2), "stage steps");
 #pragma unroll
     for (int s2 = 0; s2 < NSTEP; ++s2) {
       const TC a = ((sb >> s2) & 1u) ? -W.pos[q] : W.pos[q];
       if constexpr (sizeof(TC) == 4) {
-        const f4 u = *(const f4*)(r + 4 * s2 * F * 64);
+        const f4 u = __builtin_bit_cast(f4, v[s2]);
         W.acc[q][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.x, W.acc[q][0], 0, 0, 0);
         W.acc[q][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.y, W.acc[q][1], 0, 0, 0);
         W.acc[q][2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.z, W.acc[q][2], 0, 0, 0);
         W.acc[q][3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, u.w, W.acc[q][3], 0, 0, 0);
       } else {
-        const d2 u0 = *(const d2*)(r + 4 * s2 * F * 64), u1 = *(const d2*)(r + 4 * s2 * F * 64 + 32);
+        const d2 u0 = __builtin_bit_cast(d2, v[2 * s2]), u1 = __builtin_bit_cast(d2, v[2 * s2 + 1]);
         W.acc64[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.x, W.acc64[q][0], 0, 0, 0);
         W.acc64[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u0.y, W.acc64[q][1], 0, 0, 0);
         W.acc64[q][2] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, u1.x, W.acc64[q][2], 0, 0, 0);
@@ -1219,19 +1242,21 @@ __device__ __forceinline__ void srht2_stage(Srht2Tiles<TC, QT>& W, const TC* Lc,
             x[i][b] = a + c;
             x[i][b + h] = a - c;
           }
-#pragma unroll
-      for (int e = 0; e < F; ++e) pf[i][e * 64] = x[i][e];
+      auto wr = [&](auto kc) {
+        constexpr int k = decltype(kc)::value;
+        lds_write2_st64<k>(pf[i], __builtin_bit_cast(UB, x[i][2 * k]), __builtin_bit_cast(UB, x[i][2 * k + 1]));
+      };
+      wr(std::integral_constant<int, 0>());
+      wr(std::integral_constant<int, 1>());
+      wr(std::integral_constant<int, 2>());
+      wr(std::integral_constant<int, 3>());
+      if constexpr (F == 16) {
+        wr(std::integral_constant<int, 4>());
+        wr(std::integral_constant<int, 5>());
+        wr(std::integral_constant<int, 6>());
+        wr(std::integral_constant<int, 7>());
+      }
     }
-  }
-  // interleave: per MFMA, a share of the fold's VALU and LDS work
-  constexpr int NMF = K * NSTEP * 4;
-  constexpr int NVALU = UPT * F * FB;
-  constexpr int VPM = NMF > 0 ? (NVALU + NMF - 1) / NMF : 0;
-#pragma unroll
-  for (int i = 0; i < NMF; ++i) {
-    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);      // one MFMA
-    __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);    // VALU
-    __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);      // one LDS write
   }
   if constexpr (sizeof(TC) == 4) {
     // the FP32 chains end every 32 values of j_a, and at the last stage
