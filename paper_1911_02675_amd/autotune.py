@@ -53,11 +53,13 @@ PASSA_CANDIDATES = (1 << 14, 1 << 15, 1 << 16, 1 << 17, 1 << 18)
 PASSB_CANDIDATES = (4096, 8192, 16384)
 FOLD_ROWS = (32, 48, 64, 96, 128, 160, 192, 256)
 GAUSS_CANDIDATES = (512, 1024, 2048, 4096)
+PLANES_CANDIDATES = (256, 512, 768, 1024)
 GRAM_CANDIDATES = (1024, 2048, 4096)
 # library defaults, restored after measuring
 DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "batched_gang_unit": 8 << 20, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
             "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128,
-            "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gram_wgs": 2048}
+            "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gauss_planes_wgs": 256,
+            "gram_wgs": 2048}
 
 
 def table_path():
@@ -120,6 +122,8 @@ def choose(entry, dtype="f32", d=1024):
                 out["srht_" + key + "_" + prec] = int(sp[key])
     if "gauss_wgs" in entry:
         out["gauss_wgs"] = int(entry["gauss_wgs"])
+    if "gauss_planes_wgs" in entry:
+        out["gauss_planes_wgs"] = int(entry["gauss_planes_wgs"])
     gw = _by_bucket(entry.get("gram_wgs", {}), d)
     if gw:
         out["gram_wgs"] = int(gw)
@@ -304,6 +308,25 @@ def measure_gauss(ctx, quick=False):
     return res
 
 
+def measure_gauss_planes(ctx, quick=False):
+    """BF16 Gaussian sketch (planes form) time (ms) per workgroup target (its split of n), at the
+    precision form's shape n = 2^22, d = 1024, m = 4 d (n = 2^19 when quick)."""
+    import torch
+    n, d, m = ((1 << 19) if quick else (1 << 22)), 1024, 4096
+    A = torch.randn(n, d, dtype=torch.float32, device="cuda")
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    SA = torch.empty((m, d), dtype=torch.float64, device="cuda")
+    desc = lsq.sketch_desc("gaussian", m, seed=3, compute="bf16")
+    res = {}
+    for w in PLANES_CANDIDATES:
+        lsq.tune("gauss_planes_wgs", w)
+        res[str(w)] = round(_time_ms(lambda: ctx.sketch(A, y, desc, SA), 2), 4)
+    lsq.tune("gauss_planes_wgs", DEFAULTS["gauss_planes_wgs"])
+    del A
+    torch.cuda.empty_cache()
+    return res
+
+
 def measure_gram(ctx, quick=False):
     """Factor time (ms) of an m = 40 d sketch per Gram workgroup target, per d bucket."""
     import torch
@@ -334,6 +357,7 @@ def tune(quick=False, path=None):
         batched = measure_batched(ctx, quick)
         srht = measure_srht(ctx, quick)
         gauss = measure_gauss(ctx, quick)
+        planes = measure_gauss_planes(ctx, quick)
         gram = measure_gram(ctx, quick)
     finally:
         ctx.close()
@@ -350,9 +374,10 @@ def tune(quick=False, path=None):
                                                               {int(k): v for k, v in rec["stream16"].items()})}
                           for b, rec in per.items()} for dt, per in srht.items()},
              "gauss_wgs": _argmin(gauss),
+             "gauss_planes_wgs": _argmin(planes),
              "gram_wgs": {b: _argmin(row) for b, row in gram.items()},
              "measured": {"fused_gbs": fused, "batched_solves_per_s": batched, "srht_ms": srht,
-                          "gauss_ms": gauss, "gram_ms": gram, "quick": quick}}
+                          "gauss_ms": gauss, "gauss_planes_ms": planes, "gram_ms": gram, "quick": quick}}
     path = path or table_path()
     tab = load_table(path)
     tab[arch_name()] = entry

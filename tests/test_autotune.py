@@ -38,12 +38,12 @@ def test_choose_all_knobs_and_fold_threshold():
                                       "stream_rows": 192}},
                       "f64": {"1024": {"srht_passa_wgs": 262144, "srht_passb_wgs": 4096, "fold8_rows": 80,
                                        "stream_rows": 128}}},
-             "gauss_wgs": 2048, "gram_wgs": {"256": 1024, "1024": 4096}}
+             "gauss_wgs": 2048, "gauss_planes_wgs": 512, "gram_wgs": {"256": 1024, "1024": 4096}}
     assert autotune.choose(entry, "f32", 1024) == {"fused_groups_per_cu": 2, "srht_passa_wgs": 65536,
                                                    "srht_passb_wgs": 4096, "srht_fold8_rows_f32": 96,
                                                    "srht_fold8_rows_f64": 80, "srht_stream_rows_f32": 160,
                                                    "srht_stream_rows_f64": 128, "gauss_wgs": 2048,
-                                                   "gram_wgs": 4096}
+                                                   "gauss_planes_wgs": 512, "gram_wgs": 4096}
     assert autotune.choose(entry, "f64", 1024)["srht_passa_wgs"] == 262144
     # d = 300 takes the 256 bucket; a bucket without SRHT entries takes the nearest measured one
     v = autotune.choose(entry, "f32", 300)
@@ -62,7 +62,8 @@ def test_bad_knob_values_rejected():
     with pytest.raises(lsq.LsqError):
         lsq.tune("no_such_knob", 1)
     for key, bad in (("srht_fold8_rows_f32", 0), ("srht_stream_rows_f64", 0), ("srht_passb_wgs", 100), ("gauss_wgs", 1 << 20),
-                     ("gram_wgs", 10), ("srht_passa_wgs", -1)):
+                     ("gram_wgs", 10), ("srht_passa_wgs", -1), ("gauss_planes_wgs", 4),
+                     ("gauss_planes_min_d", 0), ("gauss_chunk_rows", -1)):
         with pytest.raises(lsq.LsqError):
             lsq.tune(key, bad)
     for key, v in autotune.DEFAULTS.items():

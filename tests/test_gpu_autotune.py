@@ -24,12 +24,13 @@ def test_autotune_quick(tmp_path):
             for key in ("fold8_rows", "stream_rows"):
                 assert v[key] in autotune.FOLD_ROWS or v[key] == max(autotune.FOLD_ROWS) + 1
     assert entry["gauss_wgs"] in autotune.GAUSS_CANDIDATES
+    assert entry["gauss_planes_wgs"] in autotune.PLANES_CANDIDATES
     assert all(v in autotune.GRAM_CANDIDATES for v in entry["gram_wgs"].values())
     try:
         vals = autotune.apply("f32", 512, path=p)
         assert set(vals) == {"fused_groups_per_cu", "batched_slots", "batched_gang_unit", "srht_passa_wgs", "srht_passb_wgs",
                              "srht_fold8_rows_f32", "srht_fold8_rows_f64", "srht_stream_rows_f32",
-                             "srht_stream_rows_f64", "gauss_wgs", "gram_wgs"}
+                             "srht_stream_rows_f64", "gauss_wgs", "gauss_planes_wgs", "gram_wgs"}
     finally:
         for k, v in autotune.DEFAULTS.items():
             lsq.tune(k, v)
