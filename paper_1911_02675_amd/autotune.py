@@ -58,7 +58,7 @@ GRAM_CANDIDATES = (1024, 2048, 4096)
 # library defaults, restored after measuring
 DEFAULTS = {"fused_groups_per_cu": 8, "batched_slots": 0, "batched_gang_unit": 8 << 20, "srht_passa_wgs": 0, "srht_passb_wgs": 8192,
             "srht_fold8_rows_f32": 64, "srht_fold8_rows_f64": 128,
-            "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gauss_planes_wgs": 256,
+            "srht_stream_rows_f32": 192, "srht_stream_rows_f64": 192, "gauss_wgs": 1024, "gauss_planes_wgs": 512,
             "gram_wgs": 2048}
 
 

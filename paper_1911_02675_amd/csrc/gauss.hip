@@ -648,7 +648,7 @@ static int64_t gauss_nks(int64_t m, int64_t d, int64_t n) {
 }
 
 int g_gauss_planes_min_d = 384;
-int g_gauss_planes_wgs = 256;
+int g_gauss_planes_wgs = 512;
 int g_gauss_chunk_rows = 0;
 
 // The plan of the planes form: column groups, row tiles, k-splits per launch (about g_gauss_planes_wgs
