@@ -376,6 +376,11 @@ lsq_status lsq_copy_bandwidth(lsq_ctx* ctx, const void* src, void* dst, int64_t 
  * pass aims at, 0 = 2^17 for an FP32 transform and 2^15 for FP64, the default); "srht_passb_wgs"
  * (workgroups the LDS-staged second pass aims at when splitting its sums over j_hi, default 8192);
  * "gauss_wgs" (workgroups the Gaussian sketch aims at when splitting the rows of A, default 1024);
+ * "gauss_planes_min_d" (the BF16 Gaussian sketch forms the three BF16 terms of A once per chunk of rows
+ * and multiplies them in 64 x 512 tiles from this d on, default 384; 1..2^30); "gauss_planes_wgs"
+ * (workgroups that form aims at per launch, 8..65536, default 512); "gauss_chunk_rows" (rows of A per
+ * chunk of that form, 0 = terms of about 1 GiB, the default; rounded down to a multiple of 32; the
+ * terms of one chunk live in the context's workspace);
  * "gram_wgs" (workgroups the CholeskyQR Gram kernel aims at when splitting the rows of S A, default 2048).
  * INVALID_ARG for an unknown key or an out-of-range value. */
 lsq_status lsq_tune(const char* key, int64_t value);
