@@ -2,7 +2,8 @@
 // specification (Section 2: i.i.d. N(0, 1/m) entries).  S is never stored: every workgroup generates
 // its block of S in registers from Philox words and multiplies it with a tile of A on the matrix cores.
 // The reduction over the long dimension n is split across workgroups (partials), then summed in a fixed
-// order.
+// order.  The BF16 precision form at d >= 384 first writes the three BF16 terms of a chunk of rows of A
+// in the matrix cores' fragment order (k_gauss_split3), then multiplies them (k_gauss_bf16_planes).
 #include <type_traits>
 
 #include "internal.h"
