@@ -33,6 +33,10 @@ CASES = [(5000, 33, 100, "f32", None), (5000, 300, 300, "f64", None), (70000, 64
          (3000, 1, 17, "f32", None), (20001, 257, 129, "f32", None),
          (20001, 700, 130, "f32", None), (9000, 512, 64, "f64", None), (5000, 384, 300, "f32", None),
          (40000, 520, 70, "f32", 4096), (6000, 1000, 33, "f32", 2048)]
+# planes form edge cases (n >= d): a ragged last 32-row step with m below one row tile, a single row of
+# S, the largest d, and rows of A at a stride wider than d (FP32 and FP64)
+EDGE = [(401, 384, 3, "f32", 0), (600, 512, 1, "f32", 0), (1100, 1024, 130, "f32", 0), (3000, 400, 65, "f32", 5),
+        (2000, 600, 40, "f64", 3)]
 
 
 @pytest.mark.parametrize("n,d,m,dtype,chunk", CASES)
@@ -47,6 +51,12 @@ def test_gauss_bf16_sketch(ctx, n, d, m, dtype, chunk):
         lsq.tune("gauss_chunk_rows", 0)
 
 
+@pytest.mark.parametrize("n,d,m,dtype,pad", EDGE)
+def test_gauss_bf16_planes_edges(ctx, n, d, m, dtype, pad):
+    say("gauss bf16 planes edge", n, d, m, dtype, pad)
+    _check_bf16_sketch(ctx, n, d, m, dtype, pad)
+
+
 def test_gauss_bf16_both_forms(ctx):
     """At d >= 384 the tile form (forced by a high threshold) and the planes form both meet the bound."""
     from paper_1911_02675_amd import lsq
@@ -57,7 +67,7 @@ def test_gauss_bf16_both_forms(ctx):
         lsq.tune("gauss_planes_min_d", 384)
 
 
-def _check_bf16_sketch(ctx, n, d, m, dtype):
+def _check_bf16_sketch(ctx, n, d, m, dtype, pad=0):
     import torch
 
     from oracle.draws import gaussian_normals, round_bf16
@@ -67,7 +77,14 @@ def _check_bf16_sketch(ctx, n, d, m, dtype):
     A = rng.standard_normal((n, d)) * rng.uniform(0.5, 2.0, d)[None, :]
     if dtype == "f32":
         A = A.astype(np.float32).astype(np.float64)
-    Ad = torch.from_numpy(A.astype(np.float32) if dtype == "f32" else A).cuda()
+    Ah = A.astype(np.float32) if dtype == "f32" else A
+    if pad:
+        # rows at a stride of d + pad elements: a view of a wider matrix
+        W = np.zeros((n, d + pad), dtype=Ah.dtype)
+        W[:, :d] = Ah
+        Ad = torch.from_numpy(W).cuda()[:, :d]
+    else:
+        Ad = torch.from_numpy(Ah).cuda()
     y = torch.zeros(n, dtype=torch.float64, device="cuda")
     SA = torch.zeros((m, d), dtype=torch.float64, device="cuda")
     seed = 31 + n
